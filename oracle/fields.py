@@ -1,0 +1,159 @@
+"""Local effective-field terms, FP64 (Methods, "Physics and discretization").
+
+All fields are in A/m; ``m`` has shape (3, nz, ny, nx), or (R, 3, nz, ny, nx)
+for a batch of replicas sharing one geometry and material.
+
+* Exchange: six-point Laplacian, H = (2A / mu0 Ms) sum_a (m_{i+a} + m_{i-a} - 2 m_i) / D_a^2.
+* Interfacial DMI: energy density D [m_z div m - (m . grad) m_z] (Rohart-Thiaville
+  sign as in mumax3), field H = (2D / mu0 Ms)(d_x m_z, d_y m_z, -d_x m_x - d_y m_y)
+  with central differences (m_{i+1} - m_{i-1}) / (2 D_a).
+* Open edges use ghost cells from the free boundary condition
+  dm/dn = (D / 2A)(z x n) x m (Results "Exact agreement"; Methods): along x,
+  d_x m = (D/2A)(m_z, 0, -m_x); along y, d_y m = (D/2A)(0, m_z, -m_y); the
+  ghost is m_edge +/- D_a d_a m.  Along z, and everywhere when D = 0, the ghost
+  is m_edge (Neumann).  Exchange and DMI share the ghosts (reading).  An axis
+  with a single cell contributes no derivative (reading).
+* Uniaxial anisotropy H = (2 Ku / mu0 Ms)(m . u) u; Zeeman H = B / mu0.
+* Thermal (Brown) field H = sigma eta with
+  sigma = sqrt(2 alpha kB T / (mu0^2 Ms V gamma0 dt)) (Results, "A
+  replica-batched engine"), V the cell volume.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .constants import GAMMA0, KB, MU0
+from . import demag as _demag
+from . import philox as _philox
+
+# numpy axis (counted from the end) of each spatial axis; component axis is -4
+_NP_AXIS = {0: -1, 1: -2, 2: -3}
+
+
+def _comp(m, c):
+    return m[..., c, :, :, :]
+
+
+def _edge_derivative(mc, axis, D, A):
+    """Boundary-condition derivative d_axis m at an open edge (3, ...)."""
+    k = D / (2.0 * A) if A != 0 else 0.0
+    mx, my, mz = _comp(mc, 0), _comp(mc, 1), _comp(mc, 2)
+    zero = np.zeros_like(mx)
+    if axis == 0:
+        return k * np.stack([mz, zero, -mx], axis=-4)
+    if axis == 1:
+        return k * np.stack([zero, mz, -my], axis=-4)
+    return np.zeros_like(mc)
+
+
+def neighbours(m, grid, mat, axis):
+    """(m_minus, m_plus): values at i-1 and i+1 along ``axis`` with periodic
+    wrap or boundary-condition ghosts."""
+    ax = _NP_AXIS[axis]
+    n = grid.n[axis]
+    h = grid.cell[axis]
+    if grid.pbc[axis]:
+        return np.roll(m, 1, axis=ax), np.roll(m, -1, axis=ax)
+    mm = np.roll(m, 1, axis=ax)
+    mp = np.roll(m, -1, axis=ax)
+    first = [slice(None)] * m.ndim
+    last = [slice(None)] * m.ndim
+    first[m.ndim + ax] = slice(0, 1)
+    last[m.ndim + ax] = slice(n - 1, n)
+    first, last = tuple(first), tuple(last)
+    use_dmi = mat.D != 0.0 and axis in (0, 1)
+    m_first = m[first]
+    m_last = m[last]
+    if use_dmi:
+        mm[first] = m_first - h * _edge_derivative(m_first, axis, mat.D, mat.A)
+        mp[last] = m_last + h * _edge_derivative(m_last, axis, mat.D, mat.A)
+    else:
+        mm[first] = m_first
+        mp[last] = m_last
+    return mm, mp
+
+
+def exchange_field(m, grid, mat):
+    pref = 2.0 * mat.A / (MU0 * mat.Ms)
+    H = np.zeros_like(m)
+    for axis in range(3):
+        if grid.n[axis] == 1:
+            continue
+        mm, mp = neighbours(m, grid, mat, axis)
+        H += pref * (mm + mp - 2.0 * m) / grid.cell[axis] ** 2
+    return H
+
+
+def dmi_field(m, grid, mat):
+    H = np.zeros_like(m)
+    if mat.D == 0.0:
+        return H
+    pref = 2.0 * mat.D / (MU0 * mat.Ms)
+    for axis in (0, 1):
+        if grid.n[axis] == 1:
+            continue
+        mm, mp = neighbours(m, grid, mat, axis)
+        d = (mp - mm) / (2.0 * grid.cell[axis])
+        # d_x m_z -> H_x ; d_y m_z -> H_y ; -d_x m_x - d_y m_y -> H_z
+        H[..., axis, :, :, :] += pref * _comp(d, 2)
+        H[..., 2, :, :, :] -= pref * _comp(d, axis)
+    return H
+
+
+def anisotropy_field(m, mat):
+    if mat.Ku == 0.0:
+        return np.zeros_like(m)
+    u = np.asarray(mat.u, float)
+    u = u / np.linalg.norm(u)
+    mu = sum(u[c] * _comp(m, c) for c in range(3))
+    pref = 2.0 * mat.Ku / (MU0 * mat.Ms)
+    return pref * np.stack([u[c] * mu for c in range(3)], axis=-4)
+
+
+def zeeman_field(m, mat):
+    H = np.zeros_like(m)
+    for c in range(3):
+        H[..., c, :, :, :] = mat.B[c] / MU0
+    return H
+
+
+def thermal_sigma(grid, mat, dt):
+    if mat.T == 0.0 or mat.alpha == 0.0:
+        return 0.0
+    return math.sqrt(2.0 * mat.alpha * KB * mat.T /
+                     (MU0 ** 2 * mat.Ms * grid.volume * GAMMA0 * dt))
+
+
+def thermal_field(grid, mat, dt, seed, step):
+    """Brown field for one replica (scalar ``seed``) or a batch (array of
+    per-replica seeds -> (R, 3, nz, ny, nx))."""
+    nx, ny, nz = grid.n
+    seeds = np.atleast_1d(np.asarray(seed, dtype=np.uint64))
+    s = thermal_sigma(grid, mat, dt)
+    if s == 0.0:
+        out = np.zeros((seeds.size, 3, nz, ny, nx))
+    else:
+        out = s * _philox.gaussian_eta(seeds, grid.ncells, step).reshape(seeds.size, 3, nz, ny, nx)
+    return out if np.ndim(seed) else out[0]
+
+
+def terms(m, grid, mat):
+    """Dict of the deterministic field terms at state m."""
+    out = {"exchange": exchange_field(m, grid, mat),
+           "dmi": dmi_field(m, grid, mat),
+           "demag": (_demag.demag_field(m, grid, mat.Ms) if mat.demag
+                     else np.zeros_like(m)),
+           "anisotropy": anisotropy_field(m, mat),
+           "zeeman": zeeman_field(m, mat)}
+    return out
+
+
+def effective_field(m, grid, mat, H_thermal=None):
+    """H_eff = demag + exchange + DMI + anisotropy + Zeeman (+ thermal)."""
+    t = terms(m, grid, mat)
+    H = t["exchange"] + t["dmi"] + t["demag"] + t["anisotropy"] + t["zeeman"]
+    if H_thermal is not None:
+        H = H + H_thermal
+    return H

@@ -1,0 +1,60 @@
+"""Observables, FP64: energy per term and topological charge.
+
+The paper reports total energies (Results, SP#1-type showcase) and classifies
+skyrmions by topological charge (Results, skyrmion phase diagram) without
+printing their discretisation.  Readings:
+
+* Energy (J): E = V sum_i [ -(mu0 Ms / 2) m_i . (H_ex + H_dmi + H_demag + H_anis)_i
+  - mu0 Ms m_i . H_zeeman ]; the anisotropy part equals -Ku V sum (m . u)^2.
+  The thermal field is excluded.
+* Topological charge: Q = (1/4 pi) sum_i m_i . (d_x m x d_y m)_i dx dy with
+  central differences, periodic wrap on periodic axes, and the cell itself as the
+  missing neighbour at open edges; layer z = 0.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from .constants import MU0
+from . import fields as _fields
+
+ENERGY_TERMS = ("exchange", "dmi", "demag", "anisotropy", "zeeman")
+
+
+def energies(m, grid, mat):
+    t = _fields.terms(m, grid, mat)
+    V = grid.volume
+    out = {}
+    for name in ENERGY_TERMS:
+        dot = float(np.sum(m * t[name]))
+        if name == "zeeman":
+            out[name] = -MU0 * mat.Ms * V * dot
+        else:
+            out[name] = -0.5 * MU0 * mat.Ms * V * dot
+    out["total"] = sum(out[k] for k in ENERGY_TERMS)
+    return out
+
+
+def topological_charge(m, grid):
+    m0 = m[:, 0]  # (3, ny, nx), layer z = 0
+    def diff(axis_np, axis):
+        if grid.pbc[axis]:
+            mp = np.roll(m0, -1, axis=axis_np)
+            mm = np.roll(m0, 1, axis=axis_np)
+        else:
+            mp = np.roll(m0, -1, axis=axis_np)
+            mm = np.roll(m0, 1, axis=axis_np)
+            n = m0.shape[axis_np]
+            sl_last = [slice(None)] * 3
+            sl_first = [slice(None)] * 3
+            sl_last[axis_np] = n - 1
+            sl_first[axis_np] = 0
+            mp[tuple(sl_last)] = m0[tuple(sl_last)]
+            mm[tuple(sl_first)] = m0[tuple(sl_first)]
+        return (mp - mm) / (2.0 * grid.cell[axis])
+    dxm = diff(2, 0) if grid.n[0] > 1 else np.zeros_like(m0)
+    dym = diff(1, 1) if grid.n[1] > 1 else np.zeros_like(m0)
+    q = np.sum(m0 * np.cross(dxm, dym, axis=0))
+    return float(q * grid.cell[0] * grid.cell[1] / (4.0 * math.pi))

@@ -1,0 +1,51 @@
+"""Problem description for the oracle: a finite-difference grid and a uniform
+material (Methods, "Physics and discretization": structured grid, x-fastest
+indexing; per-cell materials reduce to one value per group for the workloads
+checked here)."""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+
+@dataclass(frozen=True)
+class Grid:
+    n: tuple                 # (nx, ny, nz) cells
+    cell: tuple              # (dx, dy, dz) metres
+    pbc: tuple = (0, 0, 0)   # 1 = periodic along that axis
+    images: tuple = (0, 0, 0)  # periodic image count P per axis (sum p = -P..P)
+
+    @property
+    def volume(self) -> float:
+        return self.cell[0] * self.cell[1] * self.cell[2]
+
+    @property
+    def ncells(self) -> int:
+        return self.n[0] * self.n[1] * self.n[2]
+
+    @property
+    def padded(self) -> tuple:
+        """FFT size per axis: 2N on open axes with N > 1, N on periodic axes,
+        1 when N = 1 (zero padding to 2N, Methods "Physics and discretization")."""
+        out = []
+        for a in range(3):
+            N = self.n[a]
+            if N == 1:
+                out.append(1)
+            elif self.pbc[a]:
+                out.append(N)
+            else:
+                out.append(2 * N)
+        return tuple(out)
+
+
+@dataclass(frozen=True)
+class Material:
+    Ms: float = 8.0e5        # A/m
+    A: float = 1.3e-11       # J/m
+    alpha: float = 0.5
+    Ku: float = 0.0          # J/m^3
+    u: tuple = (0.0, 0.0, 1.0)
+    D: float = 0.0           # J/m^2, interfacial
+    B: tuple = (0.0, 0.0, 0.0)  # applied field, tesla
+    T: float = 0.0           # kelvin
+    demag: bool = True
