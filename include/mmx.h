@@ -1,0 +1,185 @@
+/*
+ * mmx.h -- C ABI of libmmx, an MI355X (gfx950) implementation of the
+ * micromagnetic effective-field + Landau-Lifshitz-Gilbert time step of
+ * Claude-SpinDynamics (arxiv 2608.15253).
+ *
+ * Conventions (all entry points):
+ *  - Every call returns mmx_status (0 = MMX_OK, < 0 = error) and never throws.
+ *    The message of the last error on the calling thread is mmx_last_error().
+ *  - Argument and shape errors are detected before anything is launched.
+ *    HIP runtime failures map to MMX_EHIP (message from hipGetErrorString).
+ *  - Units are SI: metres, A/m, J/m, J/m^2, J/m^3, tesla, kelvin, seconds.
+ *  - Device arrays are owned by the caller (e.g. torch tensors), are not
+ *    freed or retained by the library, and must stay alive until the work
+ *    queued on the bound stream has finished.  The library owns its context
+ *    and the device buffers it allocates in mmx_create / mmx_build_demag
+ *    (plans, tensor spectrum, stage buffers); mmx_destroy frees them.
+ *  - Magnetisation layout ("D1", Results "A replica-batched engine" and the
+ *    replica-batching figure legend: replica-outermost, component-major,
+ *    x-fastest): group g, replica r, component c, cell (x, y, z) lives at
+ *        m[goff(g) + (r * 3 + c) * N_g + x + n_x * (y + n_y * z)]
+ *    with N_g = n_x n_y n_z and goff(g) the sum of 3 R_h N_h over groups h < g.
+ *    Element type is float for MMX_F32 contexts and double for MMX_F64.
+ *  - All device work is queued asynchronously on the stream given to
+ *    mmx_set_stream (default: the null stream).  Calls that return host data
+ *    (mmx_rk45 statistics, mmx_build_demag) synchronise that stream.
+ *  - One context per host thread at a time; calls on one context that overlap
+ *    from several threads race.
+ */
+#ifndef MMX_H
+#define MMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mmx_ctx mmx_ctx;
+
+typedef enum { MMX_F32 = 1, MMX_F64 = 2 } mmx_prec;
+
+typedef enum {
+  MMX_OK = 0,
+  MMX_EINVAL = -1,      /* bad argument value or null pointer                */
+  MMX_ESHAPE = -2,      /* grid / group layout not supported or inconsistent */
+  MMX_EHIP = -3,        /* HIP runtime error                                 */
+  MMX_ESTATE = -4,      /* call out of order (e.g. demag not built)          */
+  MMX_EUNSUP = -5,      /* valid but unsupported combination                 */
+  MMX_ENONFINITE = -6,  /* a non-finite value was produced on the device     */
+  MMX_EDTMIN = -8       /* adaptive step size fell below dt_min              */
+} mmx_status;
+
+/* Effective-field terms (Methods, "Physics and discretization"). */
+enum {
+  MMX_EXCH = 1,            /* six-point Laplacian exchange                     */
+  MMX_DMI_INTERFACIAL = 2, /* interfacial DMI; open edges of every term use the
+                              free-edge condition of the material's D          */
+  MMX_ANIS_UNIAXIAL = 4,   /* uniaxial anisotropy                              */
+  MMX_ZEEMAN = 8,          /* applied field                                    */
+  MMX_DEMAG = 16,          /* Newell-tensor FFT demagnetisation                */
+  MMX_THERMAL = 32,        /* Brown thermal field (Philox4x32-10 noise)        */
+  MMX_ALL_TERMS = 63
+};
+
+/* One geometry advanced for `replicas` independent replicas. */
+typedef struct {
+  int32_t n[3];          /* cells per axis (x, y, z), each >= 1              */
+  double cell[3];        /* cell size per axis, metres                       */
+  int32_t pbc[3];        /* 1 = periodic along that axis                     */
+  int32_t pbc_images[3]; /* periodic images summed into the demag kernel     */
+  int32_t replicas;      /* R >= 1                                           */
+} mmx_group;
+
+/* Uniform material of a group (per-cell values are not supported). */
+typedef struct {
+  double Ms;     /* saturation magnetisation, A/m (> 0)                     */
+  double A;      /* exchange stiffness, J/m                                 */
+  double alpha;  /* Gilbert damping                                         */
+  double Ku;     /* uniaxial anisotropy constant, J/m^3                     */
+  double u[3];   /* anisotropy axis (normalised by the library)             */
+  double D;      /* interfacial DMI constant, J/m^2                         */
+} mmx_material;
+
+typedef struct {
+  double t, dt, err;                    /* time, next step size, last error   */
+  int64_t accepted, rejected;           /* step counts                        */
+} mmx_rk_stats;
+
+/* Creates a context for `n_groups` geometries.  Checks that device 0 of the
+ * current HIP device set is gfx950 and that every axis length can be
+ * transformed (FFT sizes with factors 2, 3, 5 only; an even length on
+ * periodic x).  Allocates the per-group stage buffers.  *out receives the
+ * context; mmx_destroy releases it.  Errors: MMX_EINVAL, MMX_ESHAPE,
+ * MMX_EUNSUP, MMX_EHIP. */
+mmx_status mmx_create(const mmx_group* groups, int32_t n_groups, mmx_prec prec,
+                      mmx_ctx** out);
+void mmx_destroy(mmx_ctx* ctx);
+
+/* Binds the HIP stream (hipStream_t passed as void*) used by every later call. */
+mmx_status mmx_set_stream(mmx_ctx* ctx, void* hip_stream);
+
+/* Material of group g (Methods, "Physics and discretization"). */
+mmx_status mmx_set_material(mmx_ctx* ctx, int32_t group, const mmx_material* mat);
+
+/* Field-term mask (bitwise or of the MMX_* term flags) used by every
+ * evaluation; default MMX_EXCH|MMX_DMI_INTERFACIAL|MMX_ANIS_UNIAXIAL|
+ * MMX_ZEEMAN|MMX_DEMAG. */
+mmx_status mmx_set_terms(mmx_ctx* ctx, uint32_t mask);
+
+/* Applied flux density B (tesla, host array of 3) of group g; H = B / mu0. */
+mmx_status mmx_set_field(mmx_ctx* ctx, int32_t group, const double B_tesla[3]);
+
+/* Temperature (K) and 64-bit Philox key of every replica of group g (host
+ * arrays of length R_g).  Brown field sigma = sqrt(2 alpha kB T /
+ * (mu0^2 Ms V gamma0 dt)) (Results, "A replica-batched engine"); noise
+ * eta ~ N(0,1) from Philox4x32-10 (Salmon et al. 2011) with key = seed and
+ * counter = (cell, step low word, step high word, 0), Box-Muller on the four
+ * uniforms (x + 1/2) 2^-32, first three normals used as (x, y, z). */
+mmx_status mmx_set_thermal(mmx_ctx* ctx, int32_t group, const double* T_per_replica,
+                           const uint64_t* seed_per_replica);
+
+/* Builds the demag kernel of every group in FP64 on the device: Newell tensor
+ * (Newell, Williams & Dunlop 1993) per offset, closed form at scaled
+ * Chebyshev distance <= 2 and Gauss-Legendre dipole quadrature beyond,
+ * periodic images summed on periodic axes, zero at the padded Nyquist offset,
+ * FFT, scaled by -Ms / (Px Py Pz), reduced to the real, parity-compressed
+ * (Px/2+1)(Py/2+1)(Pz/2+1) block per component and rounded to the context
+ * precision.  Requires the material to be set.  Synchronous. */
+mmx_status mmx_build_demag(mmx_ctx* ctx);
+
+/* Effective field H (A/m, device, layout D1) at state m (device, D1) for
+ * all groups, with the enabled terms; the thermal term uses `step` and `dt`.
+ * Methods, "Physics and discretization". */
+mmx_status mmx_field(mmx_ctx* ctx, const void* m, void* H, uint64_t step, double dt);
+
+/* LLG right-hand side dm/dt (1/s, device, D1) at m (LLG equation, Methods):
+ * -gamma' mu0 [m x H + alpha m x (m x H)], gamma' = gamma0 / (1 + alpha^2). */
+mmx_status mmx_torque(mmx_ctx* ctx, const void* m, void* dmdt, uint64_t step, double dt);
+
+/* n_steps Stratonovich Heun steps of size dt, in place on m (device, D1),
+ * steps numbered step0 .. step0+n_steps-1 for the thermal noise, which is
+ * drawn once per step and shared by predictor and corrector (Methods,
+ * "Replica batching"; Results, finite-temperature comparison).  The corrector
+ * is normalised.  If t_switch (device double[R_total]) is not null, entries
+ * still negative receive (step+1)*dt at the first step after which the
+ * replica's mean m_z is negative. */
+mmx_status mmx_heun(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
+                    void* t_switch);
+
+/* Adaptive Dormand-Prince 5(4) relaxation (Methods, "Integrators") of m
+ * (device, D1, in place) from t0 to t_end with absolute tolerance tol on the
+ * max-over-cells Euclidean norm of the embedded error; first attempt dt0;
+ * dt <- dt clamp(0.9 (tol/err)^(1/5), 0.2, 5), limited to 1e-11 s and to the
+ * time left; the candidate is normalised before the first-same-as-last stage.
+ * Step control runs on the device.  If dt_replay (host, n_replay entries) is
+ * not null the given step sizes are taken in order without control.  If
+ * energy_trace (device double, trace_cap entries) is not null the total
+ * energy after each accepted step is appended (entry 0 = initial state).
+ * Thermal terms are rejected (MMX_EUNSUP).  stats (host) receives the final
+ * controller state.  Synchronous.  MMX_EDTMIN if dt falls below 1e-20 s. */
+mmx_status mmx_rk45(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, double dt0,
+                    const double* dt_replay, int64_t n_replay, void* energy_trace,
+                    int64_t trace_cap, mmx_rk_stats* stats);
+
+/* Accepted step sizes of the last mmx_rk45 call (host array, up to cap
+ * entries); *count receives the number available. */
+mmx_status mmx_rk45_dts(mmx_ctx* ctx, double* dts, int64_t cap, int64_t* count);
+
+/* Energy per term (J) of every replica: E (device double[R_total][6]) in the
+ * order exchange, DMI, demag, anisotropy, Zeeman, total;
+ * E = V sum_i [-(mu0 Ms / 2) m.(H_ex + H_dmi + H_d + H_anis) - mu0 Ms m.H_Z]. */
+mmx_status mmx_energy(mmx_ctx* ctx, const void* m, void* E);
+
+/* Topological charge of layer z = 0 of every replica, Q (device
+ * double[R_total]) = (1/4 pi) sum m.(d_x m x d_y m) dx dy with central
+ * differences (periodic wrap, the cell itself beyond open edges). */
+mmx_status mmx_topological_charge(mmx_ctx* ctx, const void* m, void* Q);
+
+const char* mmx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMX_H */

@@ -1,0 +1,204 @@
+"""Python binding of libmmx (argument marshalling only).
+
+Every function below calls the C entry point of the same name in
+``libmmx.so`` (declared in ``include/mmx.h``); all computation happens in the
+library's HIP kernels.  Device arrays are passed as raw pointers, typically
+``torch.Tensor.data_ptr()`` of CUDA (HIP) tensors; streams as the integer
+handle ``torch.cuda.current_stream().cuda_stream``.
+
+Importing this package loads the library and fails loudly if it is missing:
+there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+# torch is imported first so that libmmx's libamdhip64.so.7 dependency binds to
+# the HIP runtime torch already loaded (same SONAME): one runtime per process,
+# so device pointers and streams from torch are valid inside the library.
+import torch  # noqa: F401
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmmx.so")
+
+MMX_F32, MMX_F64 = 1, 2
+MMX_OK = 0
+STATUS = {0: "MMX_OK", -1: "MMX_EINVAL", -2: "MMX_ESHAPE", -3: "MMX_EHIP",
+          -4: "MMX_ESTATE", -5: "MMX_EUNSUP", -6: "MMX_ENONFINITE", -8: "MMX_EDTMIN"}
+MMX_EXCH, MMX_DMI_INTERFACIAL, MMX_ANIS_UNIAXIAL = 1, 2, 4
+MMX_ZEEMAN, MMX_DEMAG, MMX_THERMAL = 8, 16, 32
+MMX_ALL_TERMS = 63
+DEFAULT_TERMS = MMX_EXCH | MMX_DMI_INTERFACIAL | MMX_ANIS_UNIAXIAL | MMX_ZEEMAN | MMX_DEMAG
+
+
+class mmx_group(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32 * 3), ("cell", ctypes.c_double * 3),
+                ("pbc", ctypes.c_int32 * 3), ("pbc_images", ctypes.c_int32 * 3),
+                ("replicas", ctypes.c_int32)]
+
+
+class mmx_material(ctypes.Structure):
+    _fields_ = [("Ms", ctypes.c_double), ("A", ctypes.c_double), ("alpha", ctypes.c_double),
+                ("Ku", ctypes.c_double), ("u", ctypes.c_double * 3), ("D", ctypes.c_double)]
+
+
+class mmx_rk_stats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("err", ctypes.c_double),
+                ("accepted", ctypes.c_int64), ("rejected", ctypes.c_int64)]
+
+
+class MMXError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} -> {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                      "(hipcc --offload-arch=gfx950) first")
+_lib = ctypes.CDLL(LIB_PATH)
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "mmx_create": [ctypes.POINTER(mmx_group), ctypes.c_int32, ctypes.c_int, ctypes.POINTER(_P)],
+    "mmx_set_stream": [_P, _P],
+    "mmx_set_material": [_P, ctypes.c_int32, ctypes.POINTER(mmx_material)],
+    "mmx_set_terms": [_P, ctypes.c_uint32],
+    "mmx_set_field": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double)],
+    "mmx_set_thermal": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                        ctypes.POINTER(ctypes.c_uint64)],
+    "mmx_build_demag": [_P],
+    "mmx_field": [_P, _P, _P, ctypes.c_uint64, ctypes.c_double],
+    "mmx_torque": [_P, _P, _P, ctypes.c_uint64, ctypes.c_double],
+    "mmx_heun": [_P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P],
+    "mmx_rk45": [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                 ctypes.POINTER(ctypes.c_double), ctypes.c_int64, _P, ctypes.c_int64,
+                 ctypes.POINTER(mmx_rk_stats)],
+    "mmx_rk45_dts": [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
+                     ctypes.POINTER(ctypes.c_int64)],
+    "mmx_energy": [_P, _P, _P],
+    "mmx_topological_charge": [_P, _P, _P],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = ctypes.c_int
+_lib.mmx_destroy.argtypes = [_P]
+_lib.mmx_destroy.restype = None
+_lib.mmx_last_error.argtypes = []
+_lib.mmx_last_error.restype = ctypes.c_char_p
+
+EXPORTED = list(_SIGS) + ["mmx_destroy", "mmx_last_error"]
+
+
+def mmx_last_error() -> str:
+    return _lib.mmx_last_error().decode()
+
+
+def _check(fn, status):
+    if status != MMX_OK:
+        raise MMXError(fn, status, mmx_last_error())
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _dbl(seq):
+    arr = (ctypes.c_double * len(seq))(*[float(v) for v in seq])
+    return arr
+
+
+def make_group(n, cell, pbc=(0, 0, 0), images=(0, 0, 0), replicas=1) -> mmx_group:
+    g = mmx_group()
+    g.n[:] = [int(v) for v in n]
+    g.cell[:] = [float(v) for v in cell]
+    g.pbc[:] = [int(v) for v in pbc]
+    g.pbc_images[:] = [int(v) for v in images]
+    g.replicas = int(replicas)
+    return g
+
+
+def mmx_create(groups, prec) -> int:
+    arr = (mmx_group * len(groups))(*groups)
+    out = _P()
+    _check("mmx_create", _lib.mmx_create(arr, len(groups), int(prec), ctypes.byref(out)))
+    return out.value
+
+
+def mmx_destroy(ctx) -> None:
+    _lib.mmx_destroy(ctx)
+
+
+def mmx_set_stream(ctx, stream) -> None:
+    _check("mmx_set_stream", _lib.mmx_set_stream(ctx, stream))
+
+
+def mmx_set_material(ctx, group, Ms, A, alpha, Ku=0.0, u=(0.0, 0.0, 1.0), D=0.0) -> None:
+    m = mmx_material(Ms, A, alpha, Ku, (ctypes.c_double * 3)(*u), D)
+    _check("mmx_set_material", _lib.mmx_set_material(ctx, group, ctypes.byref(m)))
+
+
+def mmx_set_terms(ctx, mask) -> None:
+    _check("mmx_set_terms", _lib.mmx_set_terms(ctx, int(mask)))
+
+
+def mmx_set_field(ctx, group, B) -> None:
+    _check("mmx_set_field", _lib.mmx_set_field(ctx, group, _dbl(B)))
+
+
+def mmx_set_thermal(ctx, group, T_per_replica, seeds) -> None:
+    n = len(T_per_replica)
+    Ta = (ctypes.c_double * n)(*[float(v) for v in T_per_replica])
+    Sa = (ctypes.c_uint64 * n)(*[int(v) for v in seeds])
+    _check("mmx_set_thermal", _lib.mmx_set_thermal(ctx, group, Ta, Sa))
+
+
+def mmx_build_demag(ctx) -> None:
+    _check("mmx_build_demag", _lib.mmx_build_demag(ctx))
+
+
+def mmx_field(ctx, m, H, step=0, dt=0.0) -> None:
+    _check("mmx_field", _lib.mmx_field(ctx, _ptr(m), _ptr(H), int(step), float(dt)))
+
+
+def mmx_torque(ctx, m, dmdt, step=0, dt=0.0) -> None:
+    _check("mmx_torque", _lib.mmx_torque(ctx, _ptr(m), _ptr(dmdt), int(step), float(dt)))
+
+
+def mmx_heun(ctx, m, dt, n_steps, step0=0, t_switch=None) -> None:
+    _check("mmx_heun", _lib.mmx_heun(ctx, _ptr(m), float(dt), int(n_steps), int(step0),
+                                     _ptr(t_switch)))
+
+
+def mmx_rk45(ctx, m, t0, t_end, tol, dt0=1e-14, dt_replay=None, energy_trace=None,
+             trace_cap=0) -> mmx_rk_stats:
+    st = mmx_rk_stats()
+    rp = _dbl(dt_replay) if dt_replay is not None else None
+    nrp = len(dt_replay) if dt_replay is not None else 0
+    _check("mmx_rk45", _lib.mmx_rk45(ctx, _ptr(m), float(t0), float(t_end), float(tol),
+                                     float(dt0), rp, nrp, _ptr(energy_trace), int(trace_cap),
+                                     ctypes.byref(st)))
+    return st
+
+
+def mmx_rk45_dts(ctx, cap=None):
+    count = ctypes.c_int64()
+    _check("mmx_rk45_dts", _lib.mmx_rk45_dts(ctx, None, 0, ctypes.byref(count)))
+    n = count.value if cap is None else min(cap, count.value)
+    buf = (ctypes.c_double * max(n, 1))()
+    _check("mmx_rk45_dts", _lib.mmx_rk45_dts(ctx, buf, n, ctypes.byref(count)))
+    return [buf[i] for i in range(n)]
+
+
+def mmx_energy(ctx, m, E) -> None:
+    _check("mmx_energy", _lib.mmx_energy(ctx, _ptr(m), _ptr(E)))
+
+
+def mmx_topological_charge(ctx, m, Q) -> None:
+    _check("mmx_topological_charge", _lib.mmx_topological_charge(ctx, _ptr(m), _ptr(Q)))

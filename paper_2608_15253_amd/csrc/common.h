@@ -1,0 +1,44 @@
+// Shared definitions of libmmx (host and device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mmx {
+
+// Physical constants (the paper uses gamma0, mu0 and kB without values; the
+// mumax3 gyromagnetic ratio, SI mu0 = 4 pi 1e-7 and the exact SI kB are used).
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kGamma0 = 1.7595e11;
+constexpr double kMu0 = 4.0e-7 * kPi;
+constexpr double kKB = 1.380649e-23;
+
+constexpr int kMaxPass = 16;
+
+template <typename T>
+struct cpx {
+  T re, im;
+};
+
+template <typename T>
+__host__ __device__ inline cpx<T> cmul(cpx<T> a, cpx<T> b) {
+  return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <typename T>
+__host__ __device__ inline cpx<T> cmulc(cpx<T> a, cpx<T> b) {  // a * conj(b)
+  return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+template <typename T>
+__host__ __device__ inline cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__host__ __device__ inline cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+
+// Stockham plan of one transform length: radices applied in order; `prune`
+// marks a first radix-2 pass whose upper half input is known to be zero.
+struct FftPlan {
+  int n;
+  int npass;
+  int prune;
+  int radix[kMaxPass];
+};
+
+}  // namespace mmx

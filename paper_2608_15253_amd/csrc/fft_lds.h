@@ -1,0 +1,169 @@
+// Workgroup-cooperative Stockham FFT staged in LDS (device code).
+//
+// A workgroup transforms `nlines` independent lines of length n held
+// contiguously in LDS ([line][n], complex).  Each pass of radix R reads the R
+// inputs of a butterfly at stride n/R, applies the Stockham twiddles
+// exp(-+2 pi i r (j mod Ns) / (Ns R)), transforms them with a small DFT and
+// writes them to the autosorted position (j / Ns) Ns R + (j mod Ns) + r Ns of
+// the other buffer; Ns grows by R per pass, so mixed radices 2, 3, 4, 5 and 8
+// combine in any order and the output is in natural order.  A pruned first
+// pass (radix 2, input zero beyond n/2, as in the zero-padded demag
+// convolution) reduces to duplicating its input.  Transforms are unnormalised.
+#pragma once
+#include "common.h"
+
+namespace mmx {
+
+template <typename T, bool INV>
+struct Dft {
+  static __device__ inline void r2(cpx<T>* v) {
+    cpx<T> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+  // multiply by -i (forward) or +i (inverse)
+  static __device__ inline cpx<T> rot(cpx<T> a) {
+    return INV ? cpx<T>{-a.im, a.re} : cpx<T>{a.im, -a.re};
+  }
+  static __device__ inline void r4(cpx<T>* v) {
+    cpx<T> s02 = cadd(v[0], v[2]), d02 = csub(v[0], v[2]);
+    cpx<T> s13 = cadd(v[1], v[3]), d13 = rot(csub(v[1], v[3]));
+    v[0] = cadd(s02, s13);
+    v[2] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3] = csub(d02, d13);
+  }
+  static __device__ inline void r3(cpx<T>* v) {
+    const T c = T(-0.5);
+    const T s = INV ? T(0.86602540378443864676) : T(-0.86602540378443864676);
+    cpx<T> a = v[0], b = v[1], d = v[2];
+    cpx<T> t = cadd(b, d);
+    cpx<T> u = csub(b, d);
+    cpx<T> m = {a.re + c * t.re, a.im + c * t.im};
+    // s * i * u
+    cpx<T> su = {-s * u.im, s * u.re};
+    v[0] = cadd(a, t);
+    v[1] = cadd(m, su);
+    v[2] = csub(m, su);
+  }
+  static __device__ inline void r5(cpx<T>* v) {
+    const T c1 = T(0.30901699437494742410);   // cos(2pi/5)
+    const T c2 = T(-0.80901699437494742410);  // cos(4pi/5)
+    const T s1 = INV ? T(0.95105651629515357212) : T(-0.95105651629515357212);
+    const T s2 = INV ? T(0.58778525229247312917) : T(-0.58778525229247312917);
+    cpx<T> a = v[0];
+    cpx<T> t1 = cadd(v[1], v[4]), u1 = csub(v[1], v[4]);
+    cpx<T> t2 = cadd(v[2], v[3]), u2 = csub(v[2], v[3]);
+    cpx<T> m1 = {a.re + c1 * t1.re + c2 * t2.re, a.im + c1 * t1.im + c2 * t2.im};
+    cpx<T> m2 = {a.re + c2 * t1.re + c1 * t2.re, a.im + c2 * t1.im + c1 * t2.im};
+    // i*(s1 u1 + s2 u2) and i*(s2 u1 - s1 u2)
+    cpx<T> n1 = {-(s1 * u1.im + s2 * u2.im), s1 * u1.re + s2 * u2.re};
+    cpx<T> n2 = {-(s2 * u1.im - s1 * u2.im), s2 * u1.re - s1 * u2.re};
+    v[0] = cadd(a, cadd(t1, t2));
+    v[1] = cadd(m1, n1);
+    v[4] = csub(m1, n1);
+    v[2] = cadd(m2, n2);
+    v[3] = csub(m2, n2);
+  }
+  static __device__ inline void r8(cpx<T>* v) {
+    const T h = T(0.70710678118654752440);
+    // radix-2 first stage: pairs (k, k+4)
+    cpx<T> a[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = cadd(v[k], v[k + 4]);
+      a[k + 4] = csub(v[k], v[k + 4]);
+    }
+    // twiddles w8^k on the odd half (w8 = exp(-+ i pi / 4))
+    {
+      cpx<T> x = a[5];
+      a[5] = INV ? cpx<T>{h * (x.re - x.im), h * (x.re + x.im)}
+                 : cpx<T>{h * (x.re + x.im), h * (x.im - x.re)};
+      a[6] = rot(a[6]);
+      x = a[7];
+      a[7] = INV ? cpx<T>{-h * (x.re + x.im), h * (x.re - x.im)}
+                 : cpx<T>{h * (x.im - x.re), -h * (x.re + x.im)};
+    }
+    cpx<T> e[4] = {a[0], a[1], a[2], a[3]};
+    cpx<T> o[4] = {a[4], a[5], a[6], a[7]};
+    r4(e);
+    r4(o);
+    v[0] = e[0]; v[2] = e[1]; v[4] = e[2]; v[6] = e[3];
+    v[1] = o[0]; v[3] = o[1]; v[5] = o[2]; v[7] = o[3];
+  }
+};
+
+template <typename T, bool INV, int R>
+__device__ inline void stockham_pass(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
+                                     int n, int Ns, int nlines, const cpx<T>* __restrict__ tw,
+                                     int tid, int nthr) {
+  const int nb = n / R;
+  const int total = nb * nlines;
+  const int twscale = n / (Ns * R);
+  for (int t = tid; t < total; t += nthr) {
+    const int line = t / nb;
+    const int j = t - line * nb;
+    const cpx<T>* s = src + line * n;
+    cpx<T>* d = dst + line * n;
+    const int jm = j % Ns;
+    cpx<T> v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = s[j + r * nb];
+    if (jm != 0) {
+#pragma unroll
+      for (int r = 1; r < R; ++r) {
+        const cpx<T> w = tw[r * jm * twscale];
+        v[r] = INV ? cmulc(v[r], w) : cmul(v[r], w);
+      }
+    }
+    if constexpr (R == 2) Dft<T, INV>::r2(v);
+    if constexpr (R == 3) Dft<T, INV>::r3(v);
+    if constexpr (R == 4) Dft<T, INV>::r4(v);
+    if constexpr (R == 5) Dft<T, INV>::r5(v);
+    if constexpr (R == 8) Dft<T, INV>::r8(v);
+    const int idxD = (j / Ns) * Ns * R + jm;
+#pragma unroll
+    for (int r = 0; r < R; ++r) d[idxD + r * Ns] = v[r];
+  }
+}
+
+// Transforms nlines lines in `a` (scratch `b`), returns the buffer holding the
+// result.  `tw` is the table exp(-2 pi i k / n), k < n.  Must be called by the
+// whole workgroup; ends with a barrier.
+template <typename T, bool INV>
+__device__ cpx<T>* lds_fft(cpx<T>* a, cpx<T>* b, int nlines, const FftPlan& p,
+                           const cpx<T>* __restrict__ tw) {
+  const int n = p.n;
+  const int tid = threadIdx.x, nthr = blockDim.x;
+  int Ns = 1;
+  for (int ps = 0; ps < p.npass; ++ps) {
+    const int R = p.radix[ps];
+    if (ps == 0 && p.prune) {
+      const int half = n / 2;
+      const int total = half * nlines;
+      for (int t = tid; t < total; t += nthr) {
+        const int line = t / half;
+        const int j = t - line * half;
+        const cpx<T> v = a[line * n + j];
+        b[line * n + 2 * j] = v;
+        b[line * n + 2 * j + 1] = v;
+      }
+    } else {
+      switch (R) {
+        case 2: stockham_pass<T, INV, 2>(a, b, n, Ns, nlines, tw, tid, nthr); break;
+        case 3: stockham_pass<T, INV, 3>(a, b, n, Ns, nlines, tw, tid, nthr); break;
+        case 4: stockham_pass<T, INV, 4>(a, b, n, Ns, nlines, tw, tid, nthr); break;
+        case 5: stockham_pass<T, INV, 5>(a, b, n, Ns, nlines, tw, tid, nthr); break;
+        default: stockham_pass<T, INV, 8>(a, b, n, Ns, nlines, tw, tid, nthr); break;
+      }
+    }
+    __syncthreads();
+    cpx<T>* t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+}  // namespace mmx

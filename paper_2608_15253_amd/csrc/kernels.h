@@ -1,0 +1,525 @@
+// Hot-path kernels of the effective-field + LLG step (device code).
+//
+// One field evaluation of a replica group is three launches (2-D films) or
+// five (3-D blocks), all over every replica of the group at once:
+//   k_xfwd   stage combine (RK45: m + dt sum a_sj k_j; optional
+//            normalisation) fused with the real-to-complex x transform of the
+//            zero-padded magnetisation (two real cells packed per complex
+//            value, half-length Stockham FFT in LDS, even/odd split);
+//   k_yconv  (2-D) y transform (pruned: rows >= ny are zero), product with the
+//            parity-compressed real symmetric tensor spectrum, inverse y
+//            transform, rows >= ny dropped;
+//   k_yfwd / k_zconv / k_yinv  (3-D) the same split over y and z;
+//   k_fields complex-to-real inverse x transform (outputs x < nx only) fused
+//            with exchange, interfacial DMI, uniaxial anisotropy, Zeeman and
+//            Brown thermal fields, the LLG torque and the integrator epilogue
+//            (Heun predictor/corrector, RK45 stage store, embedded error
+//            with a workgroup max reduction, energy partial sums).
+// Spectrum layout: S[((r*3 + c)*nz + z)*Sy + y][kx], Sy = ny (2-D) or Py (3-D),
+// kx < Kx = Px/2 + 1.
+#pragma once
+#include "common.h"
+#include "fft_lds.h"
+#include "philox.h"
+
+namespace mmx {
+
+enum : unsigned {
+  T_EXCH = 1, T_DMI = 2, T_ANIS = 4, T_ZEEMAN = 8, T_DEMAG = 16, T_THERMAL = 32
+};
+
+enum FieldMode { FM_FIELD = 0, FM_TORQUE, FM_HEUN1, FM_HEUN2, FM_RKK, FM_RK7, FM_ENERGY };
+
+constexpr int kBlock = 256;
+
+// Device controller state of the adaptive integrator (FP64 time and error).
+struct RkState {
+  double t, dt, t_end, tol, dt_max, dt_min;
+  unsigned long long err_bits;  // max error of the current attempt (bit pattern)
+  double last_err;
+  long long accepted, rejected, n_replay, replay_idx;
+  int done, accepted_flag, final_flag, nonfinite, dtmin_hit, pad;
+};
+
+// ---------------------------------------------------------------------------
+// x forward transform with stage combine
+// ---------------------------------------------------------------------------
+template <typename T>
+struct XArgs {
+  const T* m;
+  const T* kk[6];
+  T coef[6];
+  int ncoef;
+  const double* dtdev;
+  double dth;
+  T* mout;
+  int normalise;
+  int do_fft;
+  cpx<T>* S;
+  const cpx<T>* tw;
+  const cpx<T>* wpost;
+  FftPlan plan;
+  int nx, ny, nz, N, Sy, Kx, hx, L, xone;
+  const int* done;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
+  if (a.done && *a.done) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int hx = a.hx, L = a.L, nl = 3 * L;
+  cpx<T>* Bf = A + nl * hx;
+  const int r = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * L;
+  const size_t rb = (size_t)r * 3 * a.N;
+  const T dt = a.dtdev ? (T)(*a.dtdev) : (T)a.dth;
+  const int npair = a.xone ? 1 : (a.nx + 1) / 2;
+  for (int t = threadIdx.x; t < L * hx; t += blockDim.x) {
+    const int l = t / hx, k = t - l * hx, y = y0 + l;
+    cpx<T> v[3] = {{0, 0}, {0, 0}, {0, 0}};
+    if (y < a.ny && k < npair) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int x = 2 * k + h;
+        if (x >= a.nx) break;
+        const size_t cell = (size_t)x + (size_t)a.nx * (y + (size_t)a.ny * z);
+        T mv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T s = a.m[rb + (size_t)c * a.N + cell];
+          for (int j = 0; j < a.ncoef; ++j)
+            s += dt * a.coef[j] * a.kk[j][rb + (size_t)c * a.N + cell];
+          mv[c] = s;
+        }
+        if (a.normalise) {
+          const T inv = T(1) / sqrt(mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2]);
+          mv[0] *= inv; mv[1] *= inv; mv[2] *= inv;
+        }
+        if (a.mout) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) a.mout[rb + (size_t)c * a.N + cell] = mv[c];
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          if (h == 0) v[c].re = mv[c]; else v[c].im = mv[c];
+        }
+      }
+    }
+    if (a.do_fft) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) A[(c * L + l) * hx + k] = v[c];
+    }
+  }
+  if (!a.do_fft) return;
+  __syncthreads();
+  const cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.plan, a.tw);
+  const int Kx = a.Kx;
+  for (int t = threadIdx.x; t < nl * Kx; t += blockDim.x) {
+    const int line = t / Kx, kx = t - line * Kx;
+    const int c = line / L, l = line - c * L, y = y0 + l;
+    if (y >= a.ny) continue;
+    cpx<T> out;
+    if (a.xone) {
+      out = {X[line].re, T(0)};
+    } else {
+      const cpx<T> Zk = X[line * hx + (kx == hx ? 0 : kx)];
+      cpx<T> Zc = X[line * hx + (kx == 0 ? 0 : hx - kx)];
+      Zc.im = -Zc.im;
+      const cpx<T> E = {T(0.5) * (Zk.re + Zc.re), T(0.5) * (Zk.im + Zc.im)};
+      const cpx<T> O = {T(0.5) * (Zk.re - Zc.re), T(0.5) * (Zk.im - Zc.im)};
+      const cpx<T> w = a.wpost[kx];
+      out = {E.re + (w.re * O.im + w.im * O.re), E.im - (w.re * O.re - w.im * O.im)};
+    }
+    a.S[((((size_t)r * 3 + c) * a.nz + z) * a.Sy + y) * Kx + kx] = out;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// spectral tensor product helpers
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline void tensor_apply(const T* __restrict__ Nt, size_t cstride, size_t idx, T sxy,
+                                    T sxz, T syz, bool full, cpx<T>& X, cpx<T>& Y, cpx<T>& Z) {
+  const T nxx = Nt[idx], nyy = Nt[cstride + idx], nzz = Nt[2 * cstride + idx];
+  const T nxy = sxy * Nt[3 * cstride + idx];
+  cpx<T> hx = {nxx * X.re + nxy * Y.re, nxx * X.im + nxy * Y.im};
+  cpx<T> hy = {nxy * X.re + nyy * Y.re, nxy * X.im + nyy * Y.im};
+  cpx<T> hz = {nzz * Z.re, nzz * Z.im};
+  if (full) {
+    const T nxz = sxz * Nt[4 * cstride + idx], nyz = syz * Nt[5 * cstride + idx];
+    hx.re += nxz * Z.re; hx.im += nxz * Z.im;
+    hy.re += nyz * Z.re; hy.im += nyz * Z.im;
+    hz.re += nxz * X.re + nyz * Y.re;
+    hz.im += nxz * X.im + nyz * Y.im;
+  }
+  X = hx; Y = hy; Z = hz;
+}
+
+// ---------------------------------------------------------------------------
+// 2-D: y transform + tensor product + inverse y transform
+// ---------------------------------------------------------------------------
+template <typename T>
+struct YArgs {
+  cpx<T>* S;
+  const T* Nt;
+  const cpx<T>* tw;
+  FftPlan pf, pi;
+  int ny, Py, Kx, W, Ty, Sy, nz, Pz, Tz, z;
+  const int* done;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
+  if (a.done && *a.done) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int W = a.W, Py = a.Py, nl = 3 * W;
+  cpx<T>* Bf = A + nl * Py;
+  const int r = blockIdx.z, kx0 = blockIdx.x * W;
+  const size_t rbase = (size_t)r * 3;
+  for (int t = threadIdx.x; t < nl * Py; t += blockDim.x) {
+    const int w = t % W, rest = t / W, y = rest % Py, c = rest / Py;
+    cpx<T> v = {0, 0};
+    if (y < a.ny && kx0 + w < a.Kx)
+      v = a.S[(((rbase + c) * a.nz) * a.Sy + y) * a.Kx + kx0 + w];
+    A[(c * W + w) * Py + y] = v;
+  }
+  __syncthreads();
+  cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, a.tw);
+  cpx<T>* scratch = (X == A) ? Bf : A;
+  const size_t cs = (size_t)a.Tz * a.Ty * a.Kx;
+  for (int t = threadIdx.x; t < W * Py; t += blockDim.x) {
+    const int w = t % W, ky = t / W, kx = kx0 + w;
+    if (kx >= a.Kx) continue;
+    const bool lo = 2 * ky <= Py;
+    const int ty = lo ? ky : Py - ky;
+    const T sy = lo ? T(1) : T(-1);
+    cpx<T>& Mx = X[(0 * W + w) * Py + ky];
+    cpx<T>& My = X[(1 * W + w) * Py + ky];
+    cpx<T>& Mz = X[(2 * W + w) * Py + ky];
+    tensor_apply(a.Nt, cs, (size_t)ty * a.Kx + kx, sy, T(1), sy, false, Mx, My, Mz);
+  }
+  __syncthreads();
+  const cpx<T>* Y = lds_fft<T, true>(X, scratch, nl, a.pi, a.tw);
+  for (int t = threadIdx.x; t < nl * a.ny; t += blockDim.x) {
+    const int w = t % W, rest = t / W, y = rest % a.ny, c = rest / a.ny;
+    if (kx0 + w < a.Kx)
+      a.S[(((rbase + c) * a.nz) * a.Sy + y) * a.Kx + kx0 + w] = Y[(c * W + w) * Py + y];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 3-D: y transforms (forward pruned / inverse cropped) on z < nz planes
+// ---------------------------------------------------------------------------
+template <typename T, bool INV>
+__global__ void __launch_bounds__(kBlock) k_ypass(YArgs<T> a) {
+  if (a.done && *a.done) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int W = a.W, Py = a.Py, nl = 3 * W;
+  cpx<T>* Bf = A + nl * Py;
+  const int r = blockIdx.z, z = blockIdx.y, kx0 = blockIdx.x * W;
+  const size_t rbase = (size_t)r * 3;
+  const int nin = INV ? Py : a.ny;
+  for (int t = threadIdx.x; t < nl * Py; t += blockDim.x) {
+    const int w = t % W, rest = t / W, y = rest % Py, c = rest / Py;
+    cpx<T> v = {0, 0};
+    if (y < nin && kx0 + w < a.Kx)
+      v = a.S[(((rbase + c) * a.nz + z) * a.Sy + y) * a.Kx + kx0 + w];
+    A[(c * W + w) * Py + y] = v;
+  }
+  __syncthreads();
+  const cpx<T>* Y = lds_fft<T, INV>(A, Bf, nl, INV ? a.pi : a.pf, a.tw);
+  const int nout = INV ? a.ny : Py;
+  for (int t = threadIdx.x; t < nl * nout; t += blockDim.x) {
+    const int w = t % W, rest = t / W, y = rest % nout, c = rest / nout;
+    if (kx0 + w < a.Kx)
+      a.S[(((rbase + c) * a.nz + z) * a.Sy + y) * a.Kx + kx0 + w] = Y[(c * W + w) * Py + y];
+  }
+}
+
+// 3-D: z transform + full tensor product + inverse z transform, per ky.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
+  if (a.done && *a.done) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int W = a.W, Pz = a.Pz, nl = 3 * W;
+  cpx<T>* Bf = A + nl * Pz;
+  const int r = blockIdx.z, ky = blockIdx.y, kx0 = blockIdx.x * W;
+  const size_t rbase = (size_t)r * 3;
+  for (int t = threadIdx.x; t < nl * Pz; t += blockDim.x) {
+    const int w = t % W, rest = t / W, z = rest % Pz, c = rest / Pz;
+    cpx<T> v = {0, 0};
+    if (z < a.nz && kx0 + w < a.Kx)
+      v = a.S[(((rbase + c) * a.nz + z) * a.Sy + ky) * a.Kx + kx0 + w];
+    A[(c * W + w) * Pz + z] = v;
+  }
+  __syncthreads();
+  cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, a.tw);
+  cpx<T>* scratch = (X == A) ? Bf : A;
+  const size_t cs = (size_t)a.Tz * a.Ty * a.Kx;
+  const bool ylo = 2 * ky <= a.Py;
+  const int ty = ylo ? ky : a.Py - ky;
+  const T sy = ylo ? T(1) : T(-1);
+  for (int t = threadIdx.x; t < W * Pz; t += blockDim.x) {
+    const int w = t % W, kz = t / W, kx = kx0 + w;
+    if (kx >= a.Kx) continue;
+    const bool zlo = 2 * kz <= Pz;
+    const int tz = zlo ? kz : Pz - kz;
+    const T sz = zlo ? T(1) : T(-1);
+    cpx<T>& Mx = X[(0 * W + w) * Pz + kz];
+    cpx<T>& My = X[(1 * W + w) * Pz + kz];
+    cpx<T>& Mz = X[(2 * W + w) * Pz + kz];
+    tensor_apply(a.Nt, cs, ((size_t)tz * a.Ty + ty) * a.Kx + kx, sy, sz, sy * sz, true, Mx, My,
+                 Mz);
+  }
+  __syncthreads();
+  const cpx<T>* Y = lds_fft<T, true>(X, scratch, nl, a.pi, a.tw);
+  for (int t = threadIdx.x; t < nl * a.nz; t += blockDim.x) {
+    const int w = t % W, rest = t / W, z = rest % a.nz, c = rest / a.nz;
+    if (kx0 + w < a.Kx)
+      a.S[(((rbase + c) * a.nz + z) * a.Sy + ky) * a.Kx + kx0 + w] = Y[(c * W + w) * Pz + z];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// inverse x transform + local fields + torque + integrator epilogue
+// ---------------------------------------------------------------------------
+template <typename T>
+struct FArgs {
+  int nx, ny, nz, N, Sy, Kx, hx, L, xone;
+  int pbc[3];
+  int nax[3];
+  T idd2[3];  // 1/d^2 (exchange)
+  T ih2[3];   // 1/(2d) (DMI)
+  T hd[3];    // cell size (ghosts)
+  T cex, cdmi, kbc, can, u[3], hz[3], gpm, alpha;
+  unsigned terms;
+  const double* Trep;
+  const uint64_t* seeds;
+  double sig2pref;  // 2 alpha kB / (mu0^2 Ms V gamma0); sigma^2 = sig2pref T / dt
+  uint64_t step;
+  double dt_th;
+  const T* m;
+  const cpx<T>* S;
+  FftPlan plan;
+  const cpx<T>* tw;
+  const cpx<T>* wpost;
+  T* out;
+  T* k1;
+  const T* m0;
+  T* mout;
+  const T* kk[6];
+  double e[7];
+  const double* dtdev;
+  double dth;
+  RkState* st;
+  double* partial;
+  const int* done;
+};
+
+template <typename T>
+__device__ inline void ld3(const T* __restrict__ m, size_t rb, int N, size_t cell, T v[3]) {
+  v[0] = m[rb + cell];
+  v[1] = m[rb + N + cell];
+  v[2] = m[rb + 2 * (size_t)N + cell];
+}
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
+  if (MODE != FM_ENERGY && a.done && *a.done) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int hx = a.hx, L = a.L, nl = 3 * L;
+  cpx<T>* Bf = A + nl * hx;
+  __shared__ double red[kBlock * 5];
+  const int r = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * L;
+  const size_t rb = (size_t)r * 3 * a.N;
+  const bool demag = (a.terms & T_DEMAG) != 0;
+  const T* Hd = nullptr;  // real view of the inverse transform, line stride 2 hx
+  if (demag) {
+    const int Kx = a.Kx;
+    for (int t = threadIdx.x; t < nl * hx; t += blockDim.x) {
+      const int line = t / hx, k = t - line * hx;
+      const int c = line / L, l = line - c * L, y = y0 + l;
+      cpx<T> Z = {0, 0};
+      if (y < a.ny) {
+        const cpx<T>* row = a.S + ((((size_t)r * 3 + c) * a.nz + z) * a.Sy + y) * Kx;
+        if (a.xone) {
+          Z = {row[0].re, T(0)};
+        } else {
+          const cpx<T> Xk = row[k];
+          cpx<T> Xc = row[hx - k];
+          Xc.im = -Xc.im;
+          const cpx<T> E = cadd(Xk, Xc);
+          const cpx<T> D = csub(Xk, Xc);
+          const cpx<T> w = a.wpost[k];
+          const cpx<T> O = cmulc(D, w);  // D * conj(W^k)
+          Z = {E.re - O.im, E.im + O.re};
+        }
+      }
+      A[line * hx + k] = Z;
+    }
+    __syncthreads();
+    Hd = reinterpret_cast<const T*>(lds_fft<T, true>(A, Bf, nl, a.plan, a.tw));
+  }
+  const int ncell_blk = L * a.nx;
+  const double dt_state = a.dtdev ? *a.dtdev : a.dth;
+  const T dt = (T)dt_state;
+  T sigma = 0;
+  if ((a.terms & T_THERMAL) && a.Trep) {
+    const double Tr = a.Trep[r];
+    if (Tr > 0) sigma = (T)sqrt(a.sig2pref * Tr / a.dt_th);
+  }
+  const T kbc = a.kbc;  // free-edge condition of the material's D (0 when D = 0)
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int t = threadIdx.x; t < ncell_blk; t += blockDim.x) {
+    const int l = t / a.nx, x = t - l * a.nx, y = y0 + l;
+    if (y >= a.ny) continue;
+    const size_t cell = (size_t)x + (size_t)a.nx * (y + (size_t)a.ny * z);
+    T mc[3];
+    ld3(a.m, rb, a.N, cell, mc);
+    T Hex[3] = {0, 0, 0}, Hdm[3] = {0, 0, 0};
+    const int coord[3] = {x, y, z};
+    const size_t stride[3] = {1, (size_t)a.nx, (size_t)a.nx * a.ny};
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      if (a.nax[ax] == 1) continue;
+      const int n = a.nax[ax];
+      T mm[3], mp[3];
+      // edge-condition derivative (D/2A)(z x n) x m, applied on x and y only
+      T ev[3] = {0, 0, 0};
+      if (ax == 0) { ev[0] = mc[2]; ev[2] = -mc[0]; }
+      if (ax == 1) { ev[1] = mc[2]; ev[2] = -mc[1]; }
+      const T g = (ax < 2) ? a.hd[ax] * kbc : T(0);
+      if (coord[ax] > 0) ld3(a.m, rb, a.N, cell - stride[ax], mm);
+      else if (a.pbc[ax]) ld3(a.m, rb, a.N, cell + (size_t)(n - 1) * stride[ax], mm);
+      else { for (int c = 0; c < 3; ++c) mm[c] = mc[c] - g * ev[c]; }
+      if (coord[ax] < n - 1) ld3(a.m, rb, a.N, cell + stride[ax], mp);
+      else if (a.pbc[ax]) ld3(a.m, rb, a.N, cell - (size_t)(n - 1) * stride[ax], mp);
+      else { for (int c = 0; c < 3; ++c) mp[c] = mc[c] + g * ev[c]; }
+      if (a.terms & T_EXCH) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Hex[c] += a.cex * a.idd2[ax] * (mm[c] + mp[c] - T(2) * mc[c]);
+      }
+      if ((a.terms & T_DMI) && ax < 2) {
+        const T d_ax = (mp[ax] - mm[ax]) * a.ih2[ax];
+        const T d_z = (mp[2] - mm[2]) * a.ih2[ax];
+        Hdm[ax] += a.cdmi * d_z;
+        Hdm[2] -= a.cdmi * d_ax;
+      }
+    }
+    T Han[3] = {0, 0, 0};
+    if (a.terms & T_ANIS) {
+      const T mu = mc[0] * a.u[0] + mc[1] * a.u[1] + mc[2] * a.u[2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Han[c] = a.can * mu * a.u[c];
+    }
+    T Hz[3] = {0, 0, 0};
+    if (a.terms & T_ZEEMAN) { Hz[0] = a.hz[0]; Hz[1] = a.hz[1]; Hz[2] = a.hz[2]; }
+    T Hdd[3] = {0, 0, 0};
+    if (demag) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Hdd[c] = Hd[(c * L + l) * 2 * hx + x];
+    }
+    if (MODE == FM_ENERGY) {
+      acc[0] += (double)(mc[0] * Hex[0] + mc[1] * Hex[1] + mc[2] * Hex[2]);
+      acc[1] += (double)(mc[0] * Hdm[0] + mc[1] * Hdm[1] + mc[2] * Hdm[2]);
+      acc[2] += (double)(mc[0] * Hdd[0] + mc[1] * Hdd[1] + mc[2] * Hdd[2]);
+      acc[3] += (double)(mc[0] * Han[0] + mc[1] * Han[1] + mc[2] * Han[2]);
+      acc[4] += (double)(mc[0] * Hz[0] + mc[1] * Hz[1] + mc[2] * Hz[2]);
+      continue;
+    }
+    T H[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + Hdd[c];
+    if (sigma != T(0)) {
+      T eta[3];
+      thermal_eta<T>(a.seeds[r], (uint32_t)cell, a.step, eta);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) H[c] += sigma * eta[c];
+    }
+    if (MODE == FM_FIELD) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.out[rb + (size_t)c * a.N + cell] = H[c];
+      continue;
+    }
+    // LLG torque
+    const T cx = mc[1] * H[2] - mc[2] * H[1];
+    const T cy = mc[2] * H[0] - mc[0] * H[2];
+    const T cz = mc[0] * H[1] - mc[1] * H[0];
+    const T dx = mc[1] * cz - mc[2] * cy;
+    const T dy = mc[2] * cx - mc[0] * cz;
+    const T dz = mc[0] * cy - mc[1] * cx;
+    T k[3] = {-a.gpm * (cx + a.alpha * dx), -a.gpm * (cy + a.alpha * dy),
+              -a.gpm * (cz + a.alpha * dz)};
+    if (MODE == FM_TORQUE || MODE == FM_RKK) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.out[rb + (size_t)c * a.N + cell] = k[c];
+    } else if (MODE == FM_HEUN1) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a.k1[rb + (size_t)c * a.N + cell] = k[c];
+        a.mout[rb + (size_t)c * a.N + cell] = mc[c] + dt * k[c];
+      }
+    } else if (MODE == FM_HEUN2) {
+      T mo[3], k1v[3];
+      ld3(a.m0, rb, a.N, cell, mo);
+      ld3(a.k1, rb, a.N, cell, k1v);
+      T mn[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) mn[c] = mo[c] + T(0.5) * dt * (k1v[c] + k[c]);
+      const T inv = T(1) / sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.mout[rb + (size_t)c * a.N + cell] = mn[c] * inv;
+      acc[0] += (double)(mn[2] * inv);
+    } else if (MODE == FM_RK7) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.out[rb + (size_t)c * a.N + cell] = k[c];
+      double d2 = 0;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double s = a.e[6] * (double)k[c];
+        for (int j = 0; j < 6; ++j)
+          if (a.e[j] != 0.0) s += a.e[j] * (double)a.kk[j][rb + (size_t)c * a.N + cell];
+        s *= dt_state;
+        d2 += s * s;
+      }
+      const double en = sqrt(d2);
+      acc[0] = (en != en) ? __builtin_inf() : fmax(acc[0], en);
+    }
+  }
+  // workgroup reductions
+  if (MODE == FM_HEUN2 || MODE == FM_ENERGY || MODE == FM_RK7) {
+    const int nv = (MODE == FM_ENERGY) ? 5 : 1;
+    for (int v = 0; v < nv; ++v) red[v * kBlock + threadIdx.x] = acc[v];
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+      if ((int)threadIdx.x < s) {
+        for (int v = 0; v < nv; ++v) {
+          const double o = red[v * kBlock + threadIdx.x + s];
+          double& me = red[v * kBlock + threadIdx.x];
+          me = (MODE == FM_RK7) ? fmax(me, o) : me + o;
+        }
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+      const size_t nblk = (size_t)gridDim.x * gridDim.y;
+      if (MODE == FM_RK7) {
+        const double e = red[0];
+        if (!(e <= 1.7976931348623157e308)) {
+          a.st->nonfinite = 1;
+        } else {
+          atomicMax(&a.st->err_bits, (unsigned long long)__double_as_longlong(e));
+        }
+      } else {
+        for (int v = 0; v < nv; ++v) a.partial[((size_t)r * nblk + blk) * nv + v] = red[v * kBlock];
+      }
+    }
+  }
+}
+
+}  // namespace mmx

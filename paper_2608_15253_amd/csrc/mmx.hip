@@ -1,0 +1,897 @@
+// libmmx: host runtime and C ABI (see include/mmx.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/mmx.h"
+#include "common.h"
+#include "kernels.h"
+#include "setup_kernels.h"
+
+using namespace mmx;
+
+namespace {
+
+thread_local std::string g_err;
+
+mmx_status fail(mmx_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      return fail(MMX_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));        \
+  } while (0)
+
+#define MMX_TRY(expr)                 \
+  do {                                \
+    mmx_status s_ = (expr);           \
+    if (s_ != MMX_OK) return s_;      \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// FFT planning
+// ---------------------------------------------------------------------------
+bool make_plan(int n, bool prune, FftPlan& p) {
+  std::memset(&p, 0, sizeof(p));
+  p.n = n;
+  if (n <= 1) return n == 1;
+  int rest = n;
+  if (prune) {
+    if (n % 2) return false;
+    p.radix[p.npass++] = 2;
+    p.prune = 1;
+    rest /= 2;
+  }
+  while (rest % 4 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 4; rest /= 4; }
+  while (rest % 2 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 2; rest /= 2; }
+  while (rest % 3 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 3; rest /= 3; }
+  while (rest % 5 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 5; rest /= 5; }
+  return rest == 1;
+}
+
+bool fft_ok(int n) {
+  FftPlan p;
+  return make_plan(n, false, p);
+}
+
+// Gauss-Legendre nodes/weights by Newton iteration on the Legendre recurrence.
+void gauss_legendre(int n, double* x, double* w) {
+  for (int i = 0; i < n; ++i) {
+    double z = std::cos(kPi * (i + 0.75) / (n + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      // p1 = P_n(z), p0 = P_{n-1}(z)
+      const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    double p0 = 1.0, p1 = z;
+    for (int k = 2; k <= n; ++k) {
+      const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+      p0 = p1;
+      p1 = p2;
+    }
+    const double dp = n * (z * p1 - p0) / (z * z - 1.0);
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+template <typename T>
+std::vector<cpx<T>> twiddles(int n, int len) {
+  std::vector<cpx<T>> t(len);
+  for (int k = 0; k < len; ++k) {
+    const double a = -2.0 * kPi * (double)k / (double)n;
+    t[k] = {(T)std::cos(a), (T)std::sin(a)};
+  }
+  return t;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  hipError_t alloc(size_t b) {
+    if (p) { (void)hipFree(p); p = nullptr; }
+    bytes = b;
+    if (b == 0) return hipSuccess;
+    return hipMalloc(&p, b);
+  }
+  template <typename U> U* as() const { return reinterpret_cast<U*>(p); }
+};
+
+struct Group {
+  mmx_group g{};
+  int nx = 1, ny = 1, nz = 1, N = 1, R = 1;
+  int Px = 1, Py = 1, Pz = 1, Kx = 1, hx = 1, Ty = 1, Tz = 1, Sy = 1;
+  int xone = 0, is3d = 0;
+  int L = 1, Wy = 1, Wz = 1;
+  FftPlan plan_x{}, plan_xi{}, plan_yf{}, plan_yi{}, plan_zf{}, plan_zi{};
+  mmx_material mat{};
+  int mat_set = 0;
+  double B[3] = {0, 0, 0};
+  size_t off = 0;  // element offset of this group in caller arrays
+  // device buffers
+  DevBuf tw_x, wpost, tw_y, tw_z, Nt, S, ms, m7, k[7], Trep, seeds, partial, E;
+  int nblk = 1;  // k_fields workgroups per replica
+  int demag_built = 0;
+};
+
+}  // namespace
+
+struct mmx_ctx {
+  int prec = MMX_F32;
+  std::vector<std::unique_ptr<Group>> groups;
+  uint32_t terms = MMX_EXCH | MMX_DMI_INTERFACIAL | MMX_ANIS_UNIAXIAL | MMX_ZEEMAN | MMX_DEMAG;
+  hipStream_t stream = nullptr;
+  size_t total_elems = 0;
+  DevBuf st;       // RkState
+  DevBuf dts;      // accepted step sizes
+  DevBuf replay;   // dt replay list
+  long long dts_cap = 0;
+  long long last_accepted = 0;
+  DevBuf Etmp;     // per-replica energies for traces
+};
+
+namespace {
+
+size_t esize(const mmx_ctx* c) { return c->prec == MMX_F64 ? 8 : 4; }
+
+template <typename T>
+size_t cpxb() { return sizeof(cpx<T>); }
+
+mmx_status check_group(const mmx_group& g) {
+  for (int a = 0; a < 3; ++a) {
+    if (g.n[a] < 1) return fail(MMX_ESHAPE, "group: n must be >= 1");
+    if (!(g.cell[a] > 0)) return fail(MMX_EINVAL, "group: cell sizes must be > 0");
+    if (g.pbc[a] && g.pbc_images[a] < 0) return fail(MMX_EINVAL, "group: negative image count");
+  }
+  if (g.replicas < 1) return fail(MMX_ESHAPE, "group: replicas must be >= 1");
+  if ((long long)g.n[0] * g.n[1] * g.n[2] > (1LL << 31))
+    return fail(MMX_ESHAPE, "group: too many cells");
+  return MMX_OK;
+}
+
+template <typename T>
+mmx_status setup_group(mmx_ctx* ctx, Group& G) {
+  const mmx_group& g = G.g;
+  G.nx = g.n[0]; G.ny = g.n[1]; G.nz = g.n[2];
+  G.N = G.nx * G.ny * G.nz;
+  G.R = g.replicas;
+  auto padded = [&](int a) { return g.n[a] == 1 ? 1 : (g.pbc[a] ? g.n[a] : 2 * g.n[a]); };
+  G.Px = padded(0); G.Py = padded(1); G.Pz = padded(2);
+  G.xone = (G.nx == 1);
+  if (!G.xone && (G.Px % 2)) return fail(MMX_EUNSUP, "periodic x needs an even cell count");
+  G.hx = G.xone ? 1 : G.Px / 2;
+  G.Kx = G.xone ? 1 : G.hx + 1;
+  G.Ty = G.Py / 2 + 1;
+  G.Tz = G.Pz / 2 + 1;
+  G.is3d = G.nz > 1;
+  G.Sy = G.is3d ? G.Py : G.ny;
+  // x: half-length complex transform; input zero beyond ceil(nx/2) -> pruned when nx even & open
+  const bool px_prune = !G.xone && !g.pbc[0] && (G.nx % 2 == 0) && G.hx >= 2;
+  if (!make_plan(G.hx, px_prune, G.plan_x) || !make_plan(G.hx, false, G.plan_xi))
+    return fail(MMX_EUNSUP, "x length not 2^a 3^b 5^c");
+  const bool py_prune = G.ny > 1 && !g.pbc[1];
+  if (!make_plan(G.Py, py_prune, G.plan_yf) || !make_plan(G.Py, false, G.plan_yi))
+    return fail(MMX_EUNSUP, "y length not 2^a 3^b 5^c");
+  const bool pz_prune = G.nz > 1 && !g.pbc[2];
+  if (!make_plan(G.Pz, pz_prune, G.plan_zf) || !make_plan(G.Pz, false, G.plan_zi))
+    return fail(MMX_EUNSUP, "z length not 2^a 3^b 5^c");
+  G.L = std::max(1, std::min(G.ny, kBlock / std::max(1, G.nx)));
+  const size_t budget = 48 * 1024;
+  G.Wy = (int)std::max<size_t>(1, std::min<size_t>(16, budget / (6 * (size_t)G.Py * cpxb<T>())));
+  G.Wy = std::min(G.Wy, G.Kx);
+  G.Wz = (int)std::max<size_t>(1, std::min<size_t>(16, budget / (6 * (size_t)G.Pz * cpxb<T>())));
+  G.Wz = std::min(G.Wz, G.Kx);
+  G.nblk = ((G.ny + G.L - 1) / G.L) * G.nz;
+  // twiddles
+  auto up = [&](DevBuf& b, const void* src, size_t bytes) -> mmx_status {
+    HIP_TRY(b.alloc(bytes));
+    HIP_TRY(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
+    return MMX_OK;
+  };
+  {
+    auto t = twiddles<T>(G.hx, G.hx);
+    MMX_TRY(up(G.tw_x, t.data(), t.size() * cpxb<T>()));
+    auto w = twiddles<T>(G.xone ? 1 : G.Px, G.hx + 1);
+    MMX_TRY(up(G.wpost, w.data(), w.size() * cpxb<T>()));
+    auto ty = twiddles<T>(G.Py, G.Py);
+    MMX_TRY(up(G.tw_y, ty.data(), ty.size() * cpxb<T>()));
+    auto tz = twiddles<T>(G.Pz, G.Pz);
+    MMX_TRY(up(G.tw_z, tz.data(), tz.size() * cpxb<T>()));
+  }
+  const size_t st = (size_t)G.R * 3 * G.N * sizeof(T);
+  HIP_TRY(G.ms.alloc(st));
+  HIP_TRY(G.k[0].alloc(st));
+  HIP_TRY(G.S.alloc((size_t)G.R * 3 * G.nz * G.Sy * G.Kx * cpxb<T>()));
+  HIP_TRY(G.partial.alloc((size_t)G.R * G.nblk * 5 * sizeof(double)));
+  HIP_TRY(G.E.alloc((size_t)G.R * 6 * sizeof(double)));
+  std::vector<double> T0(G.R, 0.0);
+  std::vector<uint64_t> s0(G.R, 0);
+  MMX_TRY(up(G.Trep, T0.data(), G.R * sizeof(double)));
+  MMX_TRY(up(G.seeds, s0.data(), G.R * sizeof(uint64_t)));
+  return MMX_OK;
+}
+
+template <typename T>
+mmx_status ensure_rk_buffers(Group& G) {
+  const size_t st = (size_t)G.R * 3 * G.N * sizeof(T);
+  if (!G.m7.p) HIP_TRY(G.m7.alloc(st));
+  for (int j = 1; j < 7; ++j)
+    if (!G.k[j].p) HIP_TRY(G.k[j].alloc(st));
+  return MMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// demag kernel build
+// ---------------------------------------------------------------------------
+template <typename T>
+mmx_status build_demag_group(mmx_ctx* ctx, Group& G) {
+  GaussRules rules{};
+  const int ns[5] = {3, 4, 6, 8, 10};
+  for (int i = 0; i < 5; ++i) gauss_legendre(ns[i], rules.x[i], rules.w[i]);
+  AxisMap ax{G.nx, G.Px, G.g.pbc[0], G.g.pbc_images[0]};
+  AxisMap ay{G.ny, G.Py, G.g.pbc[1], G.g.pbc_images[1]};
+  AxisMap az{G.nz, G.Pz, G.g.pbc[2], G.g.pbc_images[2]};
+  const long total = (long)G.Px * G.Py * G.Pz;
+  DevBuf K;
+  HIP_TRY(K.alloc((size_t)6 * total * sizeof(cpx<double>)));
+  hipStream_t s = ctx->stream;
+  k_newell_kernel<<<(unsigned)((total + 127) / 128), 128, 0, s>>>(
+      K.as<cpx<double>>(), ax, ay, az, G.g.cell[0], G.g.cell[1], G.g.cell[2], rules);
+  HIP_TRY(hipGetLastError());
+  // FFT along x, y, z in FP64
+  auto line_fft = [&](int n, long os, long is, long stride, unsigned ni, unsigned no) -> mmx_status {
+    if (n == 1) return MMX_OK;
+    FftPlan p;
+    make_plan(n, false, p);
+    auto tw = twiddles<double>(n, n);
+    DevBuf tb;
+    HIP_TRY(tb.alloc(n * sizeof(cpx<double>)));
+    HIP_TRY(hipMemcpy(tb.p, tw.data(), n * sizeof(cpx<double>), hipMemcpyHostToDevice));
+    for (unsigned o0 = 0; o0 < no; o0 += 65535u) {
+      const unsigned nob = std::min(65535u, no - o0);
+      dim3 grid(ni, nob);
+      k_line_fft<<<grid, 128, 2 * n * sizeof(cpx<double>), s>>>(
+          K.as<cpx<double>>() + (long)o0 * os, os, is, stride, p, tb.as<cpx<double>>());
+      HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(s));
+    return MMX_OK;
+  };
+  const long Px = G.Px, Py = G.Py, Pz = G.Pz;
+  MMX_TRY(line_fft(G.Px, Px, 0, 1, 1u, (unsigned)(6 * Pz * Py)));                 // rows
+  MMX_TRY(line_fft(G.Py, Py * Px, 1, Px, (unsigned)Px, (unsigned)(6 * Pz)));     // columns
+  MMX_TRY(line_fft(G.Pz, Pz * Py * Px, 1, Py * Px, (unsigned)(Py * Px), 6u));    // pillars
+  const double scale = -G.mat.Ms / ((double)G.Px * G.Py * G.Pz);
+  HIP_TRY(G.Nt.alloc((size_t)6 * G.Tz * G.Ty * G.Kx * sizeof(T)));
+  const long tot = (long)6 * G.Tz * G.Ty * G.Kx;
+  k_compress<T><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(G.Nt.as<T>(), K.as<cpx<double>>(), G.Px,
+                                                             G.Py, G.Pz, G.Kx, G.Ty, G.Tz, scale);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s));
+  G.demag_built = 1;
+  return MMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// one field evaluation of a group
+// ---------------------------------------------------------------------------
+struct Combine {
+  int ncoef = 0;
+  double coef[6] = {0, 0, 0, 0, 0, 0};
+  int kidx[6] = {0, 0, 0, 0, 0, 0};  // which k buffer (0..5)
+  int normalise = 0;
+  void* mout = nullptr;
+};
+
+struct Epilogue {
+  int mode = FM_FIELD;
+  void* out = nullptr;
+  void* k1 = nullptr;
+  const void* m0 = nullptr;
+  void* mout = nullptr;
+  double e[7] = {0, 0, 0, 0, 0, 0, 0};
+  int use_k_err = 0;
+};
+
+template <typename T>
+FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
+  FArgs<T> a{};
+  a.nx = G.nx; a.ny = G.ny; a.nz = G.nz; a.N = G.N; a.Sy = G.Sy; a.Kx = G.Kx; a.hx = G.hx;
+  a.L = G.L; a.xone = G.xone;
+  const double mu0Ms = kMu0 * G.mat.Ms;
+  for (int ax = 0; ax < 3; ++ax) {
+    a.pbc[ax] = G.g.pbc[ax];
+    a.nax[ax] = G.g.n[ax];
+    const double d = G.g.cell[ax];
+    a.idd2[ax] = (T)(1.0 / (d * d));
+    a.ih2[ax] = (T)(1.0 / (2.0 * d));
+    a.hd[ax] = (T)d;
+  }
+  a.cex = (T)(2.0 * G.mat.A / mu0Ms);
+  a.cdmi = (T)(2.0 * G.mat.D / mu0Ms);
+  a.kbc = (T)(G.mat.A != 0 ? G.mat.D / (2.0 * G.mat.A) : 0.0);
+  a.can = (T)(2.0 * G.mat.Ku / mu0Ms);
+  double un = std::sqrt(G.mat.u[0] * G.mat.u[0] + G.mat.u[1] * G.mat.u[1] + G.mat.u[2] * G.mat.u[2]);
+  if (un == 0) un = 1;
+  for (int c = 0; c < 3; ++c) {
+    a.u[c] = (T)(G.mat.u[c] / un);
+    a.hz[c] = (T)(G.B[c] / kMu0);
+  }
+  a.gpm = (T)(kGamma0 / (1.0 + G.mat.alpha * G.mat.alpha) * kMu0);
+  a.alpha = (T)G.mat.alpha;
+  unsigned t = terms;
+  if (G.mat.Ku == 0) t &= ~T_ANIS;
+  if (G.mat.D == 0) t &= ~T_DMI;
+  a.terms = t;
+  const double V = G.g.cell[0] * G.g.cell[1] * G.g.cell[2];
+  a.Trep = G.Trep.as<double>();
+  a.seeds = G.seeds.as<uint64_t>();
+  a.sig2pref = 2.0 * G.mat.alpha * kKB / (kMu0 * kMu0 * G.mat.Ms * V * kGamma0);
+  a.S = G.S.as<cpx<T>>();
+  a.plan = G.plan_xi;  // inverse transform: full input
+  a.tw = G.tw_x.as<cpx<T>>();
+  a.wpost = G.wpost.as<cpx<T>>();
+  return a;
+}
+
+template <typename T>
+mmx_status launch_fields(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
+  dim3 grid((G.ny + G.L - 1) / G.L, G.nz, G.R);
+  const size_t lds = (a.terms & T_DEMAG) ? 2 * (size_t)3 * G.L * G.hx * cpxb<T>() : 0;
+  hipStream_t s = ctx->stream;
+  switch (mode) {
+    case FM_FIELD: k_fields<T, FM_FIELD><<<grid, kBlock, lds, s>>>(a); break;
+    case FM_TORQUE: k_fields<T, FM_TORQUE><<<grid, kBlock, lds, s>>>(a); break;
+    case FM_HEUN1: k_fields<T, FM_HEUN1><<<grid, kBlock, lds, s>>>(a); break;
+    case FM_HEUN2: k_fields<T, FM_HEUN2><<<grid, kBlock, lds, s>>>(a); break;
+    case FM_RKK: k_fields<T, FM_RKK><<<grid, kBlock, lds, s>>>(a); break;
+    case FM_RK7: k_fields<T, FM_RK7><<<grid, kBlock, lds, s>>>(a); break;
+    default: k_fields<T, FM_ENERGY><<<grid, kBlock, lds, s>>>(a); break;
+  }
+  HIP_TRY(hipGetLastError());
+  return MMX_OK;
+}
+
+// m: group-local base pointer of the state used for fields.
+template <typename T>
+mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb, const Epilogue& ep,
+                      uint64_t step, double dt_th, const double* dtdev, double dth,
+                      const int* done, uint32_t terms_override = 0xFFFFFFFFu) {
+  uint32_t terms = (terms_override == 0xFFFFFFFFu) ? ctx->terms : terms_override;
+  const bool demag = (terms & MMX_DEMAG) != 0;
+  if (demag && !G.demag_built) return fail(MMX_ESTATE, "mmx_build_demag has not been called");
+  hipStream_t s = ctx->stream;
+  const T* mfield = mbase;
+  // stage 1: combine (+ x forward transform)
+  if (demag || cb.mout) {
+    XArgs<T> x{};
+    x.m = mbase;
+    x.ncoef = cb.ncoef;
+    for (int j = 0; j < cb.ncoef; ++j) {
+      x.kk[j] = G.k[cb.kidx[j]].as<T>();
+      x.coef[j] = (T)cb.coef[j];
+    }
+    x.dtdev = dtdev;
+    x.dth = dth;
+    x.mout = reinterpret_cast<T*>(cb.mout);
+    x.normalise = cb.normalise;
+    x.do_fft = demag ? 1 : 0;
+    x.S = G.S.as<cpx<T>>();
+    x.tw = G.tw_x.as<cpx<T>>();
+    x.wpost = G.wpost.as<cpx<T>>();
+    x.plan = G.plan_x;
+    x.nx = G.nx; x.ny = G.ny; x.nz = G.nz; x.N = G.N; x.Sy = G.Sy; x.Kx = G.Kx; x.hx = G.hx;
+    x.L = G.L; x.xone = G.xone;
+    x.done = done;
+    dim3 grid((G.ny + G.L - 1) / G.L, G.nz, G.R);
+    const size_t lds = demag ? 2 * (size_t)3 * G.L * G.hx * cpxb<T>() : 0;
+    k_xfwd<T><<<grid, kBlock, lds, s>>>(x);
+    HIP_TRY(hipGetLastError());
+    if (cb.mout) mfield = reinterpret_cast<const T*>(cb.mout);
+  }
+  // stage 2: y (and z) passes with the tensor product
+  if (demag) {
+    YArgs<T> y{};
+    y.S = G.S.as<cpx<T>>();
+    y.Nt = G.Nt.as<T>();
+    y.ny = G.ny; y.Py = G.Py; y.Kx = G.Kx; y.Ty = G.Ty; y.Sy = G.Sy; y.nz = G.nz; y.Pz = G.Pz;
+    y.Tz = G.Tz;
+    y.done = done;
+    if (!G.is3d) {
+      y.W = G.Wy;
+      y.tw = G.tw_y.as<cpx<T>>();
+      y.pf = G.plan_yf;
+      y.pi = G.plan_yi;
+      dim3 grid((G.Kx + G.Wy - 1) / G.Wy, 1, G.R);
+      k_yconv<T><<<grid, kBlock, 2 * (size_t)3 * G.Wy * G.Py * cpxb<T>(), s>>>(y);
+      HIP_TRY(hipGetLastError());
+    } else {
+      y.W = G.Wy;
+      y.tw = G.tw_y.as<cpx<T>>();
+      y.pf = G.plan_yf;
+      y.pi = G.plan_yi;
+      dim3 gy((G.Kx + G.Wy - 1) / G.Wy, G.nz, G.R);
+      const size_t ldy = 2 * (size_t)3 * G.Wy * G.Py * cpxb<T>();
+      k_ypass<T, false><<<gy, kBlock, ldy, s>>>(y);
+      HIP_TRY(hipGetLastError());
+      YArgs<T> zz = y;
+      zz.W = G.Wz;
+      zz.tw = G.tw_z.as<cpx<T>>();
+      zz.pf = G.plan_zf;
+      zz.pi = G.plan_zi;
+      dim3 gz((G.Kx + G.Wz - 1) / G.Wz, G.Py, G.R);
+      k_zconv<T><<<gz, kBlock, 2 * (size_t)3 * G.Wz * G.Pz * cpxb<T>(), s>>>(zz);
+      HIP_TRY(hipGetLastError());
+      k_ypass<T, true><<<gy, kBlock, ldy, s>>>(y);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  // stage 3: inverse x transform + local fields + epilogue
+  FArgs<T> a = field_args<T>(ctx, G, terms);
+  a.m = mfield;
+  a.step = step;
+  a.dt_th = dt_th;
+  a.dtdev = dtdev;
+  a.dth = dth;
+  a.done = done;
+  a.out = reinterpret_cast<T*>(ep.out);
+  a.k1 = reinterpret_cast<T*>(ep.k1);
+  a.m0 = reinterpret_cast<const T*>(ep.m0);
+  a.mout = reinterpret_cast<T*>(ep.mout);
+  for (int j = 0; j < 7; ++j) a.e[j] = ep.e[j];
+  for (int j = 0; j < 6; ++j) a.kk[j] = G.k[j].as<T>();
+  a.st = ctx->st.as<RkState>();
+  a.partial = G.partial.as<double>();
+  return launch_fields<T>(ctx, G, a, ep.mode);
+}
+
+// ---------------------------------------------------------------------------
+// Dormand-Prince 5(4) coefficients (Dormand & Prince 1980)
+// ---------------------------------------------------------------------------
+const double DP_A[7][6] = {
+    {0, 0, 0, 0, 0, 0},
+    {1.0 / 5, 0, 0, 0, 0, 0},
+    {3.0 / 40, 9.0 / 40, 0, 0, 0, 0},
+    {44.0 / 45, -56.0 / 15, 32.0 / 9, 0, 0, 0},
+    {19372.0 / 6561, -25360.0 / 2187, 64448.0 / 6561, -212.0 / 729, 0, 0},
+    {9017.0 / 3168, -355.0 / 33, 46732.0 / 5247, 49.0 / 176, -5103.0 / 18656, 0},
+    {35.0 / 384, 0, 500.0 / 1113, 125.0 / 192, -2187.0 / 6784, 11.0 / 84}};
+const double DP_B4[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200,
+                         187.0 / 2100, 1.0 / 40};
+
+template <typename T>
+mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, double dt0,
+                     const double* replay, int64_t n_replay, void* trace, int64_t cap,
+                     mmx_rk_stats* stats) {
+  if (ctx->terms & MMX_THERMAL) return fail(MMX_EUNSUP, "thermal field with RK45");
+  if (!(t_end > t0)) return fail(MMX_EINVAL, "t_end must exceed t0");
+  if (!(tol > 0) && !replay) return fail(MMX_EINVAL, "tol must be > 0");
+  if (replay && n_replay < 1) return fail(MMX_EINVAL, "empty dt replay");
+  for (auto& g : ctx->groups) MMX_TRY(ensure_rk_buffers<T>(*g));
+  hipStream_t s = ctx->stream;
+  // controller state
+  RkState h{};
+  h.t = t0;
+  h.t_end = t_end;
+  h.tol = tol;
+  h.dt_max = 1e-11;
+  h.dt_min = 1e-20;
+  if (replay) {
+    h.dt = replay[0];
+    h.n_replay = n_replay;
+  } else {
+    h.dt = std::min(dt0, h.dt_max);
+    h.final_flag = (t0 + h.dt >= t_end) ? 1 : 0;
+    if (h.final_flag) h.dt = t_end - t0;
+  }
+  if (!ctx->st.p) HIP_TRY(ctx->st.alloc(sizeof(RkState)));
+  HIP_TRY(hipMemcpyAsync(ctx->st.p, &h, sizeof(RkState), hipMemcpyHostToDevice, s));
+  const long long want_cap = replay ? n_replay + 16 : std::max<long long>(ctx->dts_cap, 1 << 16);
+  if (ctx->dts_cap < want_cap) {
+    HIP_TRY(ctx->dts.alloc(want_cap * sizeof(double)));
+    ctx->dts_cap = want_cap;
+  }
+  if (replay) {
+    HIP_TRY(ctx->replay.alloc(n_replay * sizeof(double)));
+    HIP_TRY(hipMemcpyAsync(ctx->replay.p, replay, n_replay * sizeof(double),
+                           hipMemcpyHostToDevice, s));
+  }
+  RkState* st = ctx->st.as<RkState>();
+  const int* done = &st->done;
+  const double* dtdev = &st->dt;
+  T* mb = reinterpret_cast<T*>(m);
+  // trace helpers
+  int R_total = 0;
+  for (auto& g : ctx->groups) R_total += g->R;
+  if (trace && !ctx->Etmp.p) HIP_TRY(ctx->Etmp.alloc((size_t)R_total * 6 * sizeof(double)));
+  auto energy_into_trace = [&](int force0) -> mmx_status {
+    int roff = 0;
+    for (auto& gp : ctx->groups) {
+      Group& G = *gp;
+      Epilogue ep;
+      ep.mode = FM_ENERGY;
+      MMX_TRY(eval_group<T>(ctx, G, mb + G.off, Combine{}, ep, 0, 1.0, nullptr, 0.0, nullptr));
+      const double V = G.g.cell[0] * G.g.cell[1] * G.g.cell[2];
+      const double cq = -0.5 * kMu0 * G.mat.Ms * V, cz = -kMu0 * G.mat.Ms * V;
+      k_energy_reduce<<<(G.R + 63) / 64, 64, 0, s>>>(G.partial.as<double>(), G.nblk, G.R, cq, cz,
+                                                      ctx->Etmp.as<double>() + (size_t)roff * 6);
+      HIP_TRY(hipGetLastError());
+      roff += G.R;
+    }
+    k_trace_store<<<1, 1, 0, s>>>(st, ctx->Etmp.as<double>(), R_total, (double*)trace, cap, force0);
+    HIP_TRY(hipGetLastError());
+    return MMX_OK;
+  };
+  // k1 = f(m)
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    Epilogue ep;
+    ep.mode = FM_RKK;
+    ep.out = G.k[0].p;
+    MMX_TRY(eval_group<T>(ctx, G, mb + G.off, Combine{}, ep, 0, 1.0, nullptr, 0.0, nullptr));
+  }
+  if (trace) MMX_TRY(energy_into_trace(1));
+  double e[7];
+  for (int j = 0; j < 7; ++j) e[j] = (j < 6 ? DP_A[6][j] : 0.0) - DP_B4[j];
+  auto one_step = [&]() -> mmx_status {
+    for (auto& gp : ctx->groups) {
+      Group& G = *gp;
+      for (int sidx = 1; sidx < 7; ++sidx) {  // stages 2..7
+        Combine cb;
+        for (int j = 0; j < sidx; ++j) {
+          const double c = DP_A[sidx][j];
+          if (c == 0.0) continue;
+          cb.coef[cb.ncoef] = c;
+          cb.kidx[cb.ncoef] = j;
+          cb.ncoef++;
+        }
+        Epilogue ep;
+        if (sidx < 6) {
+          cb.mout = G.ms.p;
+          ep.mode = FM_RKK;
+          ep.out = G.k[sidx].p;
+        } else {
+          cb.mout = G.m7.p;
+          cb.normalise = 1;
+          ep.mode = FM_RK7;
+          ep.out = G.k[6].p;
+          for (int j = 0; j < 7; ++j) ep.e[j] = e[j];
+        }
+        MMX_TRY(eval_group<T>(ctx, G, mb + G.off, cb, ep, 0, 1.0, dtdev, 0.0, done));
+      }
+    }
+    k_rk_controller<<<1, 1, 0, s>>>(st, replay ? ctx->replay.as<double>() : nullptr,
+                                     ctx->dts.as<double>(), ctx->dts_cap);
+    HIP_TRY(hipGetLastError());
+    for (auto& gp : ctx->groups) {
+      Group& G = *gp;
+      const size_t n = (size_t)G.R * 3 * G.N;
+      const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+      k_rk_commit<T><<<nb, 256, 0, s>>>(st, mb + G.off, G.m7.as<T>(), G.k[0].as<T>(),
+                                         G.k[6].as<T>(), n);
+      HIP_TRY(hipGetLastError());
+    }
+    if (trace) MMX_TRY(energy_into_trace(0));
+    return MMX_OK;
+  };
+  const int chunk = 16;
+  for (;;) {
+    for (int i = 0; i < chunk; ++i) MMX_TRY(one_step());
+    HIP_TRY(hipMemcpyAsync(&h, ctx->st.p, sizeof(RkState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (h.done) break;
+  }
+  ctx->last_accepted = h.accepted;
+  if (stats) {
+    stats->t = h.t;
+    stats->dt = h.dt;
+    stats->err = h.last_err;
+    stats->accepted = h.accepted;
+    stats->rejected = h.rejected;
+  }
+  if (h.dtmin_hit) return fail(MMX_EDTMIN, "step size fell below dt_min");
+  return MMX_OK;
+}
+
+template <typename T>
+mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
+                     void* tsw) {
+  if (!(dt > 0)) return fail(MMX_EINVAL, "dt must be > 0");
+  if (n_steps < 0) return fail(MMX_EINVAL, "n_steps must be >= 0");
+  hipStream_t s = ctx->stream;
+  T* mb = reinterpret_cast<T*>(m);
+  double* tsw_d = reinterpret_cast<double*>(tsw);
+  for (int64_t i = 0; i < n_steps; ++i) {
+    const uint64_t step = step0 + (uint64_t)i;
+    int roff = 0;
+    for (auto& gp : ctx->groups) {
+      Group& G = *gp;
+      T* mg = mb + G.off;
+      Epilogue e1;
+      e1.mode = FM_HEUN1;
+      e1.k1 = G.k[0].p;
+      e1.mout = G.ms.p;
+      MMX_TRY(eval_group<T>(ctx, G, mg, Combine{}, e1, step, dt, nullptr, dt, nullptr));
+      Epilogue e2;
+      e2.mode = FM_HEUN2;
+      e2.k1 = G.k[0].p;
+      e2.m0 = mg;
+      e2.mout = mg;
+      MMX_TRY(eval_group<T>(ctx, G, G.ms.as<T>(), Combine{}, e2, step, dt, nullptr, dt, nullptr));
+      if (tsw_d) {
+        k_switch_reduce<<<(G.R + 63) / 64, 64, 0, s>>>(G.partial.as<double>(), G.nblk, G.R, G.N,
+                                                        tsw_d + roff, (double)(step + 1) * dt);
+        HIP_TRY(hipGetLastError());
+      }
+      roff += G.R;
+    }
+  }
+  return MMX_OK;
+}
+
+template <typename T>
+mmx_status field_impl(mmx_ctx* ctx, const void* m, void* out, uint64_t step, double dt, int mode) {
+  if ((ctx->terms & MMX_THERMAL) && !(dt > 0)) return fail(MMX_EINVAL, "thermal term needs dt > 0");
+  const T* mb = reinterpret_cast<const T*>(m);
+  T* ob = reinterpret_cast<T*>(out);
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    Epilogue ep;
+    ep.mode = mode;
+    ep.out = ob + G.off;
+    MMX_TRY(eval_group<T>(ctx, G, mb + G.off, Combine{}, ep, step, dt > 0 ? dt : 1.0, nullptr,
+                          dt, nullptr));
+  }
+  return MMX_OK;
+}
+
+template <typename T>
+mmx_status energy_impl(mmx_ctx* ctx, const void* m, void* E) {
+  const T* mb = reinterpret_cast<const T*>(m);
+  double* Eb = reinterpret_cast<double*>(E);
+  int roff = 0;
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    Epilogue ep;
+    ep.mode = FM_ENERGY;
+    MMX_TRY(eval_group<T>(ctx, G, mb + G.off, Combine{}, ep, 0, 1.0, nullptr, 0.0, nullptr,
+                          ctx->terms & ~MMX_THERMAL));
+    const double V = G.g.cell[0] * G.g.cell[1] * G.g.cell[2];
+    k_energy_reduce<<<(G.R + 63) / 64, 64, 0, ctx->stream>>>(
+        G.partial.as<double>(), G.nblk, G.R, -0.5 * kMu0 * G.mat.Ms * V, -kMu0 * G.mat.Ms * V,
+        Eb + (size_t)roff * 6);
+    HIP_TRY(hipGetLastError());
+    roff += G.R;
+  }
+  return MMX_OK;
+}
+
+template <typename T>
+mmx_status topo_impl(mmx_ctx* ctx, const void* m, void* Q) {
+  const T* mb = reinterpret_cast<const T*>(m);
+  double* Qb = reinterpret_cast<double*>(Q);
+  int roff = 0;
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    const int plane = G.nx * G.ny;
+    const int nblk = std::max(1, std::min(256, (plane + kBlock - 1) / kBlock));
+    DevBuf part;
+    HIP_TRY(part.alloc((size_t)G.R * nblk * sizeof(double)));
+    dim3 grid(nblk, G.R);
+    k_topo<T><<<grid, kBlock, 0, ctx->stream>>>(mb + G.off, G.nx, G.ny, G.N, G.g.pbc[0],
+                                                G.g.pbc[1], 1.0 / (2 * G.g.cell[0]),
+                                                1.0 / (2 * G.g.cell[1]), part.as<double>(), nblk);
+    HIP_TRY(hipGetLastError());
+    k_topo_reduce<<<(G.R + 63) / 64, 64, 0, ctx->stream>>>(
+        part.as<double>(), nblk, G.R, G.g.cell[0] * G.g.cell[1] / (4 * kPi), Qb + roff);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(ctx->stream));  // `part` is freed on return
+    roff += G.R;
+  }
+  return MMX_OK;
+}
+
+mmx_status check_ctx(const mmx_ctx* c) {
+  if (!c) return fail(MMX_EINVAL, "null context");
+  return MMX_OK;
+}
+
+mmx_status check_group_idx(const mmx_ctx* c, int32_t g) {
+  MMX_TRY(check_ctx(c));
+  if (g < 0 || g >= (int)c->groups.size()) return fail(MMX_EINVAL, "group index out of range");
+  return MMX_OK;
+}
+
+mmx_status check_materials(const mmx_ctx* c) {
+  for (auto& g : c->groups)
+    if (!g->mat_set) return fail(MMX_ESTATE, "material not set for every group");
+  return MMX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mmx_last_error(void) { return g_err.c_str(); }
+
+mmx_status mmx_create(const mmx_group* groups, int32_t n_groups, mmx_prec prec, mmx_ctx** out) {
+  if (!out) return fail(MMX_EINVAL, "out is null");
+  *out = nullptr;
+  if (!groups || n_groups < 1) return fail(MMX_EINVAL, "need at least one group");
+  if (prec != MMX_F32 && prec != MMX_F64) return fail(MMX_EINVAL, "precision must be F32 or F64");
+  for (int i = 0; i < n_groups; ++i) MMX_TRY(check_group(groups[i]));
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(MMX_EUNSUP, std::string("libmmx is built for gfx950, device is ") + prop.gcnArchName);
+  auto ctx = std::make_unique<mmx_ctx>();
+  ctx->prec = prec;
+  size_t off = 0;
+  for (int i = 0; i < n_groups; ++i) {
+    auto G = std::make_unique<Group>();
+    G->g = groups[i];
+    G->off = off;
+    mmx_status s = (prec == MMX_F64) ? setup_group<double>(ctx.get(), *G)
+                                     : setup_group<float>(ctx.get(), *G);
+    if (s != MMX_OK) return s;
+    off += (size_t)G->R * 3 * G->N;
+    ctx->groups.push_back(std::move(G));
+  }
+  ctx->total_elems = off;
+  HIP_TRY(ctx->st.alloc(sizeof(RkState)));
+  HIP_TRY(hipMemset(ctx->st.p, 0, sizeof(RkState)));
+  *out = ctx.release();
+  return MMX_OK;
+}
+
+void mmx_destroy(mmx_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+}
+
+mmx_status mmx_set_stream(mmx_ctx* ctx, void* stream) {
+  MMX_TRY(check_ctx(ctx));
+  ctx->stream = reinterpret_cast<hipStream_t>(stream);
+  return MMX_OK;
+}
+
+mmx_status mmx_set_material(mmx_ctx* ctx, int32_t group, const mmx_material* mat) {
+  MMX_TRY(check_group_idx(ctx, group));
+  if (!mat) return fail(MMX_EINVAL, "material is null");
+  if (!(mat->Ms > 0)) return fail(MMX_EINVAL, "Ms must be > 0");
+  if (mat->A < 0 || mat->alpha < 0) return fail(MMX_EINVAL, "A and alpha must be >= 0");
+  if (mat->D != 0 && mat->A == 0) return fail(MMX_EINVAL, "DMI needs A > 0 (edge condition)");
+  Group& G = *ctx->groups[group];
+  G.mat = *mat;
+  G.mat_set = 1;
+  G.demag_built = 0;
+  return MMX_OK;
+}
+
+mmx_status mmx_set_terms(mmx_ctx* ctx, uint32_t mask) {
+  MMX_TRY(check_ctx(ctx));
+  if (mask & ~(uint32_t)MMX_ALL_TERMS) return fail(MMX_EINVAL, "unknown term bits");
+  ctx->terms = mask;
+  return MMX_OK;
+}
+
+mmx_status mmx_set_field(mmx_ctx* ctx, int32_t group, const double B[3]) {
+  MMX_TRY(check_group_idx(ctx, group));
+  if (!B) return fail(MMX_EINVAL, "B is null");
+  for (int c = 0; c < 3; ++c) ctx->groups[group]->B[c] = B[c];
+  return MMX_OK;
+}
+
+mmx_status mmx_set_thermal(mmx_ctx* ctx, int32_t group, const double* T, const uint64_t* seeds) {
+  MMX_TRY(check_group_idx(ctx, group));
+  if (!T || !seeds) return fail(MMX_EINVAL, "T and seeds must not be null");
+  Group& G = *ctx->groups[group];
+  for (int r = 0; r < G.R; ++r)
+    if (!(T[r] >= 0)) return fail(MMX_EINVAL, "temperatures must be >= 0");
+  HIP_TRY(hipMemcpyAsync(G.Trep.p, T, G.R * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipMemcpyAsync(G.seeds.p, seeds, G.R * sizeof(uint64_t), hipMemcpyHostToDevice,
+                         ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return MMX_OK;
+}
+
+mmx_status mmx_build_demag(mmx_ctx* ctx) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  for (auto& g : ctx->groups) {
+    mmx_status s = (ctx->prec == MMX_F64) ? build_demag_group<double>(ctx, *g)
+                                          : build_demag_group<float>(ctx, *g);
+    if (s != MMX_OK) return s;
+  }
+  return MMX_OK;
+}
+
+mmx_status mmx_field(mmx_ctx* ctx, const void* m, void* H, uint64_t step, double dt) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  if (!m || !H) return fail(MMX_EINVAL, "null array");
+  return ctx->prec == MMX_F64 ? field_impl<double>(ctx, m, H, step, dt, FM_FIELD)
+                              : field_impl<float>(ctx, m, H, step, dt, FM_FIELD);
+}
+
+mmx_status mmx_torque(mmx_ctx* ctx, const void* m, void* dmdt, uint64_t step, double dt) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  if (!m || !dmdt) return fail(MMX_EINVAL, "null array");
+  return ctx->prec == MMX_F64 ? field_impl<double>(ctx, m, dmdt, step, dt, FM_TORQUE)
+                              : field_impl<float>(ctx, m, dmdt, step, dt, FM_TORQUE);
+}
+
+mmx_status mmx_heun(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
+                    void* t_switch) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  if (!m) return fail(MMX_EINVAL, "null array");
+  return ctx->prec == MMX_F64 ? heun_impl<double>(ctx, m, dt, n_steps, step0, t_switch)
+                              : heun_impl<float>(ctx, m, dt, n_steps, step0, t_switch);
+}
+
+mmx_status mmx_rk45(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, double dt0,
+                    const double* dt_replay, int64_t n_replay, void* energy_trace,
+                    int64_t trace_cap, mmx_rk_stats* stats) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  if (!m) return fail(MMX_EINVAL, "null array");
+  if (!dt_replay && !(dt0 > 0)) return fail(MMX_EINVAL, "dt0 must be > 0");
+  return ctx->prec == MMX_F64
+             ? rk45_impl<double>(ctx, m, t0, t_end, tol, dt0, dt_replay, n_replay, energy_trace,
+                                 trace_cap, stats)
+             : rk45_impl<float>(ctx, m, t0, t_end, tol, dt0, dt_replay, n_replay, energy_trace,
+                                trace_cap, stats);
+}
+
+mmx_status mmx_rk45_dts(mmx_ctx* ctx, double* dts, int64_t cap, int64_t* count) {
+  MMX_TRY(check_ctx(ctx));
+  if (!count) return fail(MMX_EINVAL, "count is null");
+  const long long n = std::min<long long>(ctx->last_accepted, ctx->dts_cap);
+  *count = n;
+  if (dts && cap > 0 && n > 0) {
+    HIP_TRY(hipMemcpy(dts, ctx->dts.p, std::min<long long>(n, cap) * sizeof(double),
+                      hipMemcpyDeviceToHost));
+  }
+  return MMX_OK;
+}
+
+mmx_status mmx_energy(mmx_ctx* ctx, const void* m, void* E) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  if (!m || !E) return fail(MMX_EINVAL, "null array");
+  return ctx->prec == MMX_F64 ? energy_impl<double>(ctx, m, E) : energy_impl<float>(ctx, m, E);
+}
+
+mmx_status mmx_topological_charge(mmx_ctx* ctx, const void* m, void* Q) {
+  MMX_TRY(check_ctx(ctx));
+  if (!m || !Q) return fail(MMX_EINVAL, "null array");
+  return ctx->prec == MMX_F64 ? topo_impl<double>(ctx, m, Q) : topo_impl<float>(ctx, m, Q);
+}
+
+}  // extern "C"

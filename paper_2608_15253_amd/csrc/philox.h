@@ -1,0 +1,76 @@
+// Counter-based Gaussian noise for the Brown thermal field (device code).
+//
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11): ten rounds on a
+// 4 x 32-bit counter with a 2 x 32-bit key; each round forms the two 64-bit
+// products of counter words 0 and 2 with the published multipliers, mixes
+// their high halves with the other counter words and the round key, and the
+// key is advanced by the published Weyl constants between rounds.
+// Key = replica seed (low, high); counter = (cell, step low, step high, 0).
+// Uniforms (x + 1/2) 2^-32, Box-Muller on (u0, u1) and (u2, u3); the first
+// three normals are the x, y, z components.
+#pragma once
+#include "common.h"
+
+namespace mmx {
+
+__device__ inline void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+  constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(M0, c[0]), lo0 = M0 * c[0];
+    const uint32_t hi1 = __umulhi(M1, c[2]), lo1 = M1 * c[2];
+    const uint32_t n0 = hi1 ^ c[1] ^ k0;
+    const uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += W0;
+    k1 += W1;
+  }
+}
+
+template <typename T>
+struct BoxMuller;
+
+template <>
+struct BoxMuller<double> {
+  static __device__ inline void eta(const uint32_t w[4], double out[3]) {
+    const double s = 2.3283064365386962890625e-10;  // 2^-32
+    const double u0 = ((double)w[0] + 0.5) * s, u1 = ((double)w[1] + 0.5) * s;
+    const double u2 = ((double)w[2] + 0.5) * s, u3 = ((double)w[3] + 0.5) * s;
+    const double r01 = sqrt(-2.0 * log(u0));
+    const double r23 = sqrt(-2.0 * log(u2));
+    double sn, cs;
+    sincospi(2.0 * u1, &sn, &cs);
+    out[0] = r01 * cs;
+    out[1] = r01 * sn;
+    out[2] = r23 * cospi(2.0 * u3);
+  }
+};
+
+template <>
+struct BoxMuller<float> {
+  static __device__ inline void eta(const uint32_t w[4], float out[3]) {
+    const float s = 2.3283064365386962890625e-10f;
+    const float u0 = fmaf((float)w[0], s, 0.5f * s), u1 = fmaf((float)w[1], s, 0.5f * s);
+    const float u2 = fmaf((float)w[2], s, 0.5f * s), u3 = fmaf((float)w[3], s, 0.5f * s);
+    const float r01 = sqrtf(-2.0f * logf(u0));
+    const float r23 = sqrtf(-2.0f * logf(u2));
+    float sn, cs;
+    sincospif(2.0f * u1, &sn, &cs);
+    out[0] = r01 * cs;
+    out[1] = r01 * sn;
+    out[2] = r23 * cospif(2.0f * u3);
+  }
+};
+
+template <typename T>
+__device__ inline void thermal_eta(uint64_t seed, uint32_t cell, uint64_t step, T out[3]) {
+  uint32_t c[4] = {cell, (uint32_t)(step & 0xFFFFFFFFull), (uint32_t)(step >> 32), 0u};
+  philox4x32_10(c, (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32));
+  BoxMuller<T>::eta(c, out);
+}
+
+}  // namespace mmx

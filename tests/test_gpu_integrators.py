@@ -1,0 +1,182 @@
+"""GPU parity of the time integrators through the C ABI against the FP64
+oracle (Methods, "Integrators" and "Replica batching"): Stratonovich Heun with
+the Brown field, switching times, adaptive Dormand-Prince 5(4) (independent
+runs and dt replay), energy and topological charge.
+
+Bars: FP64 max |dm| <= 1e-12, FP32 max |dm| <= 1e-5 (the north-star
+tolerances); batched versus per-trial runs bit-identical.
+"""
+import numpy as np
+import pytest
+
+from oracle import integrators as oit
+from oracle import observables as oob
+from workloads import neel_skyrmions, random_unit, replica_seeds, uniform
+
+from _mmx_case import Case, dev, host, open_ctx
+
+pytestmark = pytest.mark.gpu
+
+TOLM = {2: 1e-12, 1: 1e-5}
+
+
+def _round(m, prec):
+    return m.astype(np.float32).astype(np.float64) if prec == 1 else m
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_heun_thermal_batch_matches_oracle(prec):
+    import paper_2608_15253_amd as mmx
+    case = Case((24, 20, 1), (4e-9, 4e-9, 4e-9), R=3, alpha=0.02, Ku=5e5,
+                B=(0, 0, -0.15), T=300.0, seeds=list(replica_seeds(3, 3)),
+                terms=("exchange", "anisotropy", "zeeman", "demag", "thermal"))
+    print(f"[case] heun 3x24x20 prec={prec}", flush=True)
+    m0 = _round(random_unit(case.n, seed=4, replicas=case.R), prec)
+    ctx = open_ctx(case, prec)
+    try:
+        md = dev(m0, prec)
+        mmx.mmx_heun(ctx, md, 1e-14, 25, 100)
+        got = host(md)
+    finally:
+        mmx.mmx_destroy(ctx)
+    ref = oit.heun_run(m0, case.grid, case.material(), 1e-14, 25,
+                       seed=np.array(case.seeds), step0=100)
+    err = np.abs(got - ref).max()
+    assert err <= TOLM[prec], err
+    assert np.abs(np.linalg.norm(got, axis=1) - 1).max() < (1e-14 if prec == 2 else 1e-6)
+
+
+def test_heun_switching_times_match_oracle():
+    import paper_2608_15253_amd as mmx
+    case = Case((4, 4, 1), (4e-9, 4e-9, 4e-9), R=4, alpha=1.0, Ku=1e5, B=(0, 0, -2.0),
+                T=50.0, seeds=list(replica_seeds(9, 4)),
+                terms=("exchange", "anisotropy", "zeeman", "demag", "thermal"))
+    m0 = uniform(case.n, (0.05, 0.0, 1.0), replicas=case.R)
+    ctx = open_ctx(case, 2)
+    try:
+        md = dev(m0, 2)
+        ts = dev(-np.ones(case.R), 2)
+        mmx.mmx_heun(ctx, md, 1e-13, 400, 0, ts)
+        got = host(ts)
+        gm = host(md)
+    finally:
+        mmx.mmx_destroy(ctx)
+    tsw = [-1.0] * case.R
+    ref = oit.heun_run(m0, case.grid, case.material(), 1e-13, 400, seed=np.array(case.seeds),
+                       t_switch=tsw)
+    assert np.abs(gm - ref).max() <= 1e-12
+    assert all(t > 0 for t in tsw)
+    assert np.array_equal(got, np.array(tsw))
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_batched_equals_per_trial_bitwise(prec):
+    """Replica batching changes performance, not results: R replicas in one
+    launch equal R single-replica contexts bit for bit (Methods, "Replica
+    batching": R = 1 regression)."""
+    import paper_2608_15253_amd as mmx
+    R = 4
+    seeds = list(replica_seeds(5, R))
+    case = Case((16, 16, 1), (4e-9, 4e-9, 4e-9), R=R, alpha=0.02, Ku=5e5, B=(0, 0, -0.15),
+                T=300.0, seeds=seeds,
+                terms=("exchange", "anisotropy", "zeeman", "demag", "thermal"))
+    m0 = _round(random_unit(case.n, seed=6, replicas=R), prec)
+    ctx = open_ctx(case, prec)
+    try:
+        md = dev(m0, prec)
+        mmx.mmx_heun(ctx, md, 1e-14, 10, 0)
+        batched = host(md)
+    finally:
+        mmx.mmx_destroy(ctx)
+    for r in range(R):
+        one = Case(case.n, case.cell, R=1, alpha=case.alpha, Ku=case.Ku, B=case.B, T=case.T,
+                   seeds=[seeds[r]], terms=case.terms)
+        ctx = open_ctx(one, prec)
+        try:
+            md = dev(m0[r:r + 1], prec)
+            mmx.mmx_heun(ctx, md, 1e-14, 10, 0)
+            single = host(md)
+        finally:
+            mmx.mmx_destroy(ctx)
+        assert np.array_equal(single[0], batched[r])
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_rk45_relaxation_matches_oracle(prec):
+    import paper_2608_15253_amd as mmx
+    case = Case((16, 12, 1), (4e-9, 4e-9, 4e-9), R=1, alpha=0.5,
+                terms=("exchange", "demag"))
+    m0 = _round(random_unit(case.n, seed=1, replicas=1), prec)
+    t_end = 2e-11
+    ctx = open_ctx(case, prec)
+    try:
+        md = dev(m0, prec)
+        st = mmx.mmx_rk45(ctx, md, 0.0, t_end, 1e-6, 1e-14)
+        got = host(md)
+        dts = mmx.mmx_rk45_dts(ctx)
+    finally:
+        mmx.mmx_destroy(ctx)
+    assert st.t == t_end and st.accepted == len(dts)
+    ref = oit.rk45_run(m0[0], case.grid, case.material(), 0.0, t_end, 1e-6, 1e-14)
+    if prec == 2:
+        # same controller decisions, same states
+        assert st.accepted == ref.accepted and st.rejected == ref.rejected
+        assert np.allclose(dts, ref.dts, rtol=1e-9, atol=0)
+        assert np.abs(got[0] - ref.m).max() <= 1e-11
+    # dt replay: oracle integrates exactly the GPU's accepted steps
+    rep = oit.rk45_run(m0[0], case.grid, case.material(), 0.0, t_end, 1e-6, dt_replay=dts)
+    err = np.abs(got[0] - rep.m).max()
+    assert err <= TOLM[prec] * (10 if prec == 2 else 1), err
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_rk45_dt_replay_mode(prec):
+    import paper_2608_15253_amd as mmx
+    case = Case((12, 10, 1), (2e-9, 2e-9, 0.6e-9), pbc=(1, 1, 0), images=(1, 1, 0), R=1,
+                alpha=0.3, Ms=5.8e5, A=1.5e-11, D=3e-3, Ku=0.8e6, B=(0, 0, 0.1))
+    m0 = _round(random_unit(case.n, seed=3, replicas=1), prec)
+    dts = [1e-14, 2e-14, 3e-14, 3e-14, 5e-14, 1e-14]
+    ctx = open_ctx(case, prec)
+    try:
+        md = dev(m0, prec)
+        trace = dev(np.zeros(len(dts) + 1), 2)
+        st = mmx.mmx_rk45(ctx, md, 0.0, sum(dts), 1e-6, 1e-14, dt_replay=dts,
+                          energy_trace=trace, trace_cap=len(dts) + 1)
+        got = host(md)
+        tr = host(trace)
+    finally:
+        mmx.mmx_destroy(ctx)
+    assert st.accepted == len(dts)
+    rep = oit.rk45_run(m0[0], case.grid, case.material(), 0.0, sum(dts), 1e-6,
+                       dt_replay=dts, energy=True)
+    assert np.abs(got[0] - rep.m).max() <= TOLM[prec]
+    assert np.allclose(tr, rep.energy, rtol=(1e-11 if prec == 2 else 1e-5), atol=0)
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_energy_and_charge_match_oracle(prec):
+    import paper_2608_15253_amd as mmx
+    n, cell = (64, 48, 1), (2e-9, 2e-9, 0.6e-9)
+    case = Case(n, cell, pbc=(1, 1, 0), images=(2, 2, 0), R=2, Ms=5.8e5, A=1.5e-11, D=3e-3,
+                Ku=0.8e6, alpha=0.3, B=(0, 0, 0.1))
+    m1, _, _ = neel_skyrmions(n, cell, 2, 10e-9, 14e-9, seed=2, width=5.05e-9)
+    m2 = random_unit(n, seed=8)
+    m0 = _round(np.stack([m1, m2]), prec)
+    ctx = open_ctx(case, prec)
+    try:
+        md = dev(m0, prec)
+        E = dev(np.zeros((2, 6)), 2)
+        Q = dev(np.zeros(2), 2)
+        mmx.mmx_energy(ctx, md, E)
+        mmx.mmx_topological_charge(ctx, md, Q)
+        ge, gq = host(E), host(Q)
+    finally:
+        mmx.mmx_destroy(ctx)
+    for r in range(2):
+        ref = oob.energies(m0[r], case.grid, case.material())
+        vals = [ref[k] for k in ("exchange", "dmi", "demag", "anisotropy", "zeeman", "total")]
+        scale = max(abs(v) for v in vals)
+        assert np.abs(ge[r] - np.array(vals)).max() <= (1e-12 if prec == 2 else 2e-6) * scale
+        q = oob.topological_charge(m0[r], case.grid)
+        assert abs(gq[r] - q) <= 1e-12 * max(1.0, abs(q)) * (1 if prec == 2 else 1e5)
+    assert abs(gq[0] + 2) < 0.1
