@@ -1,0 +1,235 @@
+"""Benchmark of the replica-batched effective-field + LLG step on one MI355X.
+
+Workload (the batching form): R = 1024 replicas of a 64x64x1 film of 4 nm cells,
+Ms 8e5 A/m, A 1.3e-11 J/m, alpha 0.02, Ku 5e5 J/m^3 along z, open boundaries,
+demag on, m0 = +z, Bz = -0.15 T, T = 300 K Brown field from per-replica Philox
+keys, Stratonovich Heun with dt = 1e-14 s, FP32.  One bench step = one Heun step
+of every replica (two full field evaluations: demag FFT convolution, exchange,
+anisotropy, Zeeman, thermal, LLG torque, predictor and corrector) plus the
+switching-time update.
+
+Reported (one JSON line): batched cell-steps/s (replicas x cells x steps / s),
+the per-trial loop rate on the same GPU (the same kernels on single-replica
+contexts, one call per trial per step), the parity gate max |dm| between the
+two, the roofline of the dominant kernel from HIP-event timings, and the FP64
+oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("LLG cell-steps/s (replicas×cells×steps) batched vs per-trial at "
+          "|Δm|≤1e-5")
+HBM_PEAK_GBS = 8000.0
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2608_15253_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kernel: str, R: int, nx: int, ny: int, w: int) -> float | None:
+    """Bytes each kernel must move per launch for R replicas (each input read
+    once, each output written once; spectrum rows y < ny, kx < nx + 1)."""
+    N = nx * ny
+    spec = 3 * ny * (nx + 1) * 2 * w      # half spectrum of one replica
+    state = 3 * N * w                      # one magnetisation-sized array
+    per = {
+        "k_xfwd": state + spec,
+        "k_yconv": 2 * spec,
+        "k_fields_heun1": spec + state + 2 * state,
+        "k_fields_heun2": spec + 3 * state + state,
+    }
+    if kernel not in per:
+        return None
+    return float(per[kernel]) * R
+
+
+def read_traffic(kernel: str, src_hash: str):
+    """HBM bytes per launch of ``kernel`` from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(PROFILES, "traffic_thermal_switching_64x64_r1024.md")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"source_hash:\s*([0-9a-f]+)", text)
+    if not m or m.group(1) != src_hash:
+        return None
+    m = re.search(rf"^\|\s*{re.escape(kernel)}\s*\|[^\n]*\|\s*([0-9.eE+]+)\s*\|\s*$", text, re.M)
+    return float(m.group(1)) if m else None
+
+
+def setup(R, prec, seeds, n=(64, 64, 1)):
+    import torch
+    import paper_2608_15253_amd as mmx
+    grp = mmx.make_group(n, (4e-9, 4e-9, 4e-9), replicas=R)
+    ctx = mmx.mmx_create([grp], prec)
+    mmx.mmx_set_stream(ctx, torch.cuda.current_stream().cuda_stream)
+    mmx.mmx_set_material(ctx, 0, Ms=8.0e5, A=1.3e-11, alpha=0.02, Ku=5e5, u=(0, 0, 1), D=0.0)
+    mmx.mmx_set_field(ctx, 0, (0.0, 0.0, -0.15))
+    mmx.mmx_set_thermal(ctx, 0, [300.0] * R, seeds)
+    mmx.mmx_set_terms(ctx, mmx.MMX_EXCH | mmx.MMX_ANIS_UNIAXIAL | mmx.MMX_ZEEMAN |
+                      mmx.MMX_DEMAG | mmx.MMX_THERMAL)
+    mmx.mmx_build_demag(ctx)
+    mmx.mmx_autotune(ctx)
+    return ctx
+
+
+def cpu_baseline(seconds: float = 12.0):
+    """The FP64 oracle (numpy, single thread) on a bounded sample of the same
+    workload: 16 replicas advanced by Heun steps for about ``seconds``."""
+    from oracle import Grid, Material
+    from oracle import integrators as oit
+    from workloads import replica_seeds, uniform
+    R = 16
+    grid = Grid((64, 64, 1), (4e-9, 4e-9, 4e-9))
+    mat = Material(Ms=8.0e5, A=1.3e-11, alpha=0.02, Ku=5e5, B=(0, 0, -0.15), T=300.0)
+    seeds = replica_seeds(3, R)
+    m = uniform(grid.n, replicas=R)
+    m = oit.heun_run(m, grid, mat, 1e-14, 1, seed=seeds, step0=0)  # builds the kernel
+    t0 = time.perf_counter()
+    m = oit.heun_run(m, grid, mat, 1e-14, 2, seed=seeds, step0=1)
+    per_step = (time.perf_counter() - t0) / 2
+    steps = max(2, int(seconds / per_step))
+    t0 = time.perf_counter()
+    oit.heun_run(m, grid, mat, 1e-14, steps, seed=seeds, step0=3)
+    el = time.perf_counter() - t0
+    return {"value": R * grid.ncells * steps / el, "unit": "cell-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"FP64 numpy oracle, {R} replicas x 64x64x1 cells x {steps} Heun steps "
+                      f"({el:.1f} s, single thread)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--replicas", type=int, default=1024)
+    ap.add_argument("--trials", type=int, default=32, help="replicas in the per-trial loop")
+    ap.add_argument("--trial-steps", type=int, default=100)
+    ap.add_argument("--prof-steps", type=int, default=50)
+    ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import replica_seeds, uniform
+
+    prec = mmx.MMX_F32 if args.prec == "f32" else mmx.MMX_F64
+    tdt = torch.float32 if prec == mmx.MMX_F32 else torch.float64
+    w = 4 if prec == mmx.MMX_F32 else 8
+    R, nx, ny = args.replicas, 64, 64
+    N = nx * ny
+    dt = 1e-14
+    seeds = replica_seeds(3, R)
+    m0 = uniform((nx, ny, 1), replicas=R)
+    dev = torch.device("cuda:0")
+
+    ctx = setup(R, prec, seeds)
+    m = torch.tensor(m0, dtype=tdt, device=dev).contiguous()
+    tsw = torch.full((R,), -1.0, dtype=torch.float64, device=dev)
+
+    # ---- per-trial loop (same kernels, single-replica contexts) ------------
+    K_t = args.trial_steps
+    trials = min(args.trials, R)
+    tctx = [setup(1, prec, seeds[r:r + 1]) for r in range(trials)]
+    tm = [torch.tensor(m0[r:r + 1], dtype=tdt, device=dev).contiguous() for r in range(trials)]
+    tts = [torch.full((1,), -1.0, dtype=torch.float64, device=dev) for _ in range(trials)]
+    for r in range(trials):  # warm-up launch paths
+        mmx.mmx_heun(tctx[r], tm[r].clone(), dt, 1, 0, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K_t):
+        for r in range(trials):
+            mmx.mmx_heun(tctx[r], tm[r], dt, 1, k, tts[r])
+    torch.cuda.synchronize()
+    t_trial = time.perf_counter() - t0
+    trial_rate = trials * N * K_t / t_trial
+
+    # ---- batched parity gate: same K_t steps on all replicas ---------------
+    mmx.mmx_heun(ctx, m, dt, K_t, 0, tsw)
+    torch.cuda.synchronize()
+    gate = max(float((m[r:r + 1] - tm[r]).abs().max()) for r in range(trials))
+    for c in tctx:
+        mmx.mmx_destroy(c)
+
+    # ---- timed batched run --------------------------------------------------
+    step = K_t
+    mmx.mmx_heun(ctx, m, dt, args.warmup, step, tsw)
+    step += args.warmup
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    mmx.mmx_heun(ctx, m, dt, args.steps, step, tsw)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t0
+    step += args.steps
+    t_ev = ev0.elapsed_time(ev1) / 1e3
+    batched_rate = R * N * args.steps / t_wall
+
+    # ---- per-kernel HIP-event timings over the same step sequence ----------
+    mmx.mmx_profile_enable(ctx, 1)
+    mmx.mmx_heun(ctx, m, dt, args.prof_steps, step, tsw)
+    prof = mmx.mmx_profile_get(ctx)
+    mmx.mmx_profile_enable(ctx, 0)
+    step += args.prof_steps
+    torch.cuda.synchronize()
+    kernels = {k: {"avg_us": v[0] / v[1] * 1e3, "launches": v[1],
+                   "share": v[0] / sum(x[0] for x in prof.values())}
+               for k, v in prof.items()}
+    dom = max(prof, key=lambda k: prof[k][0])
+    src_hash = kernel_source_hash()
+    alg = algorithmic_bytes(dom, R, nx, ny, w)
+    avg_s = prof[dom][0] / prof[dom][1] / 1e3
+    achieved = alg / avg_s / 1e9 if alg else None
+    roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS if achieved else None,
+            "traffic": read_traffic(dom, src_hash), "algorithmic_bytes": alg,
+            "avg_launch_us": avg_s * 1e6, "source_hash": src_hash}
+    switched = int((tsw > 0).sum())
+    tiles = mmx.mmx_get_tiles(ctx, 0)
+    mmx.mmx_destroy(ctx)
+
+    out = {
+        "metric": METRIC, "value": batched_rate, "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": t_wall / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": "thermal_switching_64x64x1_R1024_heun", "replicas": R,
+                   "grid": [nx, ny, 1], "cell_nm": 4, "dt_s": dt, "T_K": 300,
+                   "integrator": "stratonovich_heun", "terms": "demag+exch+anis+zeeman+thermal"},
+        "per_trial": {"value": trial_rate, "unit": "cell-steps/s", "trials": trials,
+                      "steps": K_t, "seconds": t_trial},
+        "speedup_vs_per_trial": batched_rate / trial_rate,
+        "parity_max_dm_batched_vs_per_trial": gate,
+        "event_seconds": t_ev, "switched_replicas": switched, "simulated_steps": step,
+        "tiles": list(tiles), "kernels": kernels, "roofline": roof,
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

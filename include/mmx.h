@@ -177,6 +177,41 @@ mmx_status mmx_energy(mmx_ctx* ctx, const void* m, void* E);
  * differences (periodic wrap, the cell itself beyond open edges). */
 mmx_status mmx_topological_charge(mmx_ctx* ctx, const void* m, void* Q);
 
+/* Tile sizes of group g: tiles[0] = grid rows per workgroup of the x
+ * transform / local-field kernels, tiles[1] = spectrum columns per workgroup
+ * of the y transform, tiles[2] = of the z transform.  Results are identical
+ * for every valid choice; only speed changes.  mmx_set_tiles rejects sizes
+ * outside [1, n_y] / [1, n_x/2 + 1] or beyond 64 KiB of LDS per workgroup
+ * (MMX_EINVAL) and synchronises the stream.  mmx_autotune times one field
+ * evaluation of every group (after mmx_build_demag) for candidate sizes
+ * 1, 2, 4, ..., 32 per tile, keeps the fastest, and synchronises; it
+ * overwrites the library's stage buffers, not caller arrays. */
+/* Execution path of mmx_heun.  MMX_PATH_STAGED: every field evaluation is
+ * three (2-D) or five (3-D) launches over all replicas, with the spectrum in
+ * HBM.  MMX_PATH_FUSED: one workgroup per replica runs whole Heun steps with
+ * the replica's half spectrum resident in LDS (2-D films whose spectrum, row
+ * and column scratch fit the device's LDS per workgroup; mmx_heun returns
+ * MMX_EUNSUP otherwise).  MMX_PATH_AUTO (default): fused where it fits, staged
+ * elsewhere.  Both paths compute the same arithmetic per transform line and
+ * per cell. */
+enum { MMX_PATH_AUTO = 0, MMX_PATH_STAGED = 1, MMX_PATH_FUSED = 2 };
+mmx_status mmx_set_path(mmx_ctx* ctx, int32_t path);
+
+mmx_status mmx_set_tiles(mmx_ctx* ctx, int32_t group, const int32_t tiles[3]);
+mmx_status mmx_get_tiles(mmx_ctx* ctx, int32_t group, int32_t tiles[3]);
+mmx_status mmx_autotune(mmx_ctx* ctx);
+
+/* Measurement support (not part of the method).  mmx_profile_enable(ctx, 1)
+ * clears the statistics and brackets every later kernel launch of ctx with a
+ * pair of HIP events on the bound stream; mmx_profile_enable(ctx, 0) stops.
+ * mmx_profile_get reports, for kernel index idx (0 <= idx < *n_kernels), its
+ * name (NUL-terminated, truncated to name_cap), the summed event time in ms
+ * and the launch count; with idx < 0 only *n_kernels is written.  Both calls
+ * synchronise the stream. */
+mmx_status mmx_profile_enable(mmx_ctx* ctx, int32_t on);
+mmx_status mmx_profile_get(mmx_ctx* ctx, int32_t idx, char* name, int32_t name_cap,
+                           double* total_ms, int64_t* count, int32_t* n_kernels);
+
 const char* mmx_last_error(void);
 
 #ifdef __cplusplus

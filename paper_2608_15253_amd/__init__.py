@@ -79,6 +79,14 @@ _SIGS = {
                      ctypes.POINTER(ctypes.c_int64)],
     "mmx_energy": [_P, _P, _P],
     "mmx_topological_charge": [_P, _P, _P],
+    "mmx_set_path": [_P, ctypes.c_int32],
+    "mmx_set_tiles": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "mmx_get_tiles": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
+    "mmx_autotune": [_P],
+    "mmx_profile_enable": [_P, ctypes.c_int32],
+    "mmx_profile_get": [_P, ctypes.c_int32, ctypes.c_char_p, ctypes.c_int32,
+                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                        ctypes.POINTER(ctypes.c_int32)],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -202,3 +210,45 @@ def mmx_energy(ctx, m, E) -> None:
 
 def mmx_topological_charge(ctx, m, Q) -> None:
     _check("mmx_topological_charge", _lib.mmx_topological_charge(ctx, _ptr(m), _ptr(Q)))
+
+
+MMX_PATH_AUTO, MMX_PATH_STAGED, MMX_PATH_FUSED = 0, 1, 2
+
+
+def mmx_set_path(ctx, path) -> None:
+    _check("mmx_set_path", _lib.mmx_set_path(ctx, int(path)))
+
+
+def mmx_set_tiles(ctx, group, tiles) -> None:
+    arr = (ctypes.c_int32 * 3)(*[int(v) for v in tiles])
+    _check("mmx_set_tiles", _lib.mmx_set_tiles(ctx, group, arr))
+
+
+def mmx_get_tiles(ctx, group) -> tuple:
+    arr = (ctypes.c_int32 * 3)()
+    _check("mmx_get_tiles", _lib.mmx_get_tiles(ctx, group, arr))
+    return tuple(arr)
+
+
+def mmx_autotune(ctx) -> None:
+    _check("mmx_autotune", _lib.mmx_autotune(ctx))
+
+
+def mmx_profile_enable(ctx, on) -> None:
+    _check("mmx_profile_enable", _lib.mmx_profile_enable(ctx, 1 if on else 0))
+
+
+def mmx_profile_get(ctx) -> dict:
+    """{kernel name: (total ms, launches)} of the events recorded so far."""
+    n = ctypes.c_int32()
+    _check("mmx_profile_get", _lib.mmx_profile_get(ctx, -1, None, 0, None, None,
+                                                   ctypes.byref(n)))
+    out = {}
+    for i in range(n.value):
+        name = ctypes.create_string_buffer(64)
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        _check("mmx_profile_get", _lib.mmx_profile_get(ctx, i, name, 64, ctypes.byref(ms),
+                                                       ctypes.byref(cnt), ctypes.byref(n)))
+        out[name.value.decode()] = (ms.value, cnt.value)
+    return out

@@ -100,12 +100,16 @@ __device__ inline void stockham_pass(const cpx<T>* __restrict__ src, cpx<T>* __r
   const int nb = n / R;
   const int total = nb * nlines;
   const int twscale = n / (Ns * R);
+  // power-of-two extents (the common case) index with shifts and masks
+  const bool p2 = ((nb & (nb - 1)) == 0) && ((Ns & (Ns - 1)) == 0);
+  const int lnb = __builtin_ctz(nb), lns = __builtin_ctz(Ns);
   for (int t = tid; t < total; t += nthr) {
-    const int line = t / nb;
+    const int line = p2 ? (t >> lnb) : t / nb;
     const int j = t - line * nb;
     const cpx<T>* s = src + line * n;
     cpx<T>* d = dst + line * n;
-    const int jm = j % Ns;
+    const int jq = p2 ? (j >> lns) : j / Ns;
+    const int jm = j - jq * Ns;
     cpx<T> v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = s[j + r * nb];
@@ -121,7 +125,7 @@ __device__ inline void stockham_pass(const cpx<T>* __restrict__ src, cpx<T>* __r
     if constexpr (R == 4) Dft<T, INV>::r4(v);
     if constexpr (R == 5) Dft<T, INV>::r5(v);
     if constexpr (R == 8) Dft<T, INV>::r8(v);
-    const int idxD = (j / Ns) * Ns * R + jm;
+    const int idxD = jq * Ns * R + jm;
 #pragma unroll
     for (int r = 0; r < R; ++r) d[idxD + r * Ns] = v[r];
   }

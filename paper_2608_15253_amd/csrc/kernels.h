@@ -41,6 +41,13 @@ struct RkState {
   int done, accepted_flag, final_flag, nonfinite, dtmin_hit, pad;
 };
 
+// Copies a twiddle table into LDS (callers reach a barrier before using it).
+template <typename T>
+__device__ inline const cpx<T>* stage_table(cpx<T>* dst, const cpx<T>* __restrict__ src, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  return dst;
+}
+
 // ---------------------------------------------------------------------------
 // x forward transform with stage combine
 // ---------------------------------------------------------------------------
@@ -70,6 +77,8 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
   const int hx = a.hx, L = a.L, nl = 3 * L;
   cpx<T>* Bf = A + nl * hx;
+  const cpx<T>* tw = a.do_fft ? stage_table(Bf + nl * hx, a.tw, hx) : nullptr;
+  const cpx<T>* wpost = a.do_fft ? stage_table(Bf + nl * hx + hx, a.wpost, hx + 1) : nullptr;
   const int r = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * L;
   const size_t rb = (size_t)r * 3 * a.N;
   const T dt = a.dtdev ? (T)(*a.dtdev) : (T)a.dth;
@@ -112,7 +121,7 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
   }
   if (!a.do_fft) return;
   __syncthreads();
-  const cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.plan, a.tw);
+  const cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.plan, tw);
   const int Kx = a.Kx;
   for (int t = threadIdx.x; t < nl * Kx; t += blockDim.x) {
     const int line = t / Kx, kx = t - line * Kx;
@@ -127,7 +136,7 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
       Zc.im = -Zc.im;
       const cpx<T> E = {T(0.5) * (Zk.re + Zc.re), T(0.5) * (Zk.im + Zc.im)};
       const cpx<T> O = {T(0.5) * (Zk.re - Zc.re), T(0.5) * (Zk.im - Zc.im)};
-      const cpx<T> w = a.wpost[kx];
+      const cpx<T> w = wpost[kx];
       out = {E.re + (w.re * O.im + w.im * O.re), E.im - (w.re * O.re - w.im * O.im)};
     }
     a.S[((((size_t)r * 3 + c) * a.nz + z) * a.Sy + y) * Kx + kx] = out;
@@ -175,6 +184,7 @@ __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
   const int W = a.W, Py = a.Py, nl = 3 * W;
   cpx<T>* Bf = A + nl * Py;
+  const cpx<T>* tw = stage_table(Bf + nl * Py, a.tw, Py);
   const int r = blockIdx.z, kx0 = blockIdx.x * W;
   const size_t rbase = (size_t)r * 3;
   for (int t = threadIdx.x; t < nl * Py; t += blockDim.x) {
@@ -185,7 +195,7 @@ __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
     A[(c * W + w) * Py + y] = v;
   }
   __syncthreads();
-  cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, a.tw);
+  cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, tw);
   cpx<T>* scratch = (X == A) ? Bf : A;
   const size_t cs = (size_t)a.Tz * a.Ty * a.Kx;
   for (int t = threadIdx.x; t < W * Py; t += blockDim.x) {
@@ -200,7 +210,7 @@ __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
     tensor_apply(a.Nt, cs, (size_t)ty * a.Kx + kx, sy, T(1), sy, false, Mx, My, Mz);
   }
   __syncthreads();
-  const cpx<T>* Y = lds_fft<T, true>(X, scratch, nl, a.pi, a.tw);
+  const cpx<T>* Y = lds_fft<T, true>(X, scratch, nl, a.pi, tw);
   for (int t = threadIdx.x; t < nl * a.ny; t += blockDim.x) {
     const int w = t % W, rest = t / W, y = rest % a.ny, c = rest / a.ny;
     if (kx0 + w < a.Kx)
@@ -218,6 +228,7 @@ __global__ void __launch_bounds__(kBlock) k_ypass(YArgs<T> a) {
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
   const int W = a.W, Py = a.Py, nl = 3 * W;
   cpx<T>* Bf = A + nl * Py;
+  const cpx<T>* tw = stage_table(Bf + nl * Py, a.tw, Py);
   const int r = blockIdx.z, z = blockIdx.y, kx0 = blockIdx.x * W;
   const size_t rbase = (size_t)r * 3;
   const int nin = INV ? Py : a.ny;
@@ -229,7 +240,7 @@ __global__ void __launch_bounds__(kBlock) k_ypass(YArgs<T> a) {
     A[(c * W + w) * Py + y] = v;
   }
   __syncthreads();
-  const cpx<T>* Y = lds_fft<T, INV>(A, Bf, nl, INV ? a.pi : a.pf, a.tw);
+  const cpx<T>* Y = lds_fft<T, INV>(A, Bf, nl, INV ? a.pi : a.pf, tw);
   const int nout = INV ? a.ny : Py;
   for (int t = threadIdx.x; t < nl * nout; t += blockDim.x) {
     const int w = t % W, rest = t / W, y = rest % nout, c = rest / nout;
@@ -246,6 +257,7 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
   const int W = a.W, Pz = a.Pz, nl = 3 * W;
   cpx<T>* Bf = A + nl * Pz;
+  const cpx<T>* tw = stage_table(Bf + nl * Pz, a.tw, Pz);
   const int r = blockIdx.z, ky = blockIdx.y, kx0 = blockIdx.x * W;
   const size_t rbase = (size_t)r * 3;
   for (int t = threadIdx.x; t < nl * Pz; t += blockDim.x) {
@@ -256,7 +268,7 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
     A[(c * W + w) * Pz + z] = v;
   }
   __syncthreads();
-  cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, a.tw);
+  cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, tw);
   cpx<T>* scratch = (X == A) ? Bf : A;
   const size_t cs = (size_t)a.Tz * a.Ty * a.Kx;
   const bool ylo = 2 * ky <= a.Py;
@@ -275,7 +287,7 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
                  Mz);
   }
   __syncthreads();
-  const cpx<T>* Y = lds_fft<T, true>(X, scratch, nl, a.pi, a.tw);
+  const cpx<T>* Y = lds_fft<T, true>(X, scratch, nl, a.pi, tw);
   for (int t = threadIdx.x; t < nl * a.nz; t += blockDim.x) {
     const int w = t % W, rest = t / W, z = rest % a.nz, c = rest / a.nz;
     if (kx0 + w < a.Kx)
@@ -326,6 +338,67 @@ __device__ inline void ld3(const T* __restrict__ m, size_t rb, int N, size_t cel
   v[2] = m[rb + 2 * (size_t)N + cell];
 }
 
+// Exchange (six-point Laplacian), interfacial DMI (central differences), both
+// with periodic wrap or free-edge ghosts m_edge -/+ D_a (D/2A)(z x n) x m at
+// open x/y edges (Neumann along z), uniaxial anisotropy and Zeeman field of
+// the cell at (x, y, z) with magnetisation mc; neighbours read from m.
+template <typename T>
+__device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ m, size_t rb,
+                                   size_t cell, int x, int y, int z, const T mc[3], T kbc,
+                                   T Hex[3], T Hdm[3], T Han[3], T Hz[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) { Hex[c] = 0; Hdm[c] = 0; Han[c] = 0; Hz[c] = 0; }
+  const int coord[3] = {x, y, z};
+  const size_t stride[3] = {1, (size_t)a.nx, (size_t)a.nx * a.ny};
+#pragma unroll
+  for (int ax = 0; ax < 3; ++ax) {
+    if (a.nax[ax] == 1) continue;
+    const int n = a.nax[ax];
+    T mm[3], mp[3];
+    // edge-condition derivative (D/2A)(z x n) x m, applied on x and y only
+    T ev[3] = {0, 0, 0};
+    if (ax == 0) { ev[0] = mc[2]; ev[2] = -mc[0]; }
+    if (ax == 1) { ev[1] = mc[2]; ev[2] = -mc[1]; }
+    const T g = (ax < 2) ? a.hd[ax] * kbc : T(0);
+    if (coord[ax] > 0) ld3(m, rb, a.N, cell - stride[ax], mm);
+    else if (a.pbc[ax]) ld3(m, rb, a.N, cell + (size_t)(n - 1) * stride[ax], mm);
+    else { for (int c = 0; c < 3; ++c) mm[c] = mc[c] - g * ev[c]; }
+    if (coord[ax] < n - 1) ld3(m, rb, a.N, cell + stride[ax], mp);
+    else if (a.pbc[ax]) ld3(m, rb, a.N, cell - (size_t)(n - 1) * stride[ax], mp);
+    else { for (int c = 0; c < 3; ++c) mp[c] = mc[c] + g * ev[c]; }
+    if (a.terms & T_EXCH) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Hex[c] += a.cex * a.idd2[ax] * (mm[c] + mp[c] - T(2) * mc[c]);
+    }
+    if ((a.terms & T_DMI) && ax < 2) {
+      const T d_ax = (mp[ax] - mm[ax]) * a.ih2[ax];
+      const T d_z = (mp[2] - mm[2]) * a.ih2[ax];
+      Hdm[ax] += a.cdmi * d_z;
+      Hdm[2] -= a.cdmi * d_ax;
+    }
+  }
+  if (a.terms & T_ANIS) {
+    const T mu = mc[0] * a.u[0] + mc[1] * a.u[1] + mc[2] * a.u[2];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Han[c] = a.can * mu * a.u[c];
+  }
+  if (a.terms & T_ZEEMAN) { Hz[0] = a.hz[0]; Hz[1] = a.hz[1]; Hz[2] = a.hz[2]; }
+}
+
+// LLG torque -gamma' mu0 [m x H + alpha m x (m x H)]
+template <typename T>
+__device__ inline void llg_torque(const T mc[3], const T H[3], T gpm, T alpha, T k[3]) {
+  const T cx = mc[1] * H[2] - mc[2] * H[1];
+  const T cy = mc[2] * H[0] - mc[0] * H[2];
+  const T cz = mc[0] * H[1] - mc[1] * H[0];
+  const T dx = mc[1] * cz - mc[2] * cy;
+  const T dy = mc[2] * cx - mc[0] * cz;
+  const T dz = mc[0] * cy - mc[1] * cx;
+  k[0] = -gpm * (cx + alpha * dx);
+  k[1] = -gpm * (cy + alpha * dy);
+  k[2] = -gpm * (cz + alpha * dz);
+}
+
 template <typename T, int MODE>
 __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
   if (MODE != FM_ENERGY && a.done && *a.done) return;
@@ -339,6 +412,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
   const bool demag = (a.terms & T_DEMAG) != 0;
   const T* Hd = nullptr;  // real view of the inverse transform, line stride 2 hx
   if (demag) {
+    const cpx<T>* tw = stage_table(Bf + nl * hx, a.tw, hx);
     const int Kx = a.Kx;
     for (int t = threadIdx.x; t < nl * hx; t += blockDim.x) {
       const int line = t / hx, k = t - line * hx;
@@ -362,7 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       A[line * hx + k] = Z;
     }
     __syncthreads();
-    Hd = reinterpret_cast<const T*>(lds_fft<T, true>(A, Bf, nl, a.plan, a.tw));
+    Hd = reinterpret_cast<const T*>(lds_fft<T, true>(A, Bf, nl, a.plan, tw));
   }
   const int ncell_blk = L * a.nx;
   const double dt_state = a.dtdev ? *a.dtdev : a.dth;
@@ -380,44 +454,8 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
     const size_t cell = (size_t)x + (size_t)a.nx * (y + (size_t)a.ny * z);
     T mc[3];
     ld3(a.m, rb, a.N, cell, mc);
-    T Hex[3] = {0, 0, 0}, Hdm[3] = {0, 0, 0};
-    const int coord[3] = {x, y, z};
-    const size_t stride[3] = {1, (size_t)a.nx, (size_t)a.nx * a.ny};
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-      if (a.nax[ax] == 1) continue;
-      const int n = a.nax[ax];
-      T mm[3], mp[3];
-      // edge-condition derivative (D/2A)(z x n) x m, applied on x and y only
-      T ev[3] = {0, 0, 0};
-      if (ax == 0) { ev[0] = mc[2]; ev[2] = -mc[0]; }
-      if (ax == 1) { ev[1] = mc[2]; ev[2] = -mc[1]; }
-      const T g = (ax < 2) ? a.hd[ax] * kbc : T(0);
-      if (coord[ax] > 0) ld3(a.m, rb, a.N, cell - stride[ax], mm);
-      else if (a.pbc[ax]) ld3(a.m, rb, a.N, cell + (size_t)(n - 1) * stride[ax], mm);
-      else { for (int c = 0; c < 3; ++c) mm[c] = mc[c] - g * ev[c]; }
-      if (coord[ax] < n - 1) ld3(a.m, rb, a.N, cell + stride[ax], mp);
-      else if (a.pbc[ax]) ld3(a.m, rb, a.N, cell - (size_t)(n - 1) * stride[ax], mp);
-      else { for (int c = 0; c < 3; ++c) mp[c] = mc[c] + g * ev[c]; }
-      if (a.terms & T_EXCH) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) Hex[c] += a.cex * a.idd2[ax] * (mm[c] + mp[c] - T(2) * mc[c]);
-      }
-      if ((a.terms & T_DMI) && ax < 2) {
-        const T d_ax = (mp[ax] - mm[ax]) * a.ih2[ax];
-        const T d_z = (mp[2] - mm[2]) * a.ih2[ax];
-        Hdm[ax] += a.cdmi * d_z;
-        Hdm[2] -= a.cdmi * d_ax;
-      }
-    }
-    T Han[3] = {0, 0, 0};
-    if (a.terms & T_ANIS) {
-      const T mu = mc[0] * a.u[0] + mc[1] * a.u[1] + mc[2] * a.u[2];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) Han[c] = a.can * mu * a.u[c];
-    }
-    T Hz[3] = {0, 0, 0};
-    if (a.terms & T_ZEEMAN) { Hz[0] = a.hz[0]; Hz[1] = a.hz[1]; Hz[2] = a.hz[2]; }
+    T Hex[3], Hdm[3], Han[3], Hz[3];
+    local_terms(a, a.m, rb, cell, x, y, z, mc, kbc, Hex, Hdm, Han, Hz);
     T Hdd[3] = {0, 0, 0};
     if (demag) {
 #pragma unroll
@@ -445,15 +483,8 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       for (int c = 0; c < 3; ++c) a.out[rb + (size_t)c * a.N + cell] = H[c];
       continue;
     }
-    // LLG torque
-    const T cx = mc[1] * H[2] - mc[2] * H[1];
-    const T cy = mc[2] * H[0] - mc[0] * H[2];
-    const T cz = mc[0] * H[1] - mc[1] * H[0];
-    const T dx = mc[1] * cz - mc[2] * cy;
-    const T dy = mc[2] * cx - mc[0] * cz;
-    const T dz = mc[0] * cy - mc[1] * cx;
-    T k[3] = {-a.gpm * (cx + a.alpha * dx), -a.gpm * (cy + a.alpha * dy),
-              -a.gpm * (cz + a.alpha * dz)};
+    T k[3];
+    llg_torque(mc, H, a.gpm, a.alpha, k);
     if (MODE == FM_TORQUE || MODE == FM_RKK) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) a.out[rb + (size_t)c * a.N + cell] = k[c];

@@ -11,6 +11,7 @@
 
 #include "../../include/mmx.h"
 #include "common.h"
+#include "fused.h"
 #include "kernels.h"
 #include "setup_kernels.h"
 
@@ -133,12 +134,84 @@ struct Group {
   DevBuf tw_x, wpost, tw_y, tw_z, Nt, S, ms, m7, k[7], Trep, seeds, partial, E;
   int nblk = 1;  // k_fields workgroups per replica
   int demag_built = 0;
+  int fused_faster = 0;  // set by mmx_autotune when the replica-resident path timed faster
+};
+
+// Opt-in per-kernel timing with HIP events recorded on the bound stream
+// around every launch (mmx_profile_enable / mmx_profile_get).
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec {
+    int id;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<std::string> names;
+  std::vector<double> ms;
+  std::vector<long long> cnt;
+  hipStream_t stream = nullptr;
+  int id_of(const char* n) {
+    for (size_t i = 0; i < names.size(); ++i)
+      if (names[i] == n) return (int)i;
+    names.emplace_back(n);
+    ms.push_back(0.0);
+    cnt.push_back(0);
+    return (int)names.size() - 1;
+  }
+  hipEvent_t ev() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  void flush() {
+    if (recs.empty()) return;
+    (void)hipStreamSynchronize(stream);
+    for (auto& r : recs) {
+      float t = 0.f;
+      (void)hipEventElapsedTime(&t, r.a, r.b);
+      ms[r.id] += t;
+      cnt[r.id] += 1;
+    }
+    recs.clear();
+    used = 0;
+  }
+  ~Prof() {
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+struct ProfScope {
+  Prof* p;
+  int id = -1;
+  hipEvent_t a = nullptr;
+  ProfScope(Prof& pr, const char* name, hipStream_t s) : p(&pr) {
+    if (!p->on) return;
+    if (p->recs.size() >= 4096) p->flush();
+    p->stream = s;
+    id = p->id_of(name);
+    a = p->ev();
+    (void)hipEventRecord(a, s);
+  }
+  ~ProfScope() {
+    if (id < 0) return;
+    hipEvent_t b = p->ev();
+    (void)hipEventRecord(b, p->stream);
+    p->recs.push_back({id, a, b});
+  }
 };
 
 }  // namespace
 
 struct mmx_ctx {
+  Prof prof;
   int prec = MMX_F32;
+  int path = MMX_PATH_AUTO;
+  size_t max_lds = 64 * 1024;  // dynamic LDS per workgroup on this device
   std::vector<std::unique_ptr<Group>> groups;
   uint32_t terms = MMX_EXCH | MMX_DMI_INTERFACIAL | MMX_ANIS_UNIAXIAL | MMX_ZEEMAN | MMX_DEMAG;
   hipStream_t stream = nullptr;
@@ -202,6 +275,14 @@ mmx_status setup_group(mmx_ctx* ctx, Group& G) {
   G.Wy = std::min(G.Wy, G.Kx);
   G.Wz = (int)std::max<size_t>(1, std::min<size_t>(16, budget / (6 * (size_t)G.Pz * cpxb<T>())));
   G.Wz = std::min(G.Wz, G.Kx);
+  // the smallest tiles must fit the LDS budget of one workgroup
+  if ((2 * 3 * (size_t)G.hx + 2 * G.hx + 1) * cpxb<T>() > 64 * 1024 ||
+      (2 * 3 * (size_t)G.Py + G.Py) * cpxb<T>() > 64 * 1024 ||
+      (2 * 3 * (size_t)G.Pz + G.Pz) * cpxb<T>() > 64 * 1024)
+    return fail(MMX_EUNSUP, "grid too long along one axis for this precision");
+  while (G.L > 1 && (2 * 3 * (size_t)G.L * G.hx + 2 * G.hx + 1) * cpxb<T>() > 64 * 1024) G.L /= 2;
+  while (G.Wy > 1 && (2 * 3 * (size_t)G.Wy * G.Py + G.Py) * cpxb<T>() > 64 * 1024) G.Wy /= 2;
+  while (G.Wz > 1 && (2 * 3 * (size_t)G.Wz * G.Pz + G.Pz) * cpxb<T>() > 64 * 1024) G.Wz /= 2;
   G.nblk = ((G.ny + G.L - 1) / G.L) * G.nz;
   // twiddles
   auto up = [&](DevBuf& b, const void* src, size_t bytes) -> mmx_status {
@@ -358,8 +439,12 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
 template <typename T>
 mmx_status launch_fields(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
   dim3 grid((G.ny + G.L - 1) / G.L, G.nz, G.R);
-  const size_t lds = (a.terms & T_DEMAG) ? 2 * (size_t)3 * G.L * G.hx * cpxb<T>() : 0;
+  const size_t lds = (a.terms & T_DEMAG) ? (2 * (size_t)3 * G.L * G.hx + G.hx) * cpxb<T>() : 0;
   hipStream_t s = ctx->stream;
+  static const char* kname[] = {"k_fields_field", "k_fields_torque", "k_fields_heun1",
+                                 "k_fields_heun2", "k_fields_rkk", "k_fields_rk7",
+                                 "k_fields_energy"};
+  ProfScope ps(ctx->prof, kname[mode], s);
   switch (mode) {
     case FM_FIELD: k_fields<T, FM_FIELD><<<grid, kBlock, lds, s>>>(a); break;
     case FM_TORQUE: k_fields<T, FM_TORQUE><<<grid, kBlock, lds, s>>>(a); break;
@@ -405,7 +490,8 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
     x.L = G.L; x.xone = G.xone;
     x.done = done;
     dim3 grid((G.ny + G.L - 1) / G.L, G.nz, G.R);
-    const size_t lds = demag ? 2 * (size_t)3 * G.L * G.hx * cpxb<T>() : 0;
+    const size_t lds = demag ? (2 * (size_t)3 * G.L * G.hx + 2 * G.hx + 1) * cpxb<T>() : 0;
+    ProfScope ps(ctx->prof, demag ? "k_xfwd" : "k_combine", s);
     k_xfwd<T><<<grid, kBlock, lds, s>>>(x);
     HIP_TRY(hipGetLastError());
     if (cb.mout) mfield = reinterpret_cast<const T*>(cb.mout);
@@ -424,7 +510,8 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
       y.pf = G.plan_yf;
       y.pi = G.plan_yi;
       dim3 grid((G.Kx + G.Wy - 1) / G.Wy, 1, G.R);
-      k_yconv<T><<<grid, kBlock, 2 * (size_t)3 * G.Wy * G.Py * cpxb<T>(), s>>>(y);
+      ProfScope ps(ctx->prof, "k_yconv", s);
+      k_yconv<T><<<grid, kBlock, (2 * (size_t)3 * G.Wy * G.Py + G.Py) * cpxb<T>(), s>>>(y);
       HIP_TRY(hipGetLastError());
     } else {
       y.W = G.Wy;
@@ -432,8 +519,11 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
       y.pf = G.plan_yf;
       y.pi = G.plan_yi;
       dim3 gy((G.Kx + G.Wy - 1) / G.Wy, G.nz, G.R);
-      const size_t ldy = 2 * (size_t)3 * G.Wy * G.Py * cpxb<T>();
-      k_ypass<T, false><<<gy, kBlock, ldy, s>>>(y);
+      const size_t ldy = (2 * (size_t)3 * G.Wy * G.Py + G.Py) * cpxb<T>();
+      {
+        ProfScope ps(ctx->prof, "k_ypass_fwd", s);
+        k_ypass<T, false><<<gy, kBlock, ldy, s>>>(y);
+      }
       HIP_TRY(hipGetLastError());
       YArgs<T> zz = y;
       zz.W = G.Wz;
@@ -441,9 +531,13 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
       zz.pf = G.plan_zf;
       zz.pi = G.plan_zi;
       dim3 gz((G.Kx + G.Wz - 1) / G.Wz, G.Py, G.R);
-      k_zconv<T><<<gz, kBlock, 2 * (size_t)3 * G.Wz * G.Pz * cpxb<T>(), s>>>(zz);
+      ProfScope psz(ctx->prof, "k_zconv", s);
+      k_zconv<T><<<gz, kBlock, (2 * (size_t)3 * G.Wz * G.Pz + G.Pz) * cpxb<T>(), s>>>(zz);
       HIP_TRY(hipGetLastError());
-      k_ypass<T, true><<<gy, kBlock, ldy, s>>>(y);
+      {
+        ProfScope ps(ctx->prof, "k_ypass_inv", s);
+        k_ypass<T, true><<<gy, kBlock, ldy, s>>>(y);
+      }
       HIP_TRY(hipGetLastError());
     }
   }
@@ -581,6 +675,7 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
         MMX_TRY(eval_group<T>(ctx, G, mb + G.off, cb, ep, 0, 1.0, dtdev, 0.0, done));
       }
     }
+    ProfScope psc(ctx->prof, "k_rk_controller", s);
     k_rk_controller<<<1, 1, 0, s>>>(st, replay ? ctx->replay.as<double>() : nullptr,
                                      ctx->dts.as<double>(), ctx->dts_cap);
     HIP_TRY(hipGetLastError());
@@ -588,6 +683,7 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
       Group& G = *gp;
       const size_t n = (size_t)G.R * 3 * G.N;
       const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+      ProfScope ps(ctx->prof, "k_rk_commit", s);
       k_rk_commit<T><<<nb, 256, 0, s>>>(st, mb + G.off, G.m7.as<T>(), G.k[0].as<T>(),
                                          G.k[6].as<T>(), n);
       HIP_TRY(hipGetLastError());
@@ -614,6 +710,73 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
   return MMX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// replica-resident Heun path (2-D films whose half spectrum fits in LDS)
+// ---------------------------------------------------------------------------
+struct FusedTiles {
+  int C = 0, W = 0, nch = 0;
+  size_t lds = 0;
+  bool ok = false;
+};
+
+template <typename T>
+FusedTiles fused_tiles(const mmx_ctx* ctx, const Group& G) {
+  FusedTiles ft;
+  if (G.nz != 1 || G.xone || G.nx > kFusedBlock) return ft;
+  int C = 1;
+  while (2 * C <= G.ny && 2 * C * G.nx <= kFusedBlock) C *= 2;
+  const int nch = (G.ny + C - 1) / C;
+  if (nch > kFusedMaxChunks) return ft;
+  int W = std::max(1, std::min(G.Kx, C * G.hx / G.Py));
+  const size_t scratch = std::max<size_t>((size_t)3 * C * G.hx, (size_t)3 * W * G.Py);
+  const size_t elems = (size_t)3 * G.ny * G.Kx + 2 * scratch + G.hx + (G.hx + 1) + G.Py;
+  ft.lds = elems * sizeof(cpx<T>);
+  if (ft.lds + kFusedBlock / 64 * sizeof(double) > ctx->max_lds) return ft;
+  ft.C = C;
+  ft.W = W;
+  ft.nch = nch;
+  ft.ok = true;
+  return ft;
+}
+
+template <typename T>
+mmx_status heun_fused(mmx_ctx* ctx, Group& G, const FusedTiles& ft, T* mg, double dt,
+                      int64_t n_steps, uint64_t step0, double* tsw) {
+  if ((ctx->terms & MMX_DEMAG) && !G.demag_built)
+    return fail(MMX_ESTATE, "mmx_build_demag has not been called");
+  HeunFusedArgs<T> a{};
+  a.f = field_args<T>(ctx, G, ctx->terms);
+  a.pxf = G.plan_x;
+  a.pxi = G.plan_xi;
+  a.pyf = G.plan_yf;
+  a.pyi = G.plan_yi;
+  a.tw_x = G.tw_x.as<cpx<T>>();
+  a.wpost = G.wpost.as<cpx<T>>();
+  a.tw_y = G.tw_y.as<cpx<T>>();
+  a.Nt = G.Nt.as<T>();
+  a.Ty = G.Ty;
+  a.Py = G.Py;
+  a.m = mg;
+  a.ms = G.ms.as<T>();
+  a.k1 = G.k[0].as<T>();
+  a.tsw = tsw;
+  a.dt = dt;
+  a.C = ft.C;
+  a.W = ft.W;
+  a.nch = ft.nch;
+  HIP_TRY(hipFuncSetAttribute((const void*)&k_heun_fused<T>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)ft.lds));
+  const int64_t per_launch = 64;  // steps per launch
+  for (int64_t s0 = 0; s0 < n_steps; s0 += per_launch) {
+    a.step0 = step0 + (uint64_t)s0;
+    a.nsteps = (int)std::min<int64_t>(per_launch, n_steps - s0);
+    ProfScope ps(ctx->prof, "k_heun_fused", ctx->stream);
+    k_heun_fused<T><<<G.R, kFusedBlock, ft.lds, ctx->stream>>>(a);
+    HIP_TRY(hipGetLastError());
+  }
+  return MMX_OK;
+}
+
 template <typename T>
 mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
                      void* tsw) {
@@ -622,11 +785,40 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
   hipStream_t s = ctx->stream;
   T* mb = reinterpret_cast<T*>(m);
   double* tsw_d = reinterpret_cast<double*>(tsw);
-  for (int64_t i = 0; i < n_steps; ++i) {
-    const uint64_t step = step0 + (uint64_t)i;
+  // groups on the replica-resident path advance all steps at once
+  std::vector<int> staged;
+  {
+    int roff = 0;
+    for (size_t gi = 0; gi < ctx->groups.size(); ++gi) {
+      Group& G = *ctx->groups[gi];
+      const FusedTiles ft = fused_tiles<T>(ctx, G);
+      if (ctx->path == MMX_PATH_FUSED && !ft.ok)
+        return fail(MMX_EUNSUP, "group does not fit the replica-resident path");
+      const bool use_fused = ft.ok && (ctx->path == MMX_PATH_FUSED ||
+                                       (ctx->path == MMX_PATH_AUTO && G.fused_faster));
+      if (use_fused) {
+        MMX_TRY(heun_fused<T>(ctx, G, ft, mb + G.off, dt, n_steps, step0,
+                              tsw_d ? tsw_d + roff : nullptr));
+      } else {
+        staged.push_back((int)gi);
+      }
+      roff += G.R;
+    }
+  }
+  if (staged.empty()) return MMX_OK;
+  std::vector<int> roffs;
+  {
     int roff = 0;
     for (auto& gp : ctx->groups) {
-      Group& G = *gp;
+      roffs.push_back(roff);
+      roff += gp->R;
+    }
+  }
+  for (int64_t i = 0; i < n_steps; ++i) {
+    const uint64_t step = step0 + (uint64_t)i;
+    for (int gi : staged) {
+      Group& G = *ctx->groups[gi];
+      const int roff = roffs[gi];
       T* mg = mb + G.off;
       Epilogue e1;
       e1.mode = FM_HEUN1;
@@ -640,11 +832,11 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       e2.mout = mg;
       MMX_TRY(eval_group<T>(ctx, G, G.ms.as<T>(), Combine{}, e2, step, dt, nullptr, dt, nullptr));
       if (tsw_d) {
+        ProfScope ps(ctx->prof, "k_switch_reduce", s);
         k_switch_reduce<<<(G.R + 63) / 64, 64, 0, s>>>(G.partial.as<double>(), G.nblk, G.R, G.N,
                                                         tsw_d + roff, (double)(step + 1) * dt);
         HIP_TRY(hipGetLastError());
       }
-      roff += G.R;
     }
   }
   return MMX_OK;
@@ -717,6 +909,138 @@ mmx_status check_ctx(const mmx_ctx* c) {
   return MMX_OK;
 }
 
+// ---------------------------------------------------------------------------
+// tiles: rows per x workgroup (L), spectrum columns per y / z workgroup
+// (Wy, Wz).  Every column and row is transformed by the same arithmetic
+// whatever the grouping, so results do not depend on the tiles.
+// ---------------------------------------------------------------------------
+constexpr size_t kMaxDynLds = 64 * 1024;
+
+template <typename T>
+size_t lds_x(const Group& G, int L) {
+  return (2 * 3 * (size_t)L * G.hx + 2 * G.hx + 1) * cpxb<T>();
+}
+template <typename T>
+size_t lds_col(int W, int P) {
+  return (2 * 3 * (size_t)W * P + P) * cpxb<T>();
+}
+
+template <typename T>
+mmx_status apply_tiles(Group& G, int L, int Wy, int Wz) {
+  if (L < 1 || L > G.ny || Wy < 1 || Wy > G.Kx || Wz < 1 || Wz > G.Kx)
+    return fail(MMX_EINVAL, "tile sizes out of range");
+  if (lds_x<T>(G, L) > kMaxDynLds || lds_col<T>(Wy, G.Py) > kMaxDynLds ||
+      lds_col<T>(Wz, G.Pz) > kMaxDynLds)
+    return fail(MMX_EINVAL, "tile sizes exceed the LDS budget");
+  G.L = L;
+  G.Wy = Wy;
+  G.Wz = Wz;
+  const int nblk = ((G.ny + G.L - 1) / G.L) * G.nz;
+  if ((size_t)G.R * nblk * 5 * sizeof(double) > G.partial.bytes)
+    HIP_TRY(G.partial.alloc((size_t)G.R * nblk * 5 * sizeof(double)));
+  G.nblk = nblk;
+  return MMX_OK;
+}
+
+template <typename T>
+mmx_status time_eval(mmx_ctx* ctx, Group& G, float& ms) {
+  hipEvent_t a, b;
+  HIP_TRY(hipEventCreate(&a));
+  HIP_TRY(hipEventCreate(&b));
+  Epilogue ep;
+  ep.mode = FM_FIELD;
+  ep.out = G.k[0].p;
+  mmx_status st = MMX_OK;
+  float best = 1e30f;
+  for (int rep = 0; rep < 3 && st == MMX_OK; ++rep) {
+    (void)hipEventRecord(a, ctx->stream);
+    st = eval_group<T>(ctx, G, G.ms.as<T>(), Combine{}, ep, 0, 1.0, nullptr, 0.0, nullptr,
+                       ctx->terms & ~MMX_THERMAL);
+    (void)hipEventRecord(b, ctx->stream);
+    (void)hipEventSynchronize(b);
+    float t = 0;
+    (void)hipEventElapsedTime(&t, a, b);
+    if (rep > 0) best = std::min(best, t);  // first repetition warms caches
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  ms = best;
+  return st;
+}
+
+template <typename T>
+mmx_status autotune_impl(mmx_ctx* ctx) {
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    if (!G.demag_built) continue;
+    HIP_TRY(hipMemsetAsync(G.ms.p, 0, G.ms.bytes, ctx->stream));
+    const int cand[] = {1, 2, 4, 8, 16, 32};
+    int bestL = G.L, bestW = G.Wy, bestWz = G.Wz;
+    float bt = 1e30f;
+    for (int L : cand) {
+      if (L > G.ny || lds_x<T>(G, L) > kMaxDynLds || (size_t)L * G.nx > 8 * kBlock) continue;
+      MMX_TRY(apply_tiles<T>(G, L, bestW, bestWz));
+      float t;
+      MMX_TRY(time_eval<T>(ctx, G, t));
+      if (t < bt) { bt = t; bestL = L; }
+    }
+    bt = 1e30f;
+    for (int W : cand) {
+      if (W > G.Kx || lds_col<T>(W, G.Py) > kMaxDynLds) continue;
+      MMX_TRY(apply_tiles<T>(G, bestL, W, bestWz));
+      float t;
+      MMX_TRY(time_eval<T>(ctx, G, t));
+      if (t < bt) { bt = t; bestW = W; }
+    }
+    if (G.is3d) {
+      bt = 1e30f;
+      for (int W : cand) {
+        if (W > G.Kx || lds_col<T>(W, G.Pz) > kMaxDynLds) continue;
+        MMX_TRY(apply_tiles<T>(G, bestL, bestW, W));
+        float t;
+        MMX_TRY(time_eval<T>(ctx, G, t));
+        if (t < bt) { bt = t; bestWz = W; }
+      }
+    }
+    MMX_TRY(apply_tiles<T>(G, bestL, bestW, bestWz));
+    // Heun path: one predictor-corrector step staged (two evaluations) against
+    // one replica-resident step, on a zeroed state (scratch buffer m7)
+    G.fused_faster = 0;
+    const FusedTiles ft = fused_tiles<T>(ctx, G);
+    if (ft.ok) {
+      MMX_TRY(ensure_rk_buffers<T>(G));
+      HIP_TRY(hipMemsetAsync(G.m7.p, 0, G.m7.bytes, ctx->stream));
+      float staged_ms = 0, fused_ms = 0;
+      MMX_TRY(time_eval<T>(ctx, G, staged_ms));
+      staged_ms *= 2.0f;
+      hipEvent_t a, b;
+      HIP_TRY(hipEventCreate(&a));
+      HIP_TRY(hipEventCreate(&b));
+      float best = 1e30f;
+      for (int rep = 0; rep < 3; ++rep) {
+        (void)hipEventRecord(a, ctx->stream);
+        mmx_status st = heun_fused<T>(ctx, G, ft, G.m7.as<T>(), 1e-15, 1, 0, nullptr);
+        (void)hipEventRecord(b, ctx->stream);
+        (void)hipEventSynchronize(b);
+        float t = 0;
+        (void)hipEventElapsedTime(&t, a, b);
+        if (st != MMX_OK) {
+          (void)hipEventDestroy(a);
+          (void)hipEventDestroy(b);
+          return st;
+        }
+        if (rep > 0) best = std::min(best, t);
+      }
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+      fused_ms = best;
+      G.fused_faster = fused_ms < staged_ms ? 1 : 0;
+    }
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return MMX_OK;
+}
+
 mmx_status check_group_idx(const mmx_ctx* c, int32_t g) {
   MMX_TRY(check_ctx(c));
   if (g < 0 || g >= (int)c->groups.size()) return fail(MMX_EINVAL, "group index out of range");
@@ -735,6 +1059,33 @@ extern "C" {
 
 const char* mmx_last_error(void) { return g_err.c_str(); }
 
+mmx_status mmx_profile_enable(mmx_ctx* ctx, int32_t on) {
+  MMX_TRY(check_ctx(ctx));
+  ctx->prof.flush();
+  if (on) {
+    for (auto& v : ctx->prof.ms) v = 0.0;
+    for (auto& c : ctx->prof.cnt) c = 0;
+  }
+  ctx->prof.on = on != 0;
+  return MMX_OK;
+}
+
+mmx_status mmx_profile_get(mmx_ctx* ctx, int32_t idx, char* name, int32_t name_cap,
+                           double* total_ms, int64_t* count, int32_t* n_kernels) {
+  MMX_TRY(check_ctx(ctx));
+  ctx->prof.flush();
+  if (n_kernels) *n_kernels = (int32_t)ctx->prof.names.size();
+  if (idx < 0) return MMX_OK;
+  if (idx >= (int)ctx->prof.names.size()) return fail(MMX_EINVAL, "kernel index out of range");
+  if (name && name_cap > 0) {
+    std::strncpy(name, ctx->prof.names[idx].c_str(), name_cap - 1);
+    name[name_cap - 1] = 0;
+  }
+  if (total_ms) *total_ms = ctx->prof.ms[idx];
+  if (count) *count = ctx->prof.cnt[idx];
+  return MMX_OK;
+}
+
 mmx_status mmx_create(const mmx_group* groups, int32_t n_groups, mmx_prec prec, mmx_ctx** out) {
   if (!out) return fail(MMX_EINVAL, "out is null");
   *out = nullptr;
@@ -749,6 +1100,7 @@ mmx_status mmx_create(const mmx_group* groups, int32_t n_groups, mmx_prec prec, 
     return fail(MMX_EUNSUP, std::string("libmmx is built for gfx950, device is ") + prop.gcnArchName);
   auto ctx = std::make_unique<mmx_ctx>();
   ctx->prec = prec;
+  ctx->max_lds = prop.sharedMemPerBlock;
   size_t off = 0;
   for (int i = 0; i < n_groups; ++i) {
     auto G = std::make_unique<Group>();
@@ -892,6 +1244,39 @@ mmx_status mmx_topological_charge(mmx_ctx* ctx, const void* m, void* Q) {
   MMX_TRY(check_ctx(ctx));
   if (!m || !Q) return fail(MMX_EINVAL, "null array");
   return ctx->prec == MMX_F64 ? topo_impl<double>(ctx, m, Q) : topo_impl<float>(ctx, m, Q);
+}
+
+mmx_status mmx_set_tiles(mmx_ctx* ctx, int32_t group, const int32_t tiles[3]) {
+  MMX_TRY(check_group_idx(ctx, group));
+  if (!tiles) return fail(MMX_EINVAL, "tiles is null");
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  Group& G = *ctx->groups[group];
+  return ctx->prec == MMX_F64 ? apply_tiles<double>(G, tiles[0], tiles[1], tiles[2])
+                              : apply_tiles<float>(G, tiles[0], tiles[1], tiles[2]);
+}
+
+mmx_status mmx_get_tiles(mmx_ctx* ctx, int32_t group, int32_t tiles[3]) {
+  MMX_TRY(check_group_idx(ctx, group));
+  if (!tiles) return fail(MMX_EINVAL, "tiles is null");
+  const Group& G = *ctx->groups[group];
+  tiles[0] = G.L;
+  tiles[1] = G.Wy;
+  tiles[2] = G.Wz;
+  return MMX_OK;
+}
+
+mmx_status mmx_set_path(mmx_ctx* ctx, int32_t path) {
+  MMX_TRY(check_ctx(ctx));
+  if (path != MMX_PATH_AUTO && path != MMX_PATH_STAGED && path != MMX_PATH_FUSED)
+    return fail(MMX_EINVAL, "unknown path");
+  ctx->path = path;
+  return MMX_OK;
+}
+
+mmx_status mmx_autotune(mmx_ctx* ctx) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  return ctx->prec == MMX_F64 ? autotune_impl<double>(ctx) : autotune_impl<float>(ctx);
 }
 
 }  // extern "C"

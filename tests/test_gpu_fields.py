@@ -102,3 +102,36 @@ def test_thermal_field_matches_oracle_philox(prec):
             assert err <= (1e-12 if prec == 2 else 2e-6), (step, err)
     finally:
         mmx.mmx_destroy(ctx)
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("name", ["film_open_32x32", "block_open_6x5x3", "film_96x24x2_radix3"])
+def test_tile_choice_does_not_change_results(name, prec):
+    """Rows per x workgroup and columns per y/z workgroup only regroup
+    independent transforms: the field must be bit-identical for every tile
+    choice, including the autotuner's."""
+    import paper_2608_15253_amd as mmx
+    case = CASES[name]
+    m0 = _mm(case, seed=5)
+    ctx = open_ctx(case, prec)
+    try:
+        md = dev(m0, prec)
+        H = dev(np.zeros_like(m0), prec)
+        mmx.mmx_field(ctx, md, H)
+        ref = host(H)
+        ny, Kx = case.n[1], case.n[0] + 1
+        for tiles in [(1, 1, 1), (min(2, ny), min(3, Kx), 2), (ny, min(16, Kx), 1)]:
+            try:
+                mmx.mmx_set_tiles(ctx, 0, tiles)
+            except mmx.MMXError:
+                continue  # over the LDS budget for this precision
+            assert mmx.mmx_get_tiles(ctx, 0) == tuple(tiles)
+            mmx.mmx_field(ctx, md, H)
+            assert np.array_equal(host(H), ref), tiles
+        mmx.mmx_autotune(ctx)
+        mmx.mmx_field(ctx, md, H)
+        assert np.array_equal(host(H), ref), mmx.mmx_get_tiles(ctx, 0)
+        with pytest.raises(mmx.MMXError):
+            mmx.mmx_set_tiles(ctx, 0, (0, 1, 1))
+    finally:
+        mmx.mmx_destroy(ctx)

@@ -180,3 +180,61 @@ def test_energy_and_charge_match_oracle(prec):
         q = oob.topological_charge(m0[r], case.grid)
         assert abs(gq[r] - q) <= 1e-12 * max(1.0, abs(q)) * (1 if prec == 2 else 1e5)
     assert abs(gq[0] + 2) < 0.1
+
+
+FUSED_CASES = {
+    "thermal_64x64": Case((64, 64, 1), (4e-9, 4e-9, 4e-9), R=3, alpha=0.02, Ku=5e5,
+                          B=(0, 0, -0.15), T=300.0, seeds=list(replica_seeds(3, 3)),
+                          terms=("exchange", "anisotropy", "zeeman", "demag", "thermal")),
+    "dmi_periodic_32x24": Case((32, 24, 1), (2e-9, 2e-9, 0.6e-9), pbc=(1, 1, 0),
+                               images=(2, 2, 0), R=2, Ms=5.8e5, A=1.5e-11, D=3e-3,
+                               Ku=0.8e6, alpha=0.05, B=(0, 0, 0.1), T=100.0,
+                               seeds=list(replica_seeds(4, 2)),
+                               terms=("exchange", "dmi", "anisotropy", "zeeman", "demag",
+                                      "thermal")),
+    "dmi_open_30x18": Case((30, 18, 1), (4e-9, 4e-9, 4e-9), R=2, Ms=5.8e5, A=1.5e-11,
+                           D=3e-3, Ku=0.8e6, alpha=0.05, B=(0, 0, 0.1), T=100.0,
+                           seeds=list(replica_seeds(5, 2)),
+                           terms=("exchange", "dmi", "anisotropy", "zeeman", "demag", "thermal")),
+    "ragged_20x12": Case((20, 12, 1), (3e-9, 2e-9, 1e-9), R=1, Ku=3e5, alpha=0.1,
+                         terms=("exchange", "anisotropy", "demag")),
+    "wide_128x32": Case((128, 32, 1), (4e-9, 4e-9, 4e-9), R=2, alpha=0.05, Ku=2e5,
+                        B=(0, 0, 0.1), T=100.0, seeds=list(replica_seeds(6, 2)),
+                        terms=("exchange", "anisotropy", "zeeman", "demag", "thermal")),
+}
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("name", list(FUSED_CASES))
+def test_fused_path_matches_staged_and_oracle(name, prec):
+    """The replica-resident path runs the same per-line arithmetic as the
+    three-kernel path: states agree to round-off (bit-identical expected), and
+    both match the oracle."""
+    import paper_2608_15253_amd as mmx
+    case = FUSED_CASES[name]
+    print(f"[case] fused {name} prec={prec}", flush=True)
+    m0 = _round(random_unit(case.n, seed=12, replicas=case.R), prec)
+    nsteps = 12
+    out = {}
+    for path in (mmx.MMX_PATH_STAGED, mmx.MMX_PATH_FUSED):
+        ctx = open_ctx(case, prec)
+        try:
+            mmx.mmx_set_path(ctx, path)
+            md = dev(m0, prec)
+            ts = dev(-np.ones(case.R), 2)
+            try:
+                mmx.mmx_heun(ctx, md, 2e-14, nsteps, 7, ts)
+            except mmx.MMXError as e:
+                if path == mmx.MMX_PATH_FUSED and e.status == -5:
+                    pytest.skip("half spectrum does not fit LDS at this precision")
+                raise
+            out[path] = (host(md), host(ts))
+        finally:
+            mmx.mmx_destroy(ctx)
+    st, fu = out[mmx.MMX_PATH_STAGED][0], out[mmx.MMX_PATH_FUSED][0]
+    d = np.abs(st - fu).max()
+    print(f"staged vs fused max |dm| = {d:.3e} (bitwise: {np.array_equal(st, fu)})")
+    assert d <= (1e-14 if prec == 2 else 1e-6)
+    seeds = np.array(case.seeds) if case.seeds else 0
+    ref = oit.heun_run(m0, case.grid, case.material(), 2e-14, nsteps, seed=seeds, step0=7)
+    assert np.abs(fu - ref).max() <= TOLM[prec]
