@@ -5,14 +5,22 @@
 // inputs of a butterfly at stride n/R, applies the Stockham twiddles
 // exp(-+2 pi i r (j mod Ns) / (Ns R)), transforms them with a small DFT and
 // writes them to the autosorted position (j / Ns) Ns R + (j mod Ns) + r Ns of
-// the other buffer; Ns grows by R per pass, so mixed radices 2, 3, 4, 5 and 8
-// combine in any order and the output is in natural order.  A pruned first
+// the other buffer; Ns grows by R per pass, so mixed radices 2, 3, 4, 5, 8 and
+// 16 combine in any order and the output is in natural order.  A pruned first
 // pass (radix 2, input zero beyond n/2, as in the zero-padded demag
 // convolution) reduces to duplicating its input.  Transforms are unnormalised.
 #pragma once
 #include "common.h"
 
 namespace mmx {
+
+// a / d and a % d with shifts when the (uniform) divisor is a power of two
+__device__ inline int udiv(int a, int d) {
+  return ((d & (d - 1)) == 0) ? (a >> __builtin_ctz(d)) : a / d;
+}
+__device__ inline int umod(int a, int d) {
+  return ((d & (d - 1)) == 0) ? (a & (d - 1)) : a % d;
+}
 
 template <typename T, bool INV>
 struct Dft {
@@ -91,6 +99,34 @@ struct Dft {
     v[0] = e[0]; v[2] = e[1]; v[4] = e[2]; v[6] = e[3];
     v[1] = o[0]; v[3] = o[1]; v[5] = o[2]; v[7] = o[3];
   }
+  // 16-point DFT as 4 x 4: DFT4 over n1 of x[4 n1 + n2], twiddle w16^(n2 k1),
+  // DFT4 over n2; output index k1 + 4 k2.
+  static __device__ inline void r16(cpx<T>* v) {
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+    const T h = T(0.70710678118654752440);
+    // w16^j = cos(2 pi j / 16) -/+ i sin(2 pi j / 16) for j = 0..9
+    const T wc[10] = {T(1), c1, h, s1, T(0), -s1, -h, -c1, T(-1), -c1};
+    const T ws[10] = {T(0), s1, h, c1, T(1), c1, h, s1, T(0), -s1};
+    cpx<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cpx<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      r4(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) {
+        const int j = n2 * k1;
+        const cpx<T> w = {wc[j], INV ? ws[j] : -ws[j]};
+        a[n2][k1] = (j == 0) ? t[k1] : cmul(t[k1], w);
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cpx<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      r4(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
+  }
 };
 
 template <typename T, bool INV, int R>
@@ -125,6 +161,7 @@ __device__ inline void stockham_pass(const cpx<T>* __restrict__ src, cpx<T>* __r
     if constexpr (R == 4) Dft<T, INV>::r4(v);
     if constexpr (R == 5) Dft<T, INV>::r5(v);
     if constexpr (R == 8) Dft<T, INV>::r8(v);
+    if constexpr (R == 16) Dft<T, INV>::r16(v);
     const int idxD = jq * Ns * R + jm;
 #pragma unroll
     for (int r = 0; r < R; ++r) d[idxD + r * Ns] = v[r];
@@ -146,7 +183,7 @@ __device__ cpx<T>* lds_fft(cpx<T>* a, cpx<T>* b, int nlines, const FftPlan& p,
       const int half = n / 2;
       const int total = half * nlines;
       for (int t = tid; t < total; t += nthr) {
-        const int line = t / half;
+        const int line = udiv(t, half);
         const int j = t - line * half;
         const cpx<T> v = a[line * n + j];
         b[line * n + 2 * j] = v;
@@ -158,7 +195,8 @@ __device__ cpx<T>* lds_fft(cpx<T>* a, cpx<T>* b, int nlines, const FftPlan& p,
         case 3: stockham_pass<T, INV, 3>(a, b, n, Ns, nlines, tw, tid, nthr); break;
         case 4: stockham_pass<T, INV, 4>(a, b, n, Ns, nlines, tw, tid, nthr); break;
         case 5: stockham_pass<T, INV, 5>(a, b, n, Ns, nlines, tw, tid, nthr); break;
-        default: stockham_pass<T, INV, 8>(a, b, n, Ns, nlines, tw, tid, nthr); break;
+        case 8: stockham_pass<T, INV, 8>(a, b, n, Ns, nlines, tw, tid, nthr); break;
+        default: stockham_pass<T, INV, 16>(a, b, n, Ns, nlines, tw, tid, nthr); break;
       }
     }
     __syncthreads();

@@ -36,6 +36,7 @@ struct HeunFusedArgs {
   double* tsw;          // switching times or null
   double dt;
   uint64_t step0;
+  const unsigned long long* stepdev;  // if set, step0 is read here (graph replays)
   int nsteps;
   int C;                // grid rows per x chunk
   int W;                // spectrum columns per y chunk
@@ -57,7 +58,7 @@ __device__ inline void fused_forward(const HeunFusedArgs<T>& a, const T* __restr
   for (int q = 0; q < a.nch; ++q) {
     const int y0 = q * C;
     for (int t = threadIdx.x; t < C * hx; t += blockDim.x) {
-      const int l = t / hx, k = t - l * hx, y = y0 + l;
+      const int l = udiv(t, hx), k = t - l * hx, y = y0 + l;
       cpx<T> v[3] = {{0, 0}, {0, 0}, {0, 0}};
       if (y < ny && k < npair) {
 #pragma unroll
@@ -79,7 +80,7 @@ __device__ inline void fused_forward(const HeunFusedArgs<T>& a, const T* __restr
     const cpx<T>* Z = lds_fft<T, false>(A, Bf, 3 * C, a.pxf, twx);
     for (int t = threadIdx.x; t < 3 * C * Kx; t += blockDim.x) {
       const int line = t / Kx, kx = t - line * Kx;
-      const int c = line / C, l = line - c * C, y = y0 + l;
+      const int c = udiv(line, C), l = line - c * C, y = y0 + l;
       if (y >= ny) continue;
       const cpx<T> Zk = Z[line * hx + (kx == hx ? 0 : kx)];
       cpx<T> Zc = Z[line * hx + (kx == 0 ? 0 : hx - kx)];
@@ -97,7 +98,7 @@ __device__ inline void fused_forward(const HeunFusedArgs<T>& a, const T* __restr
   const size_t cs = (size_t)a.Ty * Kx;
   for (int kx0 = 0; kx0 < Kx; kx0 += W) {
     for (int t = threadIdx.x; t < 3 * W * Py; t += blockDim.x) {
-      const int w = t % W, rest = t / W, y = rest % Py, c = rest / Py;
+      const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, Py), c = udiv(rest, Py);
       cpx<T> v = {0, 0};
       if (y < ny && kx0 + w < Kx) v = X[((size_t)c * ny + y) * Kx + kx0 + w];
       A[(c * W + w) * Py + y] = v;
@@ -106,7 +107,7 @@ __device__ inline void fused_forward(const HeunFusedArgs<T>& a, const T* __restr
     cpx<T>* Y = lds_fft<T, false>(A, Bf, 3 * W, a.pyf, twy);
     cpx<T>* scratch = (Y == A) ? Bf : A;
     for (int t = threadIdx.x; t < W * Py; t += blockDim.x) {
-      const int w = t % W, ky = t / W, kx = kx0 + w;
+      const int w = umod(t, W), ky = udiv(t, W), kx = kx0 + w;
       if (kx >= Kx) continue;
       const bool lo = 2 * ky <= Py;
       const int ty = lo ? ky : Py - ky;
@@ -117,7 +118,7 @@ __device__ inline void fused_forward(const HeunFusedArgs<T>& a, const T* __restr
     __syncthreads();
     const cpx<T>* Yi = lds_fft<T, true>(Y, scratch, 3 * W, a.pyi, twy);
     for (int t = threadIdx.x; t < 3 * W * ny; t += blockDim.x) {
-      const int w = t % W, rest = t / W, y = rest % ny, c = rest / ny;
+      const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, ny), c = udiv(rest, ny);
       if (kx0 + w < Kx) X[((size_t)c * ny + y) * Kx + kx0 + w] = Yi[(c * W + w) * Py + y];
     }
     __syncthreads();
@@ -134,8 +135,8 @@ __device__ inline const T* fused_inverse_chunk(const HeunFusedArgs<T>& a, int q,
   const int hx = f.hx, Kx = f.Kx, ny = f.ny, C = a.C;
   const int y0 = q * C;
   for (int t = threadIdx.x; t < 3 * C * hx; t += blockDim.x) {
-    const int line = t / hx, k = t - line * hx;
-    const int c = line / C, l = line - c * C, y = y0 + l;
+    const int line = udiv(t, hx), k = t - line * hx;
+    const int c = udiv(line, C), l = line - c * C, y = y0 + l;
     cpx<T> Zv = {0, 0};
     if (y < ny) {
       const cpx<T>* row = X + ((size_t)c * ny + y) * Kx;
@@ -184,7 +185,7 @@ __global__ void __launch_bounds__(kFusedBlock) k_heun_fused(HeunFusedArgs<T> a) 
   const int l = t / nx, x = t - (t / nx) * nx;
   const bool active_col = t < C * nx;
   for (int s = 0; s < a.nsteps; ++s) {
-    const uint64_t step = a.step0 + (uint64_t)s;
+    const uint64_t step = (a.stepdev ? *a.stepdev : a.step0) + (uint64_t)s;
     double mz_acc = 0.0;
     for (int stage = 0; stage < 2; ++stage) {
       // predictor: fields at m; corrector: fields at the predictor state ms

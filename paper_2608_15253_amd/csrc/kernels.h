@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
   const T dt = a.dtdev ? (T)(*a.dtdev) : (T)a.dth;
   const int npair = a.xone ? 1 : (a.nx + 1) / 2;
   for (int t = threadIdx.x; t < L * hx; t += blockDim.x) {
-    const int l = t / hx, k = t - l * hx, y = y0 + l;
+    const int l = udiv(t, hx), k = t - l * hx, y = y0 + l;
     cpx<T> v[3] = {{0, 0}, {0, 0}, {0, 0}};
     if (y < a.ny && k < npair) {
 #pragma unroll
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
   const int Kx = a.Kx;
   for (int t = threadIdx.x; t < nl * Kx; t += blockDim.x) {
     const int line = t / Kx, kx = t - line * Kx;
-    const int c = line / L, l = line - c * L, y = y0 + l;
+    const int c = udiv(line, L), l = line - c * L, y = y0 + l;
     if (y >= a.ny) continue;
     cpx<T> out;
     if (a.xone) {
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
   const int r = blockIdx.z, kx0 = blockIdx.x * W;
   const size_t rbase = (size_t)r * 3;
   for (int t = threadIdx.x; t < nl * Py; t += blockDim.x) {
-    const int w = t % W, rest = t / W, y = rest % Py, c = rest / Py;
+    const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, Py), c = udiv(rest, Py);
     cpx<T> v = {0, 0};
     if (y < a.ny && kx0 + w < a.Kx)
       v = a.S[(((rbase + c) * a.nz) * a.Sy + y) * a.Kx + kx0 + w];
@@ -199,7 +199,7 @@ __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
   cpx<T>* scratch = (X == A) ? Bf : A;
   const size_t cs = (size_t)a.Tz * a.Ty * a.Kx;
   for (int t = threadIdx.x; t < W * Py; t += blockDim.x) {
-    const int w = t % W, ky = t / W, kx = kx0 + w;
+    const int w = umod(t, W), ky = udiv(t, W), kx = kx0 + w;
     if (kx >= a.Kx) continue;
     const bool lo = 2 * ky <= Py;
     const int ty = lo ? ky : Py - ky;
@@ -212,7 +212,7 @@ __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
   __syncthreads();
   const cpx<T>* Y = lds_fft<T, true>(X, scratch, nl, a.pi, tw);
   for (int t = threadIdx.x; t < nl * a.ny; t += blockDim.x) {
-    const int w = t % W, rest = t / W, y = rest % a.ny, c = rest / a.ny;
+    const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, a.ny), c = udiv(rest, a.ny);
     if (kx0 + w < a.Kx)
       a.S[(((rbase + c) * a.nz) * a.Sy + y) * a.Kx + kx0 + w] = Y[(c * W + w) * Py + y];
   }
@@ -233,7 +233,7 @@ __global__ void __launch_bounds__(kBlock) k_ypass(YArgs<T> a) {
   const size_t rbase = (size_t)r * 3;
   const int nin = INV ? Py : a.ny;
   for (int t = threadIdx.x; t < nl * Py; t += blockDim.x) {
-    const int w = t % W, rest = t / W, y = rest % Py, c = rest / Py;
+    const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, Py), c = udiv(rest, Py);
     cpx<T> v = {0, 0};
     if (y < nin && kx0 + w < a.Kx)
       v = a.S[(((rbase + c) * a.nz + z) * a.Sy + y) * a.Kx + kx0 + w];
@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(kBlock) k_ypass(YArgs<T> a) {
   const cpx<T>* Y = lds_fft<T, INV>(A, Bf, nl, INV ? a.pi : a.pf, tw);
   const int nout = INV ? a.ny : Py;
   for (int t = threadIdx.x; t < nl * nout; t += blockDim.x) {
-    const int w = t % W, rest = t / W, y = rest % nout, c = rest / nout;
+    const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, nout), c = udiv(rest, nout);
     if (kx0 + w < a.Kx)
       a.S[(((rbase + c) * a.nz + z) * a.Sy + y) * a.Kx + kx0 + w] = Y[(c * W + w) * Py + y];
   }
@@ -261,7 +261,7 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
   const int r = blockIdx.z, ky = blockIdx.y, kx0 = blockIdx.x * W;
   const size_t rbase = (size_t)r * 3;
   for (int t = threadIdx.x; t < nl * Pz; t += blockDim.x) {
-    const int w = t % W, rest = t / W, z = rest % Pz, c = rest / Pz;
+    const int w = umod(t, W), rest = udiv(t, W), z = umod(rest, Pz), c = udiv(rest, Pz);
     cpx<T> v = {0, 0};
     if (z < a.nz && kx0 + w < a.Kx)
       v = a.S[(((rbase + c) * a.nz + z) * a.Sy + ky) * a.Kx + kx0 + w];
@@ -275,7 +275,7 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
   const int ty = ylo ? ky : a.Py - ky;
   const T sy = ylo ? T(1) : T(-1);
   for (int t = threadIdx.x; t < W * Pz; t += blockDim.x) {
-    const int w = t % W, kz = t / W, kx = kx0 + w;
+    const int w = umod(t, W), kz = udiv(t, W), kx = kx0 + w;
     if (kx >= a.Kx) continue;
     const bool zlo = 2 * kz <= Pz;
     const int tz = zlo ? kz : Pz - kz;
@@ -289,7 +289,7 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
   __syncthreads();
   const cpx<T>* Y = lds_fft<T, true>(X, scratch, nl, a.pi, tw);
   for (int t = threadIdx.x; t < nl * a.nz; t += blockDim.x) {
-    const int w = t % W, rest = t / W, z = rest % a.nz, c = rest / a.nz;
+    const int w = umod(t, W), rest = udiv(t, W), z = umod(rest, a.nz), c = udiv(rest, a.nz);
     if (kx0 + w < a.Kx)
       a.S[(((rbase + c) * a.nz + z) * a.Sy + ky) * a.Kx + kx0 + w] = Y[(c * W + w) * Pz + z];
   }
@@ -312,6 +312,7 @@ struct FArgs {
   const uint64_t* seeds;
   double sig2pref;  // 2 alpha kB / (mu0^2 Ms V gamma0); sigma^2 = sig2pref T / dt
   uint64_t step;
+  const unsigned long long* stepdev;  // if set, the step index is read here (graph replays)
   double dt_th;
   const T* m;
   const cpx<T>* S;
@@ -415,8 +416,8 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
     const cpx<T>* tw = stage_table(Bf + nl * hx, a.tw, hx);
     const int Kx = a.Kx;
     for (int t = threadIdx.x; t < nl * hx; t += blockDim.x) {
-      const int line = t / hx, k = t - line * hx;
-      const int c = line / L, l = line - c * L, y = y0 + l;
+      const int line = udiv(t, hx), k = t - line * hx;
+      const int c = udiv(line, L), l = line - c * L, y = y0 + l;
       cpx<T> Z = {0, 0};
       if (y < a.ny) {
         const cpx<T>* row = a.S + ((((size_t)r * 3 + c) * a.nz + z) * a.Sy + y) * Kx;
@@ -449,7 +450,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
   const T kbc = a.kbc;  // free-edge condition of the material's D (0 when D = 0)
   double acc[5] = {0, 0, 0, 0, 0};
   for (int t = threadIdx.x; t < ncell_blk; t += blockDim.x) {
-    const int l = t / a.nx, x = t - l * a.nx, y = y0 + l;
+    const int l = udiv(t, a.nx), x = t - l * a.nx, y = y0 + l;
     if (y >= a.ny) continue;
     const size_t cell = (size_t)x + (size_t)a.nx * (y + (size_t)a.ny * z);
     T mc[3];
@@ -474,7 +475,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
     for (int c = 0; c < 3; ++c) H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + Hdd[c];
     if (sigma != T(0)) {
       T eta[3];
-      thermal_eta<T>(a.seeds[r], (uint32_t)cell, a.step, eta);
+      thermal_eta<T>(a.seeds[r], (uint32_t)cell, a.stepdev ? *a.stepdev : a.step, eta);
 #pragma unroll
       for (int c = 0; c < 3; ++c) H[c] += sigma * eta[c];
     }

@@ -53,6 +53,8 @@ bool make_plan(int n, bool prune, FftPlan& p) {
     p.prune = 1;
     rest /= 2;
   }
+  // radix 4 first: measured faster on gfx950 than 8/16 for these lengths (the
+  // wider butterflies leave threads idle and write LDS with larger strides)
   while (rest % 4 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 4; rest /= 4; }
   while (rest % 2 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 2; rest /= 2; }
   while (rest % 3 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 3; rest /= 3; }
@@ -212,6 +214,19 @@ struct mmx_ctx {
   int prec = MMX_F32;
   int path = MMX_PATH_AUTO;
   size_t max_lds = 64 * 1024;  // dynamic LDS per workgroup on this device
+  // graph replay: library stream, fencing events, step counter, last graph
+  hipStream_t cap_stream = nullptr;
+  hipEvent_t ev_user = nullptr, ev_cap = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  DevBuf stepdev;
+  const unsigned long long* cur_stepdev = nullptr;
+  ~mmx_ctx() {
+    if (cap_stream) (void)hipStreamSynchronize(cap_stream);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (ev_user) (void)hipEventDestroy(ev_user);
+    if (ev_cap) (void)hipEventDestroy(ev_cap);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
+  }
   std::vector<std::unique_ptr<Group>> groups;
   uint32_t terms = MMX_EXCH | MMX_DMI_INTERFACIAL | MMX_ANIS_UNIAXIAL | MMX_ZEEMAN | MMX_DEMAG;
   hipStream_t stream = nullptr;
@@ -227,6 +242,8 @@ struct mmx_ctx {
 namespace {
 
 size_t esize(const mmx_ctx* c) { return c->prec == MMX_F64 ? 8 : 4; }
+
+mmx_status ensure_graph_stream(mmx_ctx* ctx);
 
 template <typename T>
 size_t cpxb() { return sizeof(cpx<T>); }
@@ -543,6 +560,7 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
   }
   // stage 3: inverse x transform + local fields + epilogue
   FArgs<T> a = field_args<T>(ctx, G, terms);
+  a.stepdev = ctx->cur_stepdev;
   a.m = mfield;
   a.step = step;
   a.dt_th = dt_th;
@@ -628,12 +646,12 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
       MMX_TRY(eval_group<T>(ctx, G, mb + G.off, Combine{}, ep, 0, 1.0, nullptr, 0.0, nullptr));
       const double V = G.g.cell[0] * G.g.cell[1] * G.g.cell[2];
       const double cq = -0.5 * kMu0 * G.mat.Ms * V, cz = -kMu0 * G.mat.Ms * V;
-      k_energy_reduce<<<(G.R + 63) / 64, 64, 0, s>>>(G.partial.as<double>(), G.nblk, G.R, cq, cz,
+      k_energy_reduce<<<(G.R + 63) / 64, 64, 0, ctx->stream>>>(G.partial.as<double>(), G.nblk, G.R, cq, cz,
                                                       ctx->Etmp.as<double>() + (size_t)roff * 6);
       HIP_TRY(hipGetLastError());
       roff += G.R;
     }
-    k_trace_store<<<1, 1, 0, s>>>(st, ctx->Etmp.as<double>(), R_total, (double*)trace, cap, force0);
+    k_trace_store<<<1, 1, 0, ctx->stream>>>(st, ctx->Etmp.as<double>(), R_total, (double*)trace, cap, force0);
     HIP_TRY(hipGetLastError());
     return MMX_OK;
   };
@@ -675,28 +693,65 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
         MMX_TRY(eval_group<T>(ctx, G, mb + G.off, cb, ep, 0, 1.0, dtdev, 0.0, done));
       }
     }
-    ProfScope psc(ctx->prof, "k_rk_controller", s);
-    k_rk_controller<<<1, 1, 0, s>>>(st, replay ? ctx->replay.as<double>() : nullptr,
+    ProfScope psc(ctx->prof, "k_rk_controller", ctx->stream);
+    k_rk_controller<<<1, 1, 0, ctx->stream>>>(st, replay ? ctx->replay.as<double>() : nullptr,
                                      ctx->dts.as<double>(), ctx->dts_cap);
     HIP_TRY(hipGetLastError());
     for (auto& gp : ctx->groups) {
       Group& G = *gp;
       const size_t n = (size_t)G.R * 3 * G.N;
       const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
-      ProfScope ps(ctx->prof, "k_rk_commit", s);
-      k_rk_commit<T><<<nb, 256, 0, s>>>(st, mb + G.off, G.m7.as<T>(), G.k[0].as<T>(),
+      ProfScope ps(ctx->prof, "k_rk_commit", ctx->stream);
+      k_rk_commit<T><<<nb, 256, 0, ctx->stream>>>(st, mb + G.off, G.m7.as<T>(), G.k[0].as<T>(),
                                          G.k[6].as<T>(), n);
       HIP_TRY(hipGetLastError());
     }
     if (trace) MMX_TRY(energy_into_trace(0));
     return MMX_OK;
   };
-  const int chunk = 16;
-  for (;;) {
-    for (int i = 0; i < chunk; ++i) MMX_TRY(one_step());
-    HIP_TRY(hipMemcpyAsync(&h, ctx->st.p, sizeof(RkState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (h.done) break;
+  const int chunk = 16;  // attempts per host poll of the controller state
+  if (ctx->prof.on) {
+    for (;;) {
+      for (int i = 0; i < chunk; ++i) MMX_TRY(one_step());
+      HIP_TRY(hipMemcpyAsync(&h, ctx->st.p, sizeof(RkState), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      if (h.done) break;
+    }
+  } else {
+    // the attempt sequence is static (dt, t and acceptance live on the device),
+    // so `chunk` attempts are captured once and replayed until done
+    MMX_TRY(ensure_graph_stream(ctx));
+    hipStream_t cs = ctx->cap_stream;
+    HIP_TRY(hipEventRecord(ctx->ev_user, s));
+    HIP_TRY(hipStreamWaitEvent(cs, ctx->ev_user, 0));
+    if (ctx->gexec) {
+      HIP_TRY(hipStreamSynchronize(cs));
+      (void)hipGraphExecDestroy(ctx->gexec);
+      ctx->gexec = nullptr;
+    }
+    ctx->stream = cs;
+    hipGraph_t graph = nullptr;
+    mmx_status cap = MMX_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int i = 0; i < chunk && cap == MMX_OK; ++i) cap = one_step();
+      e = hipStreamEndCapture(cs, &graph);
+    }
+    ctx->stream = s;
+    if (cap != MMX_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cap;
+    }
+    if (e != hipSuccess) return fail(MMX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(MMX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    for (;;) {
+      HIP_TRY(hipGraphLaunch(ctx->gexec, cs));
+      HIP_TRY(hipMemcpyAsync(&h, ctx->st.p, sizeof(RkState), hipMemcpyDeviceToHost, cs));
+      HIP_TRY(hipStreamSynchronize(cs));
+      if (h.done) break;
+    }
   }
   ctx->last_accepted = h.accepted;
   if (stats) {
@@ -707,6 +762,14 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
     stats->rejected = h.rejected;
   }
   if (h.dtmin_hit) return fail(MMX_EDTMIN, "step size fell below dt_min");
+  return MMX_OK;
+}
+
+mmx_status ensure_graph_stream(mmx_ctx* ctx) {
+  if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+  if (!ctx->ev_user) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_user, hipEventDisableTiming));
+  if (!ctx->ev_cap) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_cap, hipEventDisableTiming));
+  if (!ctx->stepdev.p) HIP_TRY(ctx->stepdev.alloc(sizeof(unsigned long long)));
   return MMX_OK;
 }
 
@@ -814,8 +877,10 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       roff += gp->R;
     }
   }
-  for (int64_t i = 0; i < n_steps; ++i) {
-    const uint64_t step = step0 + (uint64_t)i;
+  // one Heun step of every staged group on ctx->stream; with ctx->cur_stepdev
+  // set the step index comes from device memory and is advanced in-stream
+  auto one_step = [&](uint64_t step) -> mmx_status {
+    hipStream_t st = ctx->stream;
     for (int gi : staged) {
       Group& G = *ctx->groups[gi];
       const int roff = roffs[gi];
@@ -832,13 +897,62 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       e2.mout = mg;
       MMX_TRY(eval_group<T>(ctx, G, G.ms.as<T>(), Combine{}, e2, step, dt, nullptr, dt, nullptr));
       if (tsw_d) {
-        ProfScope ps(ctx->prof, "k_switch_reduce", s);
-        k_switch_reduce<<<(G.R + 63) / 64, 64, 0, s>>>(G.partial.as<double>(), G.nblk, G.R, G.N,
-                                                        tsw_d + roff, (double)(step + 1) * dt);
+        ProfScope ps(ctx->prof, "k_switch_reduce", st);
+        k_switch_reduce<<<(G.R + 63) / 64, 64, 0, st>>>(G.partial.as<double>(), G.nblk, G.R,
+                                                         G.N, tsw_d + roff, (double)(step + 1) * dt,
+                                                         ctx->cur_stepdev, dt);
         HIP_TRY(hipGetLastError());
       }
     }
+    if (ctx->cur_stepdev) {
+      k_inc_u64<<<1, 1, 0, st>>>(const_cast<unsigned long long*>(ctx->cur_stepdev), 1ull);
+      HIP_TRY(hipGetLastError());
+    }
+    return MMX_OK;
+  };
+  const int64_t chunk = 32;  // steps per captured graph
+  int64_t done_steps = 0;
+  if (n_steps >= 2 * chunk && !ctx->prof.on) {
+    // capture `chunk` steps once into a graph on the library's own stream
+    // (capture is not possible on the null stream) and replay it
+    MMX_TRY(ensure_graph_stream(ctx));
+    hipStream_t user = ctx->stream, cs = ctx->cap_stream;
+    HIP_TRY(hipEventRecord(ctx->ev_user, user));
+    HIP_TRY(hipStreamWaitEvent(cs, ctx->ev_user, 0));
+    unsigned long long* sd = ctx->stepdev.as<unsigned long long>();
+    k_set_u64<<<1, 1, 0, cs>>>(sd, (unsigned long long)step0);
+    HIP_TRY(hipGetLastError());
+    if (ctx->gexec) {
+      HIP_TRY(hipStreamSynchronize(cs));
+      (void)hipGraphExecDestroy(ctx->gexec);
+      ctx->gexec = nullptr;
+    }
+    ctx->stream = cs;
+    ctx->cur_stepdev = sd;
+    hipGraph_t graph = nullptr;
+    mmx_status cap = MMX_OK;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      for (int64_t i = 0; i < chunk && cap == MMX_OK; ++i) cap = one_step(step0);
+      e = hipStreamEndCapture(cs, &graph);
+    }
+    ctx->stream = user;
+    ctx->cur_stepdev = nullptr;
+    if (cap != MMX_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return cap;
+    }
+    if (e != hipSuccess) return fail(MMX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(MMX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+    const int64_t reps = n_steps / chunk;
+    for (int64_t i = 0; i < reps; ++i) HIP_TRY(hipGraphLaunch(ctx->gexec, cs));
+    done_steps = reps * chunk;
+    HIP_TRY(hipEventRecord(ctx->ev_cap, cs));
+    HIP_TRY(hipStreamWaitEvent(user, ctx->ev_cap, 0));
   }
+  for (int64_t i = done_steps; i < n_steps; ++i) MMX_TRY(one_step(step0 + (uint64_t)i));
   return MMX_OK;
 }
 

@@ -145,13 +145,18 @@ __global__ void k_rk_commit(const RkState* st, T* m, const T* m7, T* k1, const T
 
 // per-replica fixed-order sums of workgroup partials
 __global__ void k_switch_reduce(const double* partial, int nblk, int R, int N, double* tsw,
-                                double t_after) {
+                                double t_after, const unsigned long long* stepdev, double dt) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   double s = 0;
   for (int b = 0; b < nblk; ++b) s += partial[(size_t)r * nblk + b];
-  if (tsw[r] < 0 && s / N < 0) tsw[r] = t_after;
+  const double t = stepdev ? (double)(*stepdev + 1) * dt : t_after;
+  if (tsw[r] < 0 && s / N < 0) tsw[r] = t;
 }
+
+// step counter of captured graphs: set before a replay, advanced inside it
+__global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
+__global__ void k_inc_u64(unsigned long long* p, unsigned long long d) { *p += d; }
 
 __global__ void k_energy_reduce(const double* partial, int nblk, int R, double cq, double cz,
                                 double* E) {

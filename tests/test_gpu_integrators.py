@@ -238,3 +238,36 @@ def test_fused_path_matches_staged_and_oracle(name, prec):
     seeds = np.array(case.seeds) if case.seeds else 0
     ref = oit.heun_run(m0, case.grid, case.material(), 2e-14, nsteps, seed=seeds, step0=7)
     assert np.abs(fu - ref).max() <= TOLM[prec]
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_graph_replays_equal_eager_steps(prec):
+    """Long Heun runs replay a captured graph of 32 steps whose thermal-noise
+    step index lives in device memory; every replay must equal eager
+    one-step calls bit for bit, including the switching times, with eager
+    work and synchronisation between graph runs."""
+    import paper_2608_15253_amd as mmx
+    case = Case((40, 24, 1), (4e-9, 4e-9, 4e-9), R=3, alpha=0.5, Ku=1e5, B=(0, 0, -1.5),
+                T=300.0, seeds=list(replica_seeds(8, 3)),
+                terms=("exchange", "anisotropy", "zeeman", "demag", "thermal"))
+    m0 = _round(uniform(case.n, (0.05, 0.0, 1.0), replicas=case.R), prec)
+    res = {}
+    for mode in ("graph", "eager"):
+        ctx = open_ctx(case, prec)
+        try:
+            mmx.mmx_set_path(ctx, mmx.MMX_PATH_STAGED)
+            md = dev(m0, prec)
+            ts = dev(-np.ones(case.R), 2)
+            if mode == "graph":
+                mmx.mmx_heun(ctx, md, 1e-13, 70, 0, ts)      # 2 replays + 6 eager
+                mmx.mmx_heun(ctx, md, 1e-13, 3, 70, ts)      # eager in between
+                host(md)
+                mmx.mmx_heun(ctx, md, 1e-13, 96, 73, ts)     # new capture, 3 replays
+            else:
+                for k in range(169):
+                    mmx.mmx_heun(ctx, md, 1e-13, 1, k, ts)
+            res[mode] = (host(md), host(ts))
+        finally:
+            mmx.mmx_destroy(ctx)
+    assert np.array_equal(res["graph"][0], res["eager"][0])
+    assert np.array_equal(res["graph"][1], res["eager"][1])
