@@ -201,6 +201,44 @@ mmx_status mmx_set_tiles(mmx_ctx* ctx, int32_t group, const int32_t tiles[3]);
 mmx_status mmx_get_tiles(mmx_ctx* ctx, int32_t group, int32_t tiles[3]);
 mmx_status mmx_autotune(mmx_ctx* ctx);
 
+/* ------------------------------------------------------------------------
+ * Learned demag surrogate: a Fourier neural operator h = f(m) ~ H_demag / Ms
+ * for films of H x W cells (the build's learned form; not in the paper).
+ * Network: features [m, x/W - 1/2, y/H - 1/2] -> 1x1 lift to C channels ->
+ * L layers of [truncated DFT (kx < M1, ky in [0, M2) u [H - M2, H)) ->
+ * per-mode complex C x C mixing -> inverse real DFT, plus a 1x1 map and
+ * bias, GELU except after the last layer] -> 1x1 to Cp -> GELU -> 1x1 to 3.
+ * The 1x1 maps run as BF16 matrix-core GEMMs with FP32 accumulation
+ * (use_mfma = 1) or in FP32 (use_mfma = 0); transforms, mixing and reductions
+ * are FP32.  All arrays are FP32 device pointers owned by the caller:
+ * m, h, target [B][3][H][W] (x fastest); params and grads packed as
+ *   P[C][5], p[C], then per layer R[M1][2 M2][C][C] (complex, re/im
+ *   interleaved), W[C][C], b[C], then Q1[Cp][C], q1[Cp], Q2[3][Cp], q2[3],
+ * mmx_fno_param_count floats in total; moments (Adam) 2x that.
+ * The loss is the batch mean of |h - t|^2 / |t|^2 per sample.
+ * mmx_fno_backward differentiates the last mmx_fno_forward (its activations
+ * stay in library buffers) and overwrites grads.  Errors: MMX_EINVAL for bad
+ * sizes / nulls, MMX_EUNSUP beyond C, Cp <= 128, batch <= 64, MMX_ESTATE for a
+ * backward without forward.  Work is queued on the FNO's stream; the loss is
+ * returned synchronously when `loss` is not null.
+ * ------------------------------------------------------------------------ */
+typedef struct mmx_fno mmx_fno;
+mmx_status mmx_fno_create(int32_t H, int32_t W, int32_t C, int32_t M1, int32_t M2, int32_t L,
+                          int32_t Cp, int32_t batch_max, int32_t use_mfma, mmx_fno** out);
+void mmx_fno_destroy(mmx_fno* f);
+mmx_status mmx_fno_set_stream(mmx_fno* f, void* hip_stream);
+mmx_status mmx_fno_param_count(const mmx_fno* f, int64_t* n);
+/* Seeded initial weights (scaled normals; spectral weights uniform in [0, 1/C^2)). */
+mmx_status mmx_fno_init(mmx_fno* f, float* params, uint64_t seed);
+mmx_status mmx_fno_forward(mmx_fno* f, const float* params, const float* m, float* h,
+                           int32_t batch);
+mmx_status mmx_fno_backward(mmx_fno* f, const float* params, const float* h, const float* target,
+                            float* grads, double* loss);
+/* Adam (Kingma & Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8) on every float of
+ * params; moments = [first moments | second moments], zero before step t = 1. */
+mmx_status mmx_fno_adam(mmx_fno* f, float* params, const float* grads, float* moments, double lr,
+                        int64_t t);
+
 /* Measurement support (not part of the method).  mmx_profile_enable(ctx, 1)
  * clears the statistics and brackets every later kernel launch of ctx with a
  * pair of HIP events on the bound stream; mmx_profile_enable(ctx, 0) stops.

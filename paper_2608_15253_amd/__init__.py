@@ -79,6 +79,13 @@ _SIGS = {
                      ctypes.POINTER(ctypes.c_int64)],
     "mmx_energy": [_P, _P, _P],
     "mmx_topological_charge": [_P, _P, _P],
+    "mmx_fno_create": [ctypes.c_int32] * 9 + [ctypes.POINTER(_P)],
+    "mmx_fno_set_stream": [_P, _P],
+    "mmx_fno_param_count": [_P, ctypes.POINTER(ctypes.c_int64)],
+    "mmx_fno_init": [_P, _P, ctypes.c_uint64],
+    "mmx_fno_forward": [_P, _P, _P, _P, ctypes.c_int32],
+    "mmx_fno_backward": [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)],
+    "mmx_fno_adam": [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int64],
     "mmx_set_path": [_P, ctypes.c_int32],
     "mmx_set_tiles": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "mmx_get_tiles": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
@@ -94,10 +101,12 @@ for _name, _args in _SIGS.items():
     _f.restype = ctypes.c_int
 _lib.mmx_destroy.argtypes = [_P]
 _lib.mmx_destroy.restype = None
+_lib.mmx_fno_destroy.argtypes = [_P]
+_lib.mmx_fno_destroy.restype = None
 _lib.mmx_last_error.argtypes = []
 _lib.mmx_last_error.restype = ctypes.c_char_p
 
-EXPORTED = list(_SIGS) + ["mmx_destroy", "mmx_last_error"]
+EXPORTED = list(_SIGS) + ["mmx_destroy", "mmx_last_error", "mmx_fno_destroy"]
 
 
 def mmx_last_error() -> str:
@@ -252,3 +261,47 @@ def mmx_profile_get(ctx) -> dict:
                                                        ctypes.byref(cnt), ctypes.byref(n)))
         out[name.value.decode()] = (ms.value, cnt.value)
     return out
+
+
+# --------------------------------------------------------------------------
+# learned demag surrogate
+# --------------------------------------------------------------------------
+def mmx_fno_create(H, W, C=32, M1=12, M2=12, L=4, Cp=128, batch_max=32, use_mfma=True) -> int:
+    out = _P()
+    _check("mmx_fno_create", _lib.mmx_fno_create(H, W, C, M1, M2, L, Cp, batch_max,
+                                                 1 if use_mfma else 0, ctypes.byref(out)))
+    return out.value
+
+
+def mmx_fno_destroy(f) -> None:
+    _lib.mmx_fno_destroy(f)
+
+
+def mmx_fno_set_stream(f, stream) -> None:
+    _check("mmx_fno_set_stream", _lib.mmx_fno_set_stream(f, stream))
+
+
+def mmx_fno_param_count(f) -> int:
+    n = ctypes.c_int64()
+    _check("mmx_fno_param_count", _lib.mmx_fno_param_count(f, ctypes.byref(n)))
+    return n.value
+
+
+def mmx_fno_init(f, params, seed) -> None:
+    _check("mmx_fno_init", _lib.mmx_fno_init(f, _ptr(params), int(seed)))
+
+
+def mmx_fno_forward(f, params, m, h, batch) -> None:
+    _check("mmx_fno_forward", _lib.mmx_fno_forward(f, _ptr(params), _ptr(m), _ptr(h), int(batch)))
+
+
+def mmx_fno_backward(f, params, h, target, grads) -> float:
+    loss = ctypes.c_double()
+    _check("mmx_fno_backward", _lib.mmx_fno_backward(f, _ptr(params), _ptr(h), _ptr(target),
+                                                     _ptr(grads), ctypes.byref(loss)))
+    return loss.value
+
+
+def mmx_fno_adam(f, params, grads, moments, lr, t) -> None:
+    _check("mmx_fno_adam", _lib.mmx_fno_adam(f, _ptr(params), _ptr(grads), _ptr(moments),
+                                             float(lr), int(t)))

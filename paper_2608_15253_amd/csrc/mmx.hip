@@ -1394,3 +1394,5 @@ mmx_status mmx_autotune(mmx_ctx* ctx) {
 }
 
 }  // extern "C"
+
+#include "fno_api.h"
