@@ -239,6 +239,44 @@ mmx_status mmx_fno_backward(mmx_fno* f, const float* params, const float* h, con
 mmx_status mmx_fno_adam(mmx_fno* f, float* params, const float* grads, float* moments, double lr,
                         int64_t t);
 
+/* ---- RK45 with learned demag stages --------------------------------------
+ * The adaptive Dormand-Prince integration of mmx_rk45 (Methods,
+ * "Integrators"; same tableau, controller, dt_max and dt_min) in which stages
+ * 2-6 of an attempt take the demagnetising field from the network `net` with
+ * parameters `params` (device, FP32, layout above) instead of the FFT
+ * convolution: Hd = Ms * f(m) + (0, 0, -Ms m_z if residual_mz).  Stage 7, at
+ * the candidate point, and the first stage of the run use the exact field.
+ * (The learned stages and their gate are an extension, not a method of the
+ * paper.)  Gate: when the controller accepts such an attempt, the network is evaluated
+ * at the candidate state m7 and compared with the exact stage-7 field; the
+ * step is kept iff, for every replica, |Hd_net - Hd_exact|_2 / |Hd_exact|_2
+ * <= gate_tol over the film.  Otherwise the attempt (and equally an attempt
+ * the controller rejects) is discarded and repeated from the same state and
+ * step size with the exact field in every stage; after a gate failure the
+ * next exact_after_fail accepted steps are also exact.  With gate_tol = 0 (or
+ * unusable weights) every kept step is an exact one and the result equals
+ * mmx_rk45's bit for bit.  Requires: FP32 context, one group, a film
+ * (nz = 1) of net's H x W grid (ny = H, nx = W), replicas <= net's
+ * batch_max, demag term on and built, no thermal term.  The run is driven
+ * from the host (one synchronisation per attempt, one per gate check) on the
+ * context's stream; net's own stream is left unchanged.  gate_log (host,
+ * optional, gate_cap entries) receives the largest replica error of each
+ * gate check in order; stats (host, optional) the counters below.
+ * Errors: EINVAL, ESHAPE, ESTATE, EUNSUP, EHIP, EDTMIN as for mmx_rk45. */
+typedef struct {
+  double t, dt, err;            /* final time, next step size, last error estimate */
+  int64_t accepted, rejected;   /* accepted steps; controller rejections of exact attempts */
+  int64_t surrogate_steps;      /* accepted steps whose stages 2-6 used the network */
+  int64_t exact_steps;          /* accepted steps with the exact field in every stage */
+  int64_t gate_checks, gate_failures;
+  int64_t surrogate_rejected;   /* network attempts rejected by the controller (repeated) */
+  double gate_max_passed;       /* largest gate error among the kept steps */
+} mmx_surrogate_stats;
+mmx_status mmx_rk45_surrogate(mmx_ctx* ctx, mmx_fno* net, const float* params, void* m, double t0,
+                              double t_end, double tol, double dt0, double gate_tol,
+                              int32_t residual_mz, int32_t exact_after_fail, double* gate_log,
+                              int64_t gate_cap, mmx_surrogate_stats* stats);
+
 /* Measurement support (not part of the method).  mmx_profile_enable(ctx, 1)
  * clears the statistics and brackets every later kernel launch of ctx with a
  * pair of HIP events on the bound stream; mmx_profile_enable(ctx, 0) stops.

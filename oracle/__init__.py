@@ -23,7 +23,7 @@ stencil only), long-horizon thermal trajectories (chaotic; statistical only).
 """
 from .constants import GAMMA0, MU0, KB
 from .problem import Grid, Material
-from . import newell, demag, fields, llg, philox, integrators, observables, fno
+from . import newell, demag, fields, llg, philox, integrators, observables, fno, surrogate
 
 __all__ = ["GAMMA0", "MU0", "KB", "Grid", "Material", "newell", "demag",
-           "fields", "llg", "philox", "integrators", "observables", "fno"]
+           "fields", "llg", "philox", "integrators", "observables", "fno", "surrogate"]

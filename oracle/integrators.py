@@ -85,16 +85,18 @@ def heun_run(m0, grid, mat, dt, nsteps, seed=0, step0=0, t_switch=None):
 # ----------------------------------------------------------------------------
 # Dormand-Prince 5(4)
 # ----------------------------------------------------------------------------
-def dopri5_attempt(m, k1, grid, mat, dt):
+def dopri5_attempt(m, k1, grid, mat, dt, stage_rhs=None):
     """One DOPRI5 attempt from (m, k1 = f(m)).  Returns (m7, k7, err) where m7 is
-    the normalised 5th-order candidate and k7 = f(m7)."""
+    the normalised 5th-order candidate and k7 = f(m7).  ``stage_rhs(ms)``, if
+    given, replaces f for stages 2-6 (the seventh stage is always f)."""
+    f_stage = stage_rhs if stage_rhs is not None else (lambda ms: rhs(ms, grid, mat))
     ks = [k1]
     for s in range(1, 6):
         ms = m.copy()
         for j in range(s):
             if A[s][j] != 0:
                 ms = ms + dt * float(A[s][j]) * ks[j]
-        ks.append(rhs(ms, grid, mat))
+        ks.append(f_stage(ms))
     y5 = m.copy()
     for j in range(6):
         if B5[j] != 0:

@@ -14,6 +14,8 @@ from __future__ import annotations
 import ctypes
 import os
 
+import numpy as np
+
 # torch is imported first so that libmmx's libamdhip64.so.7 dependency binds to
 # the HIP runtime torch already loaded (same SONAME): one runtime per process,
 # so device pointers and streams from torch are valid inside the library.
@@ -46,6 +48,14 @@ class mmx_material(ctypes.Structure):
 class mmx_rk_stats(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("err", ctypes.c_double),
                 ("accepted", ctypes.c_int64), ("rejected", ctypes.c_int64)]
+
+
+class mmx_surrogate_stats(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("dt", ctypes.c_double), ("err", ctypes.c_double),
+                ("accepted", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("surrogate_steps", ctypes.c_int64), ("exact_steps", ctypes.c_int64),
+                ("gate_checks", ctypes.c_int64), ("gate_failures", ctypes.c_int64),
+                ("surrogate_rejected", ctypes.c_int64), ("gate_max_passed", ctypes.c_double)]
 
 
 class MMXError(RuntimeError):
@@ -86,6 +96,10 @@ _SIGS = {
     "mmx_fno_forward": [_P, _P, _P, _P, ctypes.c_int32],
     "mmx_fno_backward": [_P, _P, _P, _P, _P, ctypes.POINTER(ctypes.c_double)],
     "mmx_fno_adam": [_P, _P, _P, _P, ctypes.c_double, ctypes.c_int64],
+    "mmx_rk45_surrogate": [_P, _P, _P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                           ctypes.c_double, ctypes.c_double, ctypes.c_int32, ctypes.c_int32,
+                           ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
+                           ctypes.POINTER(mmx_surrogate_stats)],
     "mmx_set_path": [_P, ctypes.c_int32],
     "mmx_set_tiles": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
     "mmx_get_tiles": [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)],
@@ -121,8 +135,8 @@ def _check(fn, status):
 def _ptr(x):
     if x is None:
         return None
-    if isinstance(x, int):
-        return x
+    if isinstance(x, (int, np.integer)):
+        return int(x)
     return x.data_ptr()
 
 
@@ -202,6 +216,21 @@ def mmx_rk45(ctx, m, t0, t_end, tol, dt0=1e-14, dt_replay=None, energy_trace=Non
                                      float(dt0), rp, nrp, _ptr(energy_trace), int(trace_cap),
                                      ctypes.byref(st)))
     return st
+
+
+def mmx_rk45_surrogate(ctx, net, params, m, t0, t_end, tol, dt0=1e-14, gate_tol=1e-3,
+                       residual_mz=True, exact_after_fail=10, gate_cap=0):
+    """RK45 whose stages 2-6 use the network's demag field, gated at every
+    accepted step by the exact field; returns (stats, gate errors list)."""
+    st = mmx_surrogate_stats()
+    log = (ctypes.c_double * max(int(gate_cap), 1))()
+    _check("mmx_rk45_surrogate",
+           _lib.mmx_rk45_surrogate(ctx, net, _ptr(params), _ptr(m), float(t0), float(t_end),
+                                   float(tol), float(dt0), float(gate_tol), int(bool(residual_mz)),
+                                   int(exact_after_fail), log if gate_cap else None,
+                                   int(gate_cap), ctypes.byref(st)))
+    n = min(int(gate_cap), st.gate_checks)
+    return st, [log[i] for i in range(n)]
 
 
 def mmx_rk45_dts(ctx, cap=None):
@@ -295,11 +324,13 @@ def mmx_fno_forward(f, params, m, h, batch) -> None:
     _check("mmx_fno_forward", _lib.mmx_fno_forward(f, _ptr(params), _ptr(m), _ptr(h), int(batch)))
 
 
-def mmx_fno_backward(f, params, h, target, grads) -> float:
+def mmx_fno_backward(f, params, h, target, grads, want_loss=True):
+    """Gradients of the last forward; returns the loss (synchronous) or None."""
     loss = ctypes.c_double()
     _check("mmx_fno_backward", _lib.mmx_fno_backward(f, _ptr(params), _ptr(h), _ptr(target),
-                                                     _ptr(grads), ctypes.byref(loss)))
-    return loss.value
+                                                     _ptr(grads),
+                                                     ctypes.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
 
 
 def mmx_fno_adam(f, params, grads, moments, lr, t) -> None:

@@ -330,6 +330,9 @@ struct FArgs {
   RkState* st;
   double* partial;
   const int* done;
+  const float* hext;  // if set (demag term off): Hd = hext_scale * hext + (0, 0, hext_mz m_z)
+  T hext_scale, hext_mz;
+  T* hd_out;          // if set: the exact demag field is also stored here
 };
 
 template <typename T>
@@ -461,6 +464,14 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
     if (demag) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) Hdd[c] = Hd[(c * L + l) * 2 * hx + x];
+      if (a.hd_out) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.hd_out[rb + (size_t)c * a.N + cell] = Hdd[c];
+      }
+    } else if (a.hext) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Hdd[c] = a.hext_scale * (T)a.hext[rb + (size_t)c * a.N + cell];
+      Hdd[2] += a.hext_mz * mc[2];
     }
     if (MODE == FM_ENERGY) {
       acc[0] += (double)(mc[0] * Hex[0] + mc[1] * Hex[1] + mc[2] * Hex[2]);

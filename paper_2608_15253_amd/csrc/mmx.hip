@@ -237,6 +237,11 @@ struct mmx_ctx {
   long long dts_cap = 0;
   long long last_accepted = 0;
   DevBuf Etmp;     // per-replica energies for traces
+  // learned-demag stages: network field input and exact-demag output of k_fields
+  const float* hext = nullptr;
+  double hext_scale = 0, hext_mz = 0;
+  void* hd_out = nullptr;
+  DevBuf sg_h, sg_hd, sg_part, sg_err;  // surrogate integrator buffers
 };
 
 namespace {
@@ -475,6 +480,39 @@ mmx_status launch_fields(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
   return MMX_OK;
 }
 
+// stage combine m + dt sum_j c_j k_j (optionally normalised) fused with the x
+// forward transform of the demag convolution when `demag` is set
+template <typename T>
+mmx_status launch_xfwd(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb, bool demag,
+                       const double* dtdev, double dth, const int* done) {
+  hipStream_t s = ctx->stream;
+  XArgs<T> x{};
+  x.m = mbase;
+  x.ncoef = cb.ncoef;
+  for (int j = 0; j < cb.ncoef; ++j) {
+    x.kk[j] = G.k[cb.kidx[j]].as<T>();
+    x.coef[j] = (T)cb.coef[j];
+  }
+  x.dtdev = dtdev;
+  x.dth = dth;
+  x.mout = reinterpret_cast<T*>(cb.mout);
+  x.normalise = cb.normalise;
+  x.do_fft = demag ? 1 : 0;
+  x.S = G.S.as<cpx<T>>();
+  x.tw = G.tw_x.as<cpx<T>>();
+  x.wpost = G.wpost.as<cpx<T>>();
+  x.plan = G.plan_x;
+  x.nx = G.nx; x.ny = G.ny; x.nz = G.nz; x.N = G.N; x.Sy = G.Sy; x.Kx = G.Kx; x.hx = G.hx;
+  x.L = G.L; x.xone = G.xone;
+  x.done = done;
+  dim3 grid((G.ny + G.L - 1) / G.L, G.nz, G.R);
+  const size_t lds = demag ? (2 * (size_t)3 * G.L * G.hx + 2 * G.hx + 1) * cpxb<T>() : 0;
+  ProfScope ps(ctx->prof, demag ? "k_xfwd" : "k_combine", s);
+  k_xfwd<T><<<grid, kBlock, lds, s>>>(x);
+  HIP_TRY(hipGetLastError());
+  return MMX_OK;
+}
+
 // m: group-local base pointer of the state used for fields.
 template <typename T>
 mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb, const Epilogue& ep,
@@ -487,30 +525,7 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
   const T* mfield = mbase;
   // stage 1: combine (+ x forward transform)
   if (demag || cb.mout) {
-    XArgs<T> x{};
-    x.m = mbase;
-    x.ncoef = cb.ncoef;
-    for (int j = 0; j < cb.ncoef; ++j) {
-      x.kk[j] = G.k[cb.kidx[j]].as<T>();
-      x.coef[j] = (T)cb.coef[j];
-    }
-    x.dtdev = dtdev;
-    x.dth = dth;
-    x.mout = reinterpret_cast<T*>(cb.mout);
-    x.normalise = cb.normalise;
-    x.do_fft = demag ? 1 : 0;
-    x.S = G.S.as<cpx<T>>();
-    x.tw = G.tw_x.as<cpx<T>>();
-    x.wpost = G.wpost.as<cpx<T>>();
-    x.plan = G.plan_x;
-    x.nx = G.nx; x.ny = G.ny; x.nz = G.nz; x.N = G.N; x.Sy = G.Sy; x.Kx = G.Kx; x.hx = G.hx;
-    x.L = G.L; x.xone = G.xone;
-    x.done = done;
-    dim3 grid((G.ny + G.L - 1) / G.L, G.nz, G.R);
-    const size_t lds = demag ? (2 * (size_t)3 * G.L * G.hx + 2 * G.hx + 1) * cpxb<T>() : 0;
-    ProfScope ps(ctx->prof, demag ? "k_xfwd" : "k_combine", s);
-    k_xfwd<T><<<grid, kBlock, lds, s>>>(x);
-    HIP_TRY(hipGetLastError());
+    MMX_TRY(launch_xfwd<T>(ctx, G, mbase, cb, demag, dtdev, dth, done));
     if (cb.mout) mfield = reinterpret_cast<const T*>(cb.mout);
   }
   // stage 2: y (and z) passes with the tensor product
@@ -575,6 +590,12 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
   for (int j = 0; j < 6; ++j) a.kk[j] = G.k[j].as<T>();
   a.st = ctx->st.as<RkState>();
   a.partial = G.partial.as<double>();
+  if (!demag && ctx->hext) {
+    a.hext = ctx->hext;
+    a.hext_scale = (T)ctx->hext_scale;
+    a.hext_mz = (T)ctx->hext_mz;
+  }
+  if (demag) a.hd_out = reinterpret_cast<T*>(ctx->hd_out);
   return launch_fields<T>(ctx, G, a, ep.mode);
 }
 
@@ -592,10 +613,21 @@ const double DP_A[7][6] = {
 const double DP_B4[7] = {5179.0 / 57600, 0, 7571.0 / 16695, 393.0 / 640, -92097.0 / 339200,
                          187.0 / 2100, 1.0 / 40};
 
+// learned-demag hook of an RK45 attempt: stages 2-6 take the demag field from
+// `field` (written to h, applied as scale * h + (0, 0, mz m_z)); stage 7 uses
+// the exact convolution and also stores it in hd
+struct StageHook {
+  virtual mmx_status field(mmx_ctx* ctx, Group& G, const float* m) const = 0;
+  float* h = nullptr;
+  double scale = 0, mz = 0;
+  void* hd = nullptr;
+};
+
+// validates the arguments, allocates the stage buffers and uploads the initial
+// controller state (dt clamped to dt_max, final step landing on t_end)
 template <typename T>
-mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, double dt0,
-                     const double* replay, int64_t n_replay, void* trace, int64_t cap,
-                     mmx_rk_stats* stats) {
+mmx_status rk_begin(mmx_ctx* ctx, double t0, double t_end, double tol, double dt0,
+                    const double* replay, int64_t n_replay, RkState& h) {
   if (ctx->terms & MMX_THERMAL) return fail(MMX_EUNSUP, "thermal field with RK45");
   if (!(t_end > t0)) return fail(MMX_EINVAL, "t_end must exceed t0");
   if (!(tol > 0) && !replay) return fail(MMX_EINVAL, "tol must be > 0");
@@ -603,7 +635,7 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
   for (auto& g : ctx->groups) MMX_TRY(ensure_rk_buffers<T>(*g));
   hipStream_t s = ctx->stream;
   // controller state
-  RkState h{};
+  h = RkState{};
   h.t = t0;
   h.t_end = t_end;
   h.tol = tol;
@@ -629,9 +661,100 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
     HIP_TRY(hipMemcpyAsync(ctx->replay.p, replay, n_replay * sizeof(double),
                            hipMemcpyHostToDevice, s));
   }
+  return MMX_OK;
+}
+
+// stages 2..7 of one Dormand-Prince attempt for group G from its state mg; the
+// stage-7 evaluation also yields the embedded error estimate (e = b5 - b4)
+template <typename T>
+mmx_status rk_stages(mmx_ctx* ctx, Group& G, T* mg, const double e[7], const StageHook* hook) {
   RkState* st = ctx->st.as<RkState>();
   const int* done = &st->done;
   const double* dtdev = &st->dt;
+  for (int sidx = 1; sidx < 7; ++sidx) {
+    Combine cb;
+    for (int j = 0; j < sidx; ++j) {
+      const double c = DP_A[sidx][j];
+      if (c == 0.0) continue;
+      cb.coef[cb.ncoef] = c;
+      cb.kidx[cb.ncoef] = j;
+      cb.ncoef++;
+    }
+    Epilogue ep;
+    if (sidx < 6) {
+      cb.mout = G.ms.p;
+      ep.mode = FM_RKK;
+      ep.out = G.k[sidx].p;
+    } else {
+      cb.mout = G.m7.p;
+      cb.normalise = 1;
+      ep.mode = FM_RK7;
+      ep.out = G.k[6].p;
+      for (int j = 0; j < 7; ++j) ep.e[j] = e[j];
+    }
+    if (hook && sidx < 6) {
+      // learned demag: combine, network field at the stage state, local terms
+      MMX_TRY(launch_xfwd<T>(ctx, G, mg, cb, false, dtdev, 0.0, done));
+      MMX_TRY(hook->field(ctx, G, reinterpret_cast<const float*>(cb.mout)));  // FP32 only
+      ctx->hext = hook->h;
+      ctx->hext_scale = hook->scale;
+      ctx->hext_mz = hook->mz;
+      const mmx_status r = eval_group<T>(ctx, G, reinterpret_cast<const T*>(cb.mout), Combine{}, ep,
+                                         0, 1.0, dtdev, 0.0, done, ctx->terms & ~MMX_DEMAG);
+      ctx->hext = nullptr;
+      MMX_TRY(r);
+    } else {
+      ctx->hd_out = (hook && sidx == 6) ? hook->hd : nullptr;
+      const mmx_status r = eval_group<T>(ctx, G, mg, cb, ep, 0, 1.0, dtdev, 0.0, done);
+      ctx->hd_out = nullptr;
+      MMX_TRY(r);
+    }
+  }
+  return MMX_OK;
+}
+
+// controller decision, then m <- m7 and k1 <- k7 if the attempt was accepted
+template <typename T>
+mmx_status rk_finish(mmx_ctx* ctx, T* mb, const double* replay) {
+  RkState* st = ctx->st.as<RkState>();
+  {
+    ProfScope psc(ctx->prof, "k_rk_controller", ctx->stream);
+    k_rk_controller<<<1, 1, 0, ctx->stream>>>(st, replay, ctx->dts.as<double>(), ctx->dts_cap);
+    HIP_TRY(hipGetLastError());
+  }
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    const size_t n = (size_t)G.R * 3 * G.N;
+    const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
+    ProfScope ps(ctx->prof, "k_rk_commit", ctx->stream);
+    k_rk_commit<T><<<nb, 256, 0, ctx->stream>>>(st, mb + G.off, G.m7.as<T>(), G.k[0].as<T>(),
+                                               G.k[6].as<T>(), n);
+    HIP_TRY(hipGetLastError());
+  }
+  return MMX_OK;
+}
+
+// k1 = f(m) for every group (first stage; later steps reuse k7 of the last accepted one)
+template <typename T>
+mmx_status rk_first_stage(mmx_ctx* ctx, T* mb) {
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    Epilogue ep;
+    ep.mode = FM_RKK;
+    ep.out = G.k[0].p;
+    MMX_TRY(eval_group<T>(ctx, G, mb + G.off, Combine{}, ep, 0, 1.0, nullptr, 0.0, nullptr));
+  }
+  return MMX_OK;
+}
+
+template <typename T>
+mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, double dt0,
+                     const double* replay, int64_t n_replay, void* trace, int64_t cap,
+                     mmx_rk_stats* stats) {
+  RkState h;
+  MMX_TRY(rk_begin<T>(ctx, t0, t_end, tol, dt0, replay, n_replay, h));
+  hipStream_t s = ctx->stream;
+  RkState* st = ctx->st.as<RkState>();
   T* mb = reinterpret_cast<T*>(m);
   // trace helpers
   int R_total = 0;
@@ -655,57 +778,13 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
     HIP_TRY(hipGetLastError());
     return MMX_OK;
   };
-  // k1 = f(m)
-  for (auto& gp : ctx->groups) {
-    Group& G = *gp;
-    Epilogue ep;
-    ep.mode = FM_RKK;
-    ep.out = G.k[0].p;
-    MMX_TRY(eval_group<T>(ctx, G, mb + G.off, Combine{}, ep, 0, 1.0, nullptr, 0.0, nullptr));
-  }
+  MMX_TRY(rk_first_stage<T>(ctx, mb));
   if (trace) MMX_TRY(energy_into_trace(1));
   double e[7];
   for (int j = 0; j < 7; ++j) e[j] = (j < 6 ? DP_A[6][j] : 0.0) - DP_B4[j];
   auto one_step = [&]() -> mmx_status {
-    for (auto& gp : ctx->groups) {
-      Group& G = *gp;
-      for (int sidx = 1; sidx < 7; ++sidx) {  // stages 2..7
-        Combine cb;
-        for (int j = 0; j < sidx; ++j) {
-          const double c = DP_A[sidx][j];
-          if (c == 0.0) continue;
-          cb.coef[cb.ncoef] = c;
-          cb.kidx[cb.ncoef] = j;
-          cb.ncoef++;
-        }
-        Epilogue ep;
-        if (sidx < 6) {
-          cb.mout = G.ms.p;
-          ep.mode = FM_RKK;
-          ep.out = G.k[sidx].p;
-        } else {
-          cb.mout = G.m7.p;
-          cb.normalise = 1;
-          ep.mode = FM_RK7;
-          ep.out = G.k[6].p;
-          for (int j = 0; j < 7; ++j) ep.e[j] = e[j];
-        }
-        MMX_TRY(eval_group<T>(ctx, G, mb + G.off, cb, ep, 0, 1.0, dtdev, 0.0, done));
-      }
-    }
-    ProfScope psc(ctx->prof, "k_rk_controller", ctx->stream);
-    k_rk_controller<<<1, 1, 0, ctx->stream>>>(st, replay ? ctx->replay.as<double>() : nullptr,
-                                     ctx->dts.as<double>(), ctx->dts_cap);
-    HIP_TRY(hipGetLastError());
-    for (auto& gp : ctx->groups) {
-      Group& G = *gp;
-      const size_t n = (size_t)G.R * 3 * G.N;
-      const unsigned nb = (unsigned)std::min<size_t>((n + 255) / 256, 4096);
-      ProfScope ps(ctx->prof, "k_rk_commit", ctx->stream);
-      k_rk_commit<T><<<nb, 256, 0, ctx->stream>>>(st, mb + G.off, G.m7.as<T>(), G.k[0].as<T>(),
-                                         G.k[6].as<T>(), n);
-      HIP_TRY(hipGetLastError());
-    }
+    for (auto& gp : ctx->groups) MMX_TRY(rk_stages<T>(ctx, *gp, mb + gp->off, e, nullptr));
+    MMX_TRY(rk_finish<T>(ctx, mb, replay ? ctx->replay.as<double>() : nullptr));
     if (trace) MMX_TRY(energy_into_trace(0));
     return MMX_OK;
   };
@@ -1396,3 +1475,4 @@ mmx_status mmx_autotune(mmx_ctx* ctx) {
 }  // extern "C"
 
 #include "fno_api.h"
+#include "surrogate.h"
