@@ -204,28 +204,29 @@ def train(net: Net, m_all, t_all, n_train, epochs, lr0=1e-3, log=print, seed=0):
     t0 = time.time()
     for ep in range(epochs):
         order = rng.permutation(nb)
-        acc = 0.0
+        sampled = []
         for j, bi in enumerate(order):
             lr = 0.5 * lr0 * (1.0 + math.cos(math.pi * it / total))
-            want = (j % 50 == 0)
+            want = (j % 16 == 0)   # loss read back (a synchronisation) on every 16th batch
             loss = net.step(_batch_ptrs(m_all, bi * B, B), _batch_ptrs(t_all, bi * B, B), B, lr,
                             want_loss=want)
             if want:
-                acc = loss
+                sampled.append(loss)
             it += 1
         torch.cuda.synchronize()
-        hist.append(acc)
-        log(f"  epoch {ep + 1}/{epochs}: train loss {acc:.4e} ({time.time() - t0:.1f} s)")
+        hist.append(float(np.mean(sampled)) if sampled else None)
+        log(f"  epoch {ep + 1}/{epochs}: mean sampled train loss {hist[-1]:.4e} "
+            f"({time.time() - t0:.1f} s)")
     return hist, time.time() - t0
 
 
-def speedup(net: Net, n=(128, 128, 1), R=8, t_end=5e-11, tol=1e-5, gate_tol=1e-3, seed=SEED0 + 90_000,
-            log=print):
+def speedup(net: Net, n=(128, 128, 1), R=8, t_end=5e-11, tol=1e-5, gates=(1e-3,),
+            seed=SEED0 + 90_000, log=print):
     """Held-out skyrmion-film relaxations (0 K): plain FP32 RK45 versus RK45
-    with learned stages, both against an FP64 RK45 reference at tol 1e-9."""
+    with learned stages at each gate threshold, all against an FP64 RK45
+    reference at tol 1e-9; plus a per-kernel time split of one learned run."""
     style = Style("eval", alpha=0.3, Ku=6e5, D=3e-3, B=(0.0, 0.0, 0.1), init="skyrmions")
     m0 = initial_states(style, n, R, seed)
-    # reference
     ref_ctx = _film_ctx(n, R, style, prec=mmx.MMX_F64)
     try:
         mref = torch.as_tensor(m0, dtype=torch.float64, device="cuda:0").contiguous()
@@ -234,7 +235,8 @@ def speedup(net: Net, n=(128, 128, 1), R=8, t_end=5e-11, tol=1e-5, gate_tol=1e-3
     finally:
         mmx.mmx_destroy(ref_ctx)
     ctx = _film_ctx(n, R, style)
-    out = {}
+    out = dict(workload=f"skyrmion film relaxation {n[0]}x{n[1]}x1, {R} replicas, "
+                        f"0..{t_end:g} s, tol {tol:g}, held-out seeds")
     try:
         def timed(fn):
             m = _dev(m0)
@@ -244,33 +246,46 @@ def speedup(net: Net, n=(128, 128, 1), R=8, t_end=5e-11, tol=1e-5, gate_tol=1e-3
             torch.cuda.synchronize()
             return m, time.perf_counter() - t0, res
 
+        def dm(m):
+            return float((m.double() - mref).norm(dim=1).max())
+
         timed(lambda m: mmx.mmx_rk45(ctx, m, 0.0, t_end / 10, tol))  # warm-up (graph, buffers)
         m_plain, t_plain, st_plain = timed(lambda m: mmx.mmx_rk45(ctx, m, 0.0, t_end, tol))
-        m_sur, t_sur, (st, gl) = timed(lambda m: mmx.mmx_rk45_surrogate(
-            ctx, net.f, net.params, m, 0.0, t_end, tol, gate_tol=gate_tol, gate_cap=100000))
-        d_plain = float((m_plain.double() - mref).norm(dim=1).max())
-        d_sur = float((m_sur.double() - mref).norm(dim=1).max())
-        gl = np.asarray(gl)
-        out = dict(
-            workload=f"skyrmion film relaxation {n[0]}x{n[1]}x1, {R} replicas, 0..{t_end:g} s, "
-                     f"tol {tol:g}, gate {gate_tol:g}",
-            t_plain_s=t_plain, t_surrogate_s=t_sur, speedup=t_plain / t_sur,
-            dm_plain=d_plain, dm_surrogate=d_sur,
-            plain_accepted=st_plain.accepted, plain_rejected=st_plain.rejected,
-            accepted=st.accepted, surrogate_steps=st.surrogate_steps, exact_steps=st.exact_steps,
-            gate_checks=st.gate_checks, gate_failures=st.gate_failures,
-            surrogate_rejected=st.surrogate_rejected,
-            fallback_rate=(st.gate_failures / st.gate_checks) if st.gate_checks else None,
-            gate_error_quantiles=(dict(zip(["min", "p10", "p50", "p90", "max"],
-                                           np.quantile(gl, [0, .1, .5, .9, 1]).tolist()))
-                                  if gl.size else None),
-            gate_histogram=(np.histogram(np.log10(np.maximum(gl, 1e-12)),
-                                         bins=np.arange(-5, 1.01, 0.5))[0].tolist()
-                            if gl.size else None),
-            gate_histogram_bins="log10 edges -5.0, -4.5, ..., 1.0",
-        )
-        log(f"  plain {t_plain:.3f} s |dm| {d_plain:.2e}; learned {t_sur:.3f} s |dm| {d_sur:.2e}; "
-            f"kept {st.surrogate_steps}/{st.accepted}, gate failures {st.gate_failures}")
+        out["plain"] = dict(seconds=t_plain, dm=dm(m_plain), accepted=st_plain.accepted,
+                            rejected=st_plain.rejected)
+        log(f"  plain FP32 RK45: {t_plain:.3f} s, |dm| {dm(m_plain):.2e}, "
+            f"{st_plain.accepted} steps")
+        runs = []
+        for g in gates:
+            m_sur, t_sur, (st, gl) = timed(lambda m: mmx.mmx_rk45_surrogate(
+                ctx, net.f, net.params, m, 0.0, t_end, tol, gate_tol=g, gate_cap=100000))
+            gl = np.asarray(gl)
+            run = dict(
+                gate=g, seconds=t_sur, speedup=t_plain / t_sur, dm=dm(m_sur),
+                accepted=st.accepted, surrogate_steps=st.surrogate_steps,
+                exact_steps=st.exact_steps, gate_checks=st.gate_checks,
+                gate_failures=st.gate_failures, surrogate_rejected=st.surrogate_rejected,
+                fallback_rate=(st.gate_failures / st.gate_checks) if st.gate_checks else None,
+                gate_error_quantiles=(dict(zip(["min", "p10", "p50", "p90", "max"],
+                                               np.quantile(gl, [0, .1, .5, .9, 1]).tolist()))
+                                      if gl.size else None),
+                gate_histogram_log10=(np.histogram(np.log10(np.maximum(gl, 1e-12)),
+                                                   bins=np.arange(-5, 1.01, 0.5))[0].tolist()
+                                      if gl.size else None))
+            runs.append(run)
+            log(f"  learned, gate {g:g}: {t_sur:.3f} s (x{t_plain / t_sur:.3f}), "
+                f"|dm| {run['dm']:.2e}, kept {st.surrogate_steps}/{st.accepted}, "
+                f"gate failures {st.gate_failures}/{st.gate_checks}")
+        out["learned"] = runs
+        out["gate_histogram_bins"] = "log10 edges -5.0, -4.5, ..., 1.0"
+        # where the time of a learned run goes (HIP events around each launch)
+        mmx.mmx_profile_enable(ctx, 1)
+        m = _dev(m0)
+        mmx.mmx_rk45_surrogate(ctx, net.f, net.params, m, 0.0, t_end, tol, gate_tol=math.inf)
+        prof = mmx.mmx_profile_get(ctx)
+        mmx.mmx_profile_enable(ctx, 0)
+        out["learned_time_split_ms"] = {k: dict(total=v[0], launches=v[1])
+                                        for k, v in sorted(prof.items(), key=lambda kv: -kv[1][0])}
     finally:
         mmx.mmx_destroy(ctx)
     return out
@@ -290,38 +305,51 @@ def main(argv=None):
     ap.add_argument("--eval-replicas", type=int, default=8)
     ap.add_argument("--t-end", type=float, default=5e-11)
     ap.add_argument("--tol", type=float, default=1e-5)
-    ap.add_argument("--gate", type=float, default=1e-3)
+    ap.add_argument("--gate", type=float, nargs="+", default=[1e-3, 3e-2, math.inf],
+                    help="gate thresholds to evaluate (the first is the method's)")
     ap.add_argument("--out", default=None)
     ap.add_argument("--save-params", default=None)
+    ap.add_argument("--load-params", default=None,
+                    help="start from saved parameters (with --epochs 0: evaluation only)")
     a = ap.parse_args(argv)
     log = lambda s: print(s, flush=True)
     n = (a.n, a.n, 1)
-    log(f"generating {a.snapshots} snapshots of {a.n}x{a.n} films")
-    t0 = time.time()
-    m_all, t_all = generate(n, a.snapshots, a.replicas, a.every, log=log)
-    t_data = time.time() - t0
+    gate = a.gate[0]
     net = Net(a.n, a.n, batch=a.batch, use_mfma=not a.fp32_net)
     try:
-        n_train = a.snapshots - a.val
-        loss0, gate0 = evaluate(net, m_all, t_all, n_train, a.snapshots)
-        log(f"initial validation loss {loss0:.4e}")
-        hist, t_train = train(net, m_all, t_all, n_train, a.epochs, a.lr, log=log)
-        vloss, vgate = evaluate(net, m_all, t_all, n_train, a.snapshots)
-        log(f"validation loss {vloss:.4e}; total-field error median {np.median(vgate):.3e}, "
-            f"fraction <= {a.gate:g}: {(vgate <= a.gate).mean():.3f}")
-        ev = speedup(net, n, a.eval_replicas, a.t_end, a.tol, a.gate, log=log)
-        report = dict(
-            data=dict(snapshots=a.snapshots, train=n_train, val=a.val, replicas=a.replicas,
-                      every=a.every, styles=[s.name for s in STYLES], seconds=t_data),
-            net=dict(net.shape, params=net.n, batch=a.batch, bf16_mfma=not a.fp32_net),
-            train=dict(epochs=a.epochs, lr0=a.lr, schedule="cosine", seconds=t_train,
-                       loss_history=hist, val_loss_initial=loss0, val_loss=vloss,
-                       val_total_error_median=float(np.median(vgate)),
-                       val_total_error_p90=float(np.quantile(vgate, 0.9)),
-                       val_fraction_within_gate=float((vgate <= a.gate).mean())),
-            rk45=ev)
+        if a.load_params:
+            prm = np.fromfile(a.load_params, dtype=np.float32)
+            if prm.size != net.n:
+                raise SystemExit(f"{a.load_params}: {prm.size} floats, the network has {net.n}")
+            net.params.copy_(torch.from_numpy(prm))
+        report = dict(net=dict(net.shape, params=net.n, batch=a.batch,
+                               bf16_mfma=not a.fp32_net, loaded=a.load_params))
+        if a.snapshots > 0:
+            log(f"generating {a.snapshots} snapshots of {a.n}x{a.n} films")
+            t0 = time.time()
+            m_all, t_all = generate(n, a.snapshots, a.replicas, a.every, log=log)
+            t_data = time.time() - t0
+            n_train = a.snapshots - a.val
+            loss0, _ = evaluate(net, m_all, t_all, n_train, a.snapshots)
+            log(f"initial validation loss {loss0:.4e}")
+            hist, t_train = train(net, m_all, t_all, n_train, a.epochs, a.lr, log=log)
+            vloss, vgate = evaluate(net, m_all, t_all, n_train, a.snapshots)
+            log(f"validation loss {vloss:.4e}; total-field error median "
+                f"{np.median(vgate):.3e}, fraction <= {gate:g}: {(vgate <= gate).mean():.3f}")
+            report["data"] = dict(snapshots=a.snapshots, train=n_train, val=a.val,
+                                  replicas=a.replicas, every=a.every,
+                                  styles=[s.name for s in STYLES], seconds=t_data)
+            report["train"] = dict(
+                epochs=a.epochs, lr0=a.lr, schedule="cosine", seconds=t_train,
+                loss_history=hist, val_loss_initial=loss0, val_loss=vloss,
+                val_total_error_median=float(np.median(vgate)),
+                val_total_error_p90=float(np.quantile(vgate, 0.9)),
+                val_fraction_within_gate=float((vgate <= gate).mean()))
+            del m_all, t_all
+            torch.cuda.empty_cache()
         if a.save_params:
             net.params.cpu().numpy().tofile(a.save_params)
+        report["rk45"] = speedup(net, n, a.eval_replicas, a.t_end, a.tol, a.gate, log=log)
         text = json.dumps(report, indent=1)
         log(text)
         if a.out:

@@ -271,3 +271,42 @@ def test_graph_replays_equal_eager_steps(prec):
             mmx.mmx_destroy(ctx)
     assert np.array_equal(res["graph"][0], res["eager"][0])
     assert np.array_equal(res["graph"][1], res["eager"][1])
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_uneven_groups_in_one_context(prec):
+    """Groups of different sizes (films of several aspect ratios and a
+    two-layer film) advanced together by one captured Heun sequence: each
+    group equals its own single-group context bit for bit, and the oracle
+    to the precision bar (Methods, "Replica batching")."""
+    import paper_2608_15253_amd as mmx
+    terms = ("exchange", "anisotropy", "zeeman", "demag", "thermal")
+    shapes = [((32, 32, 1), 3), ((32, 8, 1), 2), ((12, 12, 2), 2), ((64, 16, 1), 2)]
+    cases = [Case(n, (4e-9, 4e-9, 4e-9), R=R, alpha=0.05, Ku=5e5, B=(0, 0, -0.15), T=100.0,
+                  seeds=list(replica_seeds(40 + g, R)), terms=terms)
+             for g, (n, R) in enumerate(shapes)]
+    m0s = [_round(uniform(c.n, (0.1, 0.0, 1.0), replicas=c.R), prec) for c in cases]
+    flat = np.concatenate([m.ravel() for m in m0s])
+    nsteps, dt = 70, 1e-14      # >= 64 steps: the captured-graph path
+    ctx = open_ctx(cases[0], prec, groups=cases)
+    try:
+        md = dev(flat, prec)
+        mmx.mmx_heun(ctx, md, dt, nsteps, 0)
+        got = host(md)
+    finally:
+        mmx.mmx_destroy(ctx)
+    off = 0
+    for c, m0 in zip(cases, m0s):
+        n = m0.size
+        mine = got[off:off + n].reshape(m0.shape)
+        off += n
+        one = open_ctx(c, prec)
+        try:
+            ms = dev(m0, prec)
+            mmx.mmx_heun(one, ms, dt, nsteps, 0)
+            single = host(ms)
+        finally:
+            mmx.mmx_destroy(one)
+        assert np.array_equal(mine, single), c.n
+        ref = oit.heun_run(m0, c.grid, c.material(), dt, nsteps, seed=np.array(c.seeds))
+        assert np.abs(mine - ref).max() <= TOLM[prec], c.n
