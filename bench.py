@@ -74,6 +74,111 @@ def read_traffic(kernel: str, src_hash: str):
     return float(m.group(1)) if m else None
 
 
+COPY_MIB = 256   # calibration copy: COPY_MIB read + COPY_MIB written per launch
+
+
+def traffic_probe(args):
+    """Workload of the counter runs: three launches of a plain elementwise copy
+    of known size (torch's scalar multiply, out-of-place) for calibration, then
+    the benchmark's Heun steps on all replicas."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import replica_seeds, uniform
+    a = torch.ones(COPY_MIB * 2**20 // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.mul(a, 2.0, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    R = args.replicas
+    seeds = replica_seeds(3, R)
+    ctx = setup(R, mmx.MMX_F32, seeds)
+    m = torch.tensor(uniform((64, 64, 1), replicas=R), dtype=torch.float32,
+                     device="cuda:0").contiguous()
+    mmx.mmx_set_path(ctx, mmx.MMX_PATH_STAGED)
+    mmx.mmx_profile_enable(ctx, 1)   # plain launches (no graph), as in the kernel table
+    mmx.mmx_heun(ctx, m, 1e-14, 20, 0, None)
+    mmx.mmx_profile_enable(ctx, 0)
+    torch.cuda.synchronize()
+    mmx.mmx_destroy(ctx)
+    print(json.dumps({"traffic_probe": "done", "replicas": R}), flush=True)
+
+
+def _pmc_means(path, counter):
+    """Mean counter value per kernel name (KiB per dispatch) from a rocprofv3
+    counter_collection.csv."""
+    import csv
+    acc = {}
+    with open(path) as fh:
+        for row in csv.DictReader(fh):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row["Kernel_Name"]
+            v = float(row["Counter_Value"])
+            s, n = acc.get(name, (0.0, 0))
+            acc[name] = (s + v, n + 1)
+    return {k: (s / n, n) for k, (s, n) in acc.items()}
+
+
+def traffic_summary(fetch_csv, write_csv, cmd, R):
+    """Markdown table: per kernel, FETCH_SIZE and WRITE_SIZE per dispatch,
+    scaled by the calibration copy (known bytes / counted bytes), and the
+    algorithmic bytes of the Heun kernels for comparison."""
+    fetch = _pmc_means(fetch_csv, "FETCH_SIZE")
+    write = _pmc_means(write_csv, "WRITE_SIZE")
+    copy_bytes = COPY_MIB * 2**20
+    def find(table, key):
+        for k, v in table.items():
+            if key in k:
+                return v
+        return None
+    cf = find(fetch, "MulFunctor") or find(fetch, "elementwise")
+    cw = find(write, "MulFunctor") or find(write, "elementwise")
+    sf = copy_bytes / (cf[0] * 1024) if cf else 1.0
+    sw = copy_bytes / (cw[0] * 1024) if cw else 1.0
+    lines = [
+        "# HBM traffic per launch: thermal switching batch, 1024 x 64x64x1, FP32 Heun (staged)",
+        "",
+        f"source_hash: {kernel_source_hash()}",
+        "",
+        "Commands (each counter in its own run; then this table):",
+        "",
+        "```",
+        cmd.strip() or "(not recorded)",
+        "```",
+        "",
+        f"Calibration: a {COPY_MIB} MiB elementwise copy reads/writes {copy_bytes} B; the "
+        f"counters report {cf[0] if cf else float('nan'):.1f} KiB fetched and "
+        f"{cw[0] if cw else float('nan'):.1f} KiB written per launch, so FETCH_SIZE is scaled "
+        f"by {sf:.4f} and WRITE_SIZE by {sw:.4f}.",
+        "",
+        "| kernel | dispatches | FETCH KiB | WRITE KiB | algorithmic bytes | "
+        "traffic / algorithmic | value |",
+        "|---|---|---|---|---|---|---|",
+    ]
+    for short in ("k_xfwd", "k_yconv", "k_fields_heun1", "k_fields_heun2",
+                  "k_fields<float, 2>", "k_fields<float, 3>"):
+        f = find(fetch, short)
+        w = find(write, short)
+        if not f or not w:
+            continue
+        label = {"k_fields<float, 2>": "k_fields_heun1",
+                 "k_fields<float, 3>": "k_fields_heun2"}.get(short, short)
+        traffic = f[0] * 1024 * sf + w[0] * 1024 * sw
+        alg = algorithmic_bytes(label, R, 64, 64, 4)
+        ratio = f"{traffic / alg:.2f}" if alg else "-"
+        lines.append(f"| {label} | {f[1]} | {f[0]:.1f} | {w[0]:.1f} | "
+                     f"{alg:.0f} | {ratio} | {traffic:.0f} |")
+    lines.append("")
+    lines.append("All kernels seen (mean KiB per dispatch):")
+    lines.append("")
+    for k in sorted(set(fetch) | set(write)):
+        f, w = fetch.get(k), write.get(k)
+        lines.append(f"- `{k[:110]}`: fetch {f[0] if f else float('nan'):.1f}, "
+                     f"write {w[0] if w else float('nan'):.1f}")
+    return "\n".join(lines) + "\n"
+
+
 def setup(R, prec, seeds, n=(64, 64, 1)):
     import torch
     import paper_2608_15253_amd as mmx
@@ -126,10 +231,21 @@ def main():
     ap.add_argument("--prof-steps", type=int, default=50)
     ap.add_argument("--prec", choices=["f32", "f64"], default="f32")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--traffic-probe", action="store_true",
+                    help="only a calibration copy and a few Heun steps (for counter runs)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the HBM traffic table from two rocprofv3 --pmc runs")
+    ap.add_argument("--traffic-cmd", default="", help="command line recorded in the summary")
     args = ap.parse_args()
+    if args.traffic_summary:
+        print(traffic_summary(*args.traffic_summary, args.traffic_cmd, args.replicas))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.traffic_probe:
+        traffic_probe(args)
+        return
     import torch
     import paper_2608_15253_amd as mmx
     from workloads import replica_seeds, uniform

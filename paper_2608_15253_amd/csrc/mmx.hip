@@ -7,6 +7,7 @@
 #include <cstring>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mmx.h"
@@ -14,6 +15,7 @@
 #include "fused.h"
 #include "kernels.h"
 #include "setup_kernels.h"
+#include "yconv_reg.h"
 
 using namespace mmx;
 
@@ -480,6 +482,31 @@ mmx_status launch_fields(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
   return MMX_OK;
 }
 
+// Register-resident column convolution for FP32 films whose padded y length
+// is 64, 128 or 256 (split 8 x 8, 8 x 16, 16 x 16); false: not applicable.
+template <typename T>
+bool launch_yconv_reg(const Group& G, const YArgs<T>& y, hipStream_t s) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return false;
+  } else {
+    const bool prune = G.plan_yf.prune != 0;
+    auto go = [&](auto kern, int NC) {
+      dim3 grid((G.Kx + NC - 1) / NC, 1, G.R);
+      kern<<<grid, 64, 0, s>>>(y);
+      return true;
+    };
+    switch (G.Py) {
+      case 64: return prune ? go(k_yconv_reg<float, 8, 8, true>, 8)
+                            : go(k_yconv_reg<float, 8, 8, false>, 8);
+      case 128: return prune ? go(k_yconv_reg<float, 8, 16, true>, 8)
+                             : go(k_yconv_reg<float, 8, 16, false>, 8);
+      case 256: return prune ? go(k_yconv_reg<float, 16, 16, true>, 4)
+                             : go(k_yconv_reg<float, 16, 16, false>, 4);
+      default: return false;
+    }
+  }
+}
+
 // stage combine m + dt sum_j c_j k_j (optionally normalised) fused with the x
 // forward transform of the demag convolution when `demag` is set
 template <typename T>
@@ -541,9 +568,11 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
       y.tw = G.tw_y.as<cpx<T>>();
       y.pf = G.plan_yf;
       y.pi = G.plan_yi;
-      dim3 grid((G.Kx + G.Wy - 1) / G.Wy, 1, G.R);
       ProfScope ps(ctx->prof, "k_yconv", s);
-      k_yconv<T><<<grid, kBlock, (2 * (size_t)3 * G.Wy * G.Py + G.Py) * cpxb<T>(), s>>>(y);
+      if (!launch_yconv_reg<T>(G, y, s)) {
+        dim3 grid((G.Kx + G.Wy - 1) / G.Wy, 1, G.R);
+        k_yconv<T><<<grid, kBlock, (2 * (size_t)3 * G.Wy * G.Py + G.Py) * cpxb<T>(), s>>>(y);
+      }
       HIP_TRY(hipGetLastError());
     } else {
       y.W = G.Wy;

@@ -1,0 +1,118 @@
+// Column convolution of 2-D films with the columns held in registers (device
+// code): y transform, tensor product and inverse y transform of N1 N2-point
+// columns, one wave per NC = 64 / N1 spectrum columns.
+//
+// A column x[y], y = a + N2 b (a < N2, b < N1), has the spectrum
+//   X[c + N1 d] = sum_a w_N2^(a d) w^(a c) sum_b x[a + N2 b] w_N1^(b c)
+// (w = exp(-2 pi i / (N1 N2))).  Lane q of a column first holds the columns
+// a = q, q + N1, ... and takes the N1-point transforms over b; the products
+// Y[a][c] are transposed through LDS so that lane q then holds all a for
+// c = q and takes the N2-point transform over a, which leaves it the spectrum
+// rows ky = q + N1 d of all three components: the tensor product is local.
+// The inverse runs the same steps backwards (N2-point over d, twiddle,
+// transpose, N1-point over c).  Compared with the LDS Stockham kernel this
+// moves each column through LDS twice instead of once per radix pass.  With
+// a zero-padded (pruned) axis only b < N1/2 carries input and only those rows
+// are written back.  The arithmetic differs from the Stockham kernel only in
+// the order of the butterflies (round-off level).
+#pragma once
+#include "common.h"
+#include "fft_lds.h"
+#include "kernels.h"
+
+namespace mmx {
+
+template <typename T, bool INV, int R>
+__device__ inline void dft_reg(cpx<T>* v) {
+  if constexpr (R == 2) Dft<T, INV>::r2(v);
+  if constexpr (R == 4) Dft<T, INV>::r4(v);
+  if constexpr (R == 8) Dft<T, INV>::r8(v);
+  if constexpr (R == 16) Dft<T, INV>::r16(v);
+}
+
+template <typename T, int N1, int N2, bool PRUNE>
+__global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
+  static_assert(N2 % N1 == 0 && 64 % N1 == 0, "column split");
+  constexpr int n = N1 * N2, NC = 64 / N1, S2 = N2 / N1, STR = N2 + 1;
+  constexpr int NB = PRUNE ? N1 / 2 : N1;  // input rows (forward) = output rows (inverse) per a
+  __shared__ cpx<T> E[NC * N1 * STR];
+  if (a.done && *a.done) return;
+  const int lane = threadIdx.x, wc = lane / N1, q = lane - wc * N1;
+  const int kx = blockIdx.x * NC + wc;
+  const bool live = kx < a.Kx;
+  const int Kx = a.Kx;
+  const size_t plane = (size_t)a.Sy * Kx;  // one component of one replica (nz = 1)
+  cpx<T>* S = a.S + (size_t)blockIdx.z * 3 * plane + kx;
+  cpx<T>* Ew = E + wc * N1 * STR;
+  const cpx<T>* __restrict__ tw = a.tw;
+  cpx<T> X[3][N2];
+  // forward, step 1 per component (the next component's loads are issued
+  // before the transpose of the current one): N1-point transforms over b for
+  // a = q + N1 s, twiddles, transpose so that lane q gathers Y[a][q], all a
+  cpx<T> v[S2][N1];
+  auto load = [&](int c) {
+#pragma unroll
+    for (int s = 0; s < S2; ++s)
+#pragma unroll
+      for (int b = 0; b < N1; ++b)
+        v[s][b] = (b < NB && live) ? S[c * plane + (size_t)(q + N1 * s + N2 * b) * Kx]
+                                   : cpx<T>{0, 0};
+  };
+  load(0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int s = 0; s < S2; ++s) {
+      const int av = q + N1 * s;
+      dft_reg<T, false, N1>(v[s]);
+      Ew[av] = v[s][0];
+#pragma unroll
+      for (int cc = 1; cc < N1; ++cc) Ew[cc * STR + av] = cmul(v[s][cc], tw[(av * cc) & (n - 1)]);
+    }
+    if (c < 2) load(c + 1);
+    __syncthreads();
+#pragma unroll
+    for (int av = 0; av < N2; ++av) X[c][av] = Ew[q * STR + av];
+    __syncthreads();
+  }
+  // forward, step 2: N2-point transforms over a -> rows ky = q + N1 d
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dft_reg<T, false, N2>(X[c]);
+  if (live) {
+    const size_t cs = (size_t)a.Tz * a.Ty * Kx;
+#pragma unroll
+    for (int d = 0; d < N2; ++d) {
+      const int ky = q + N1 * d;
+      const bool lo = 2 * ky <= n;
+      const int ty = lo ? ky : n - ky;
+      const T sy = lo ? T(1) : T(-1);
+      tensor_apply(a.Nt, cs, (size_t)ty * Kx + kx, sy, T(1), sy, false, X[0][d], X[1][d],
+                   X[2][d]);
+    }
+  }
+  // inverse per component: N2-point transforms over d, conjugate twiddles,
+  // transpose back, N1-point transforms over c for a = q + N1 s, store
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    dft_reg<T, true, N2>(X[c]);
+    Ew[q * STR] = X[c][0];
+#pragma unroll
+    for (int av = 1; av < N2; ++av) Ew[q * STR + av] = cmulc(X[c][av], tw[(av * q) & (n - 1)]);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S2; ++s) {
+      const int av = q + N1 * s;
+      cpx<T> u[N1];
+#pragma unroll
+      for (int cc = 0; cc < N1; ++cc) u[cc] = Ew[cc * STR + av];
+      dft_reg<T, true, N1>(u);
+      if (live) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) S[c * plane + (size_t)(av + N2 * b) * Kx] = u[b];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace mmx
