@@ -49,11 +49,13 @@ def algorithmic_bytes(kernel: str, R: int, nx: int, ny: int, w: int) -> float | 
     N = nx * ny
     spec = 3 * ny * (nx + 1) * 2 * w      # half spectrum of one replica
     state = 3 * N * w                      # one magnetisation-sized array
+    # the Heun epilogues also write the half spectrum of the state they
+    # produce (the x transform of the next evaluation)
     per = {
         "k_xfwd": state + spec,
         "k_yconv": 2 * spec,
-        "k_fields_heun1": spec + state + 2 * state,
-        "k_fields_heun2": spec + 3 * state + state,
+        "k_fields_heun1": spec + state + 2 * state + spec,
+        "k_fields_heun2": spec + 3 * state + state + spec,
     }
     if kernel not in per:
         return None
@@ -179,6 +181,137 @@ def traffic_summary(fetch_csv, write_csv, cmd, R):
     return "\n".join(lines) + "\n"
 
 
+def _ctx_for(workloads, prec):
+    """One context with a group per workload (uniform material per group)."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import replica_seeds
+    grps = [mmx.make_group(w.n, w.cell, w.pbc, w.images, w.replicas) for w in workloads]
+    ctx = mmx.mmx_create(grps, prec)
+    mmx.mmx_set_stream(ctx, torch.cuda.current_stream().cuda_stream)
+    terms = mmx.MMX_EXCH | mmx.MMX_DEMAG
+    for g, w in enumerate(workloads):
+        mmx.mmx_set_material(ctx, g, Ms=w.Ms, A=w.A, alpha=w.alpha, Ku=w.Ku, u=w.u, D=w.D)
+        mmx.mmx_set_field(ctx, g, w.B)
+        terms |= (mmx.MMX_DMI_INTERFACIAL if w.D else 0) | \
+            (mmx.MMX_ANIS_UNIAXIAL if w.Ku else 0) | (mmx.MMX_ZEEMAN if any(w.B) else 0)
+        if w.T > 0:
+            base = w.extra.get("seed_base", 7 + g)
+            mmx.mmx_set_thermal(ctx, g, [w.T] * w.replicas, replica_seeds(base, w.replicas))
+            terms |= mmx.MMX_THERMAL
+    mmx.mmx_set_terms(ctx, terms)
+    mmx.mmx_build_demag(ctx)
+    return ctx
+
+
+def bench_uneven(args):
+    """Replica groups of uneven sizes (256 replicas each of 32x32x1, 128x32x1,
+    96x96x2 and 256x64x1 films, T = 100 K) advanced by one Heun call per
+    timed block, FP32."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import uneven_groups, uniform
+    ws = uneven_groups(256)
+    ctx = _ctx_for(ws, mmx.MMX_F32)
+    mmx.mmx_autotune(ctx)
+    m = torch.tensor(np.concatenate([uniform(w.n, replicas=w.replicas).ravel() for w in ws]),
+                     dtype=torch.float32, device="cuda:0")
+    cells = sum(w.replicas * w.n[0] * w.n[1] * w.n[2] for w in ws)
+    dt = ws[0].extra["dt"]
+    mmx.mmx_heun(ctx, m, dt, args.warmup, 0, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mmx.mmx_heun(ctx, m, dt, args.steps, args.warmup, None)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    finite = bool(torch.isfinite(m).all())
+    mmx.mmx_destroy(ctx)
+    return {"metric": "LLG cell-steps/s, uneven replica groups in one context",
+            "value": cells * args.steps / el, "unit": "cell-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "uneven_groups_heun",
+                       "groups": [f"{w.n[0]}x{w.n[1]}x{w.n[2]}x{w.replicas}" for w in ws],
+                       "T_K": ws[0].T, "dt_s": dt}, "finite": finite}
+
+
+def bench_closure(args):
+    """256x256x32 block of 4 nm cubes (Landau seed), FP32 RK45 at tol 1e-6
+    from 0 to t_end: accepted steps per second and cell-steps/s."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import closure_block_fp32, landau_seed
+    w = closure_block_fp32()
+    ctx = _ctx_for([w], mmx.MMX_F32)
+    mmx.mmx_autotune(ctx)
+    t_end = args.t_end or 2e-11
+    m = torch.tensor(landau_seed(w.n)[None], dtype=torch.float32, device="cuda:0").contiguous()
+    warm = m.clone()
+    mmx.mmx_rk45(ctx, warm, 0.0, t_end / 20, w.extra["tol"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = mmx.mmx_rk45(ctx, m, 0.0, t_end, w.extra["tol"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    E = torch.zeros((1, 6), dtype=torch.float64, device="cuda:0")
+    mmx.mmx_energy(ctx, m, E)
+    mmx.mmx_destroy(ctx)
+    cells = w.n[0] * w.n[1] * w.n[2]
+    return {"metric": "RK45 cell-steps/s (accepted steps x cells / s), 3-D closure block",
+            "value": cells * st.accepted / el, "unit": "cell-steps/s", "n_gpus": 1,
+            "ms_per_step": el / max(st.accepted, 1) * 1e3, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "closure_block_256x256x32_rk45", "t_end_s": t_end,
+                       "tol": w.extra["tol"]},
+            "accepted": st.accepted, "rejected": st.rejected, "seconds": el,
+            "energy_J": E[0].tolist()}
+
+
+def bench_skyrmion512(args):
+    """512x512 periodic skyrmion film, RK45 from 0 to t_end (default 2 ns) in
+    FP32 and in FP64: time, accepted steps, and the FP32 - FP64 differences
+    in m, energy and topological charge (the precision form's comparison)."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import neel_skyrmions, skyrmion_film_fp32
+    w = skyrmion_film_fp32()
+    x = w.extra
+    t_end = args.t_end or x["t_end"]
+    m0, _, _ = neel_skyrmions(w.n, w.cell, x["count"], x["rmin"], x["rmax"], seed=x["seed"],
+                              width=5.05e-9, periodic=True)
+    m0 = m0[None].astype(np.float32).astype(np.float64)
+    out = {}
+    for prec, dt_ in ((mmx.MMX_F32, torch.float32), (mmx.MMX_F64, torch.float64)):
+        ctx = _ctx_for([w], prec)
+        m = torch.tensor(m0, dtype=dt_, device="cuda:0").contiguous()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = mmx.mmx_rk45(ctx, m, 0.0, t_end, x["tol"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        E = torch.zeros((1, 6), dtype=torch.float64, device="cuda:0")
+        Q = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        mmx.mmx_energy(ctx, m, E)
+        mmx.mmx_topological_charge(ctx, m, Q)
+        out[prec] = (m.double().cpu().numpy(), E[0].tolist(), float(Q[0]), st, el)
+        mmx.mmx_destroy(ctx)
+        print(f"  prec {prec}: {el:.1f} s, {st.accepted} steps", file=sys.stderr, flush=True)
+    m32, e32, q32, s32, t32 = out[mmx.MMX_F32]
+    m64, e64, q64, s64, t64 = out[mmx.MMX_F64]
+    cells = w.n[0] * w.n[1]
+    return {"metric": "RK45 cell-steps/s (accepted steps x cells / s), FP32 precision form",
+            "value": cells * s32.accepted / t32, "unit": "cell-steps/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "skyrmion_film_512x512_rk45", "t_end_s": t_end,
+                       "tol": x["tol"]},
+            "fp32": {"seconds": t32, "accepted": s32.accepted, "rejected": s32.rejected,
+                     "energy_J": e32, "Q": q32},
+            "fp64": {"seconds": t64, "accepted": s64.accepted, "rejected": s64.rejected,
+                     "energy_J": e64, "Q": q64},
+            "max_dm_fp32_vs_fp64": float(np.abs(m32 - m64).max()),
+            "rel_dE_total": abs(e32[5] - e64[5]) / abs(e64[5]), "dQ": abs(q32 - q64)}
+
+
 def setup(R, prec, seeds, n=(64, 64, 1)):
     import torch
     import paper_2608_15253_amd as mmx
@@ -236,15 +369,25 @@ def main():
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the HBM traffic table from two rocprofv3 --pmc runs")
     ap.add_argument("--traffic-cmd", default="", help="command line recorded in the summary")
+    ap.add_argument("--workload", default="switching",
+                    choices=["switching", "uneven", "closure", "skyrmion512"],
+                    help="switching: the benchmark line; the others measure the other "
+                         "workload configurations (one JSON line each)")
+    ap.add_argument("--t-end", type=float, default=None,
+                    help="closure / skyrmion512: integration horizon (s)")
     args = ap.parse_args()
     if args.traffic_summary:
         print(traffic_summary(*args.traffic_summary, args.traffic_cmd, args.replicas))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     if args.traffic_probe:
         traffic_probe(args)
+        return
+    if args.workload != "switching":
+        print(json.dumps({"uneven": bench_uneven, "closure": bench_closure,
+                          "skyrmion512": bench_skyrmion512}[args.workload](args)))
         return
     import torch
     import paper_2608_15253_amd as mmx

@@ -203,7 +203,7 @@ mmx_status mmx_autotune(mmx_ctx* ctx);
 
 /* ------------------------------------------------------------------------
  * Learned demag surrogate: a Fourier neural operator h = f(m) ~ H_demag / Ms
- * for films of H x W cells (the build's learned form; not in the paper).
+ * for films of H x W cells (an extension; not in the paper).
  * Network: features [m, x/W - 1/2, y/H - 1/2] -> 1x1 lift to C channels ->
  * L layers of [truncated DFT (kx < M1, ky in [0, M2) u [H - M2, H)) ->
  * per-mode complex C x C mixing -> inverse real DFT, plus a 1x1 map and

@@ -19,7 +19,9 @@ mpmath Newell values) and invariants (|m| = 1, m . dm/dt = 0, energy decay).
 Parity unpinned: the exact Philox stream (no published known-answer vectors are
 available here; checked statistically and bit-for-bit against the GPU), the
 interfacial-DMI edge ghosts against another code (closed forms pin the bulk
-stencil only), long-horizon thermal trajectories (chaotic; statistical only).
+stencil only), long-horizon thermal trajectories (chaotic; statistical only),
+and the behaviour of trained network weights (the network's arithmetic and the
+learned-stage attempt are pinned; what training reaches is not).
 """
 from .constants import GAMMA0, MU0, KB
 from .problem import Grid, Material

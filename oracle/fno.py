@@ -1,7 +1,7 @@
 """FP64 reference of the learned demag surrogate (a Fourier neural operator).
 
-Not part of the paper: the build's learned form asks for a small spectral
-convolution neural operator (width 32, 12 modes, 4 layers) that predicts the
+Not part of the paper: an extension in which a small spectral
+convolution neural operator (width 32, 12 modes, 4 layers) predicts the
 demagnetising field h = H_demag / Ms of a film from m, is trained on fields the
 method itself produces, and stands in for the exact demag in intermediate RK45
 stages.  This module is the plain definition the GPU forward and backward
@@ -9,7 +9,7 @@ kernels are checked against; gradients are pinned by central differences.
 
 Layout: activations (B, C, H, W) with x (W) fastest, as the magnetisation.
 
-Network (reading of the brief's description):
+Network (the reading taken here):
   X0 = [m_x, m_y, m_z, x/W - 1/2, y/H - 1/2]                      (5 channels)
   V  = P X0 + p                                                    (lift, 1x1)
   for l = 0..L-1:

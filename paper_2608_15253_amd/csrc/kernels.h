@@ -48,9 +48,74 @@ __device__ inline const cpx<T>* stage_table(cpx<T>* dst, const cpx<T>* __restric
   return dst;
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin in launch order.  This
+// relabels a 3-D grid so that blocks with neighbouring logical indices
+// (adjacent row or column tiles of one replica, which share cache lines)
+// run on the same XCD and its L2.  A bijection on the blocks of the grid.
+__device__ inline void xcd_block(int& bx, int& by, int& bz) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int nblk = gx * gy * gridDim.z;
+  const int lin = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int per = nblk / 8;
+  const int lg = lin < 8 * per ? (lin % 8) * per + lin / 8 : lin;
+  bx = lg % gx;
+  by = (lg / gx) % gy;
+  bz = lg / (gx * gy);
+}
+
+// Moves elements t = 0 .. total-1 with v = ld(t); st(t, v), eight per thread
+// at a time: the eight loads are issued before the first store, so their
+// global-memory latencies overlap instead of adding up.  Whole workgroup of
+// kBlock threads.
+constexpr int kBatch = 8;
+template <typename V, typename Ld, typename St>
+__device__ inline void batched_move(int total, Ld ld, St st) {
+  for (int base = 0; base < total; base += kBatch * kBlock) {
+    V v[kBatch];
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int t = base + i * kBlock + (int)threadIdx.x;
+      if (t < total) v[i] = ld(t);
+    }
+#pragma unroll
+    for (int i = 0; i < kBatch; ++i) {
+      const int t = base + i * kBlock + (int)threadIdx.x;
+      if (t < total) st(t, v[i]);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // x forward transform with stage combine
 // ---------------------------------------------------------------------------
+// Half spectrum rows y0 .. y0+L-1 (plane z of replica r) from the
+// half-length complex transforms X of their packed cell pairs (line c L + l):
+// the real-to-complex split S[kx] = E + conj(W^kx) O with W = exp(-2 pi i / Px).
+template <typename T>
+__device__ inline void xfwd_store(const cpx<T>* X, const cpx<T>* __restrict__ wpost,
+                                  cpx<T>* __restrict__ S, int r, int z, int y0, int L, int hx,
+                                  int Kx, int ny, int nz, int Sy, int xone) {
+  const int nl = 3 * L;
+  for (int t = threadIdx.x; t < nl * Kx; t += blockDim.x) {
+    const int line = t / Kx, kx = t - line * Kx;
+    const int c = udiv(line, L), l = line - c * L, y = y0 + l;
+    if (y >= ny) continue;
+    cpx<T> out;
+    if (xone) {
+      out = {X[line].re, T(0)};
+    } else {
+      const cpx<T> Zk = X[line * hx + (kx == hx ? 0 : kx)];
+      cpx<T> Zc = X[line * hx + (kx == 0 ? 0 : hx - kx)];
+      Zc.im = -Zc.im;
+      const cpx<T> E = {T(0.5) * (Zk.re + Zc.re), T(0.5) * (Zk.im + Zc.im)};
+      const cpx<T> O = {T(0.5) * (Zk.re - Zc.re), T(0.5) * (Zk.im - Zc.im)};
+      const cpx<T> w = wpost[kx];
+      out = {E.re + (w.re * O.im + w.im * O.re), E.im - (w.re * O.re - w.im * O.im)};
+    }
+    S[((((size_t)r * 3 + c) * nz + z) * Sy + y) * Kx + kx] = out;
+  }
+}
+
 template <typename T>
 struct XArgs {
   const T* m;
@@ -79,12 +144,16 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
   cpx<T>* Bf = A + nl * hx;
   const cpx<T>* tw = a.do_fft ? stage_table(Bf + nl * hx, a.tw, hx) : nullptr;
   const cpx<T>* wpost = a.do_fft ? stage_table(Bf + nl * hx + hx, a.wpost, hx + 1) : nullptr;
-  const int r = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * L;
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int r = bz, z = by, y0 = bx * L;
   const size_t rb = (size_t)r * 3 * a.N;
   const T dt = a.dtdev ? (T)(*a.dtdev) : (T)a.dth;
   const int npair = a.xone ? 1 : (a.nx + 1) / 2;
-  for (int t = threadIdx.x; t < L * hx; t += blockDim.x) {
-    const int l = udiv(t, hx), k = t - l * hx, y = y0 + l;
+  // a pruned transform never reads k >= hx/2 = npair: those slots stay unfilled
+  const int kw = (a.do_fft && !a.plan.prune) ? hx : npair;
+  for (int t = threadIdx.x; t < L * kw; t += blockDim.x) {
+    const int l = udiv(t, kw), k = t - l * kw, y = y0 + l;
     cpx<T> v[3] = {{0, 0}, {0, 0}, {0, 0}};
     if (y < a.ny && k < npair) {
 #pragma unroll
@@ -122,25 +191,7 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
   if (!a.do_fft) return;
   __syncthreads();
   const cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.plan, tw);
-  const int Kx = a.Kx;
-  for (int t = threadIdx.x; t < nl * Kx; t += blockDim.x) {
-    const int line = t / Kx, kx = t - line * Kx;
-    const int c = udiv(line, L), l = line - c * L, y = y0 + l;
-    if (y >= a.ny) continue;
-    cpx<T> out;
-    if (a.xone) {
-      out = {X[line].re, T(0)};
-    } else {
-      const cpx<T> Zk = X[line * hx + (kx == hx ? 0 : kx)];
-      cpx<T> Zc = X[line * hx + (kx == 0 ? 0 : hx - kx)];
-      Zc.im = -Zc.im;
-      const cpx<T> E = {T(0.5) * (Zk.re + Zc.re), T(0.5) * (Zk.im + Zc.im)};
-      const cpx<T> O = {T(0.5) * (Zk.re - Zc.re), T(0.5) * (Zk.im - Zc.im)};
-      const cpx<T> w = wpost[kx];
-      out = {E.re + (w.re * O.im + w.im * O.re), E.im - (w.re * O.re - w.im * O.im)};
-    }
-    a.S[((((size_t)r * 3 + c) * a.nz + z) * a.Sy + y) * Kx + kx] = out;
-  }
+  xfwd_store(X, wpost, a.S, r, z, y0, L, hx, a.Kx, a.ny, a.nz, a.Sy, a.xone);
 }
 
 // ---------------------------------------------------------------------------
@@ -315,7 +366,7 @@ struct FArgs {
   const unsigned long long* stepdev;  // if set, the step index is read here (graph replays)
   double dt_th;
   const T* m;
-  const cpx<T>* S;
+  cpx<T>* S;
   FftPlan plan;
   const cpx<T>* tw;
   const cpx<T>* wpost;
@@ -332,6 +383,8 @@ struct FArgs {
   const int* done;
   const float* hext;  // if set (demag term off): Hd = hext_scale * hext + (0, 0, hext_mz m_z)
   T hext_scale, hext_mz;
+  int fwd;            // Heun epilogues: also x-transform the new state into S
+  FftPlan plan_f;     // forward x plan (pruned like the one of k_xfwd)
   T* hd_out;          // if set: the exact demag field is also stored here
 };
 
@@ -410,37 +463,59 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
   const int hx = a.hx, L = a.L, nl = 3 * L;
   cpx<T>* Bf = A + nl * hx;
-  __shared__ double red[kBlock * 5];
-  const int r = blockIdx.z, z = blockIdx.y, y0 = blockIdx.x * L;
+  __shared__ double red[kBlock * (MODE == FM_ENERGY ? 5 : 1)];
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int r = bz, z = by, y0 = bx * L;
   const size_t rb = (size_t)r * 3 * a.N;
   const bool demag = (a.terms & T_DEMAG) != 0;
   const T* Hd = nullptr;  // real view of the inverse transform, line stride 2 hx
+  cpx<T>* Hbuf = nullptr;
+  const cpx<T>* tw_lds = nullptr;
   if (demag) {
     const cpx<T>* tw = stage_table(Bf + nl * hx, a.tw, hx);
+    tw_lds = tw;
     const int Kx = a.Kx;
-    for (int t = threadIdx.x; t < nl * hx; t += blockDim.x) {
-      const int line = udiv(t, hx), k = t - line * hx;
-      const int c = udiv(line, L), l = line - c * L, y = y0 + l;
-      cpx<T> Z = {0, 0};
-      if (y < a.ny) {
-        const cpx<T>* row = a.S + ((((size_t)r * 3 + c) * a.nz + z) * a.Sy + y) * Kx;
-        if (a.xone) {
-          Z = {row[0].re, T(0)};
-        } else {
-          const cpx<T> Xk = row[k];
-          cpx<T> Xc = row[hx - k];
-          Xc.im = -Xc.im;
-          const cpx<T> E = cadd(Xk, Xc);
-          const cpx<T> D = csub(Xk, Xc);
-          const cpx<T> w = a.wpost[k];
-          const cpx<T> O = cmulc(D, w);  // D * conj(W^k)
-          Z = {E.re - O.im, E.im + O.re};
-        }
-      }
-      A[line * hx + k] = Z;
-    }
+    batched_move<cpx<T>>(
+        nl * hx,
+        [&](int t) {
+          const int line = udiv(t, hx), k = t - line * hx;
+          const int c = udiv(line, L), l = line - c * L, y = y0 + l;
+          cpx<T> Z = {0, 0};
+          if (y < a.ny) {
+            const cpx<T>* row = a.S + ((((size_t)r * 3 + c) * a.nz + z) * a.Sy + y) * Kx;
+            if (a.xone) {
+              Z = {row[0].re, T(0)};
+            } else {
+              const cpx<T> Xk = row[k];
+              cpx<T> Xc = row[hx - k];
+              Xc.im = -Xc.im;
+              const cpx<T> E = cadd(Xk, Xc);
+              const cpx<T> D = csub(Xk, Xc);
+              const cpx<T> w = a.wpost[k];
+              const cpx<T> O = cmulc(D, w);  // D * conj(W^k)
+              Z = {E.re - O.im, E.im + O.re};
+            }
+          }
+          return Z;
+        },
+        [&](int t, cpx<T> Z) { A[t] = Z; });
     __syncthreads();
-    Hd = reinterpret_cast<const T*>(lds_fft<T, true>(A, Bf, nl, a.plan, tw));
+    Hbuf = lds_fft<T, true>(A, Bf, nl, a.plan, tw);
+    Hd = reinterpret_cast<const T*>(Hbuf);
+  }
+  // Heun epilogues with `fwd`: the new state of the block's rows is packed
+  // into the free LDS buffer (real view, line c L + l) and x-transformed
+  // after the cell loop, so the next field evaluation needs no k_xfwd pass
+  constexpr bool kFwdMode = (MODE == FM_HEUN1 || MODE == FM_HEUN2);
+  const bool fwd = kFwdMode && demag && a.fwd;
+  T* F = fwd ? reinterpret_cast<T*>(Hbuf == A ? Bf : A) : nullptr;
+  if (fwd && !a.plan_f.prune) {
+    const int tail = 2 * hx - a.nx;  // zero input beyond the last cell
+    for (int t = threadIdx.x; t < nl * tail; t += blockDim.x) {
+      const int line = t / tail;
+      F[line * 2 * hx + a.nx + (t - line * tail)] = T(0);
+    }
   }
   const int ncell_blk = L * a.nx;
   const double dt_state = a.dtdev ? *a.dtdev : a.dth;
@@ -503,8 +578,10 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
     } else if (MODE == FM_HEUN1) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
+        const T mn = mc[c] + dt * k[c];
         a.k1[rb + (size_t)c * a.N + cell] = k[c];
-        a.mout[rb + (size_t)c * a.N + cell] = mc[c] + dt * k[c];
+        a.mout[rb + (size_t)c * a.N + cell] = mn;
+        if (fwd) F[(c * L + l) * 2 * hx + x] = mn;
       }
     } else if (MODE == FM_HEUN2) {
       T mo[3], k1v[3];
@@ -515,7 +592,10 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       for (int c = 0; c < 3; ++c) mn[c] = mo[c] + T(0.5) * dt * (k1v[c] + k[c]);
       const T inv = T(1) / sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.mout[rb + (size_t)c * a.N + cell] = mn[c] * inv;
+      for (int c = 0; c < 3; ++c) {
+        a.mout[rb + (size_t)c * a.N + cell] = mn[c] * inv;
+        if (fwd) F[(c * L + l) * 2 * hx + x] = mn[c] * inv;
+      }
       acc[0] += (double)(mn[2] * inv);
     } else if (MODE == FM_RK7) {
 #pragma unroll
@@ -533,6 +613,13 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       acc[0] = (en != en) ? __builtin_inf() : fmax(acc[0], en);
     }
   }
+  if (fwd) {
+    __syncthreads();
+    const cpx<T>* X =
+        lds_fft<T, false>(reinterpret_cast<cpx<T>*>(F), Hbuf, nl, a.plan_f, tw_lds);
+    xfwd_store(X, a.wpost, a.S, r, z, y0, L, hx, a.Kx, a.ny, a.nz, a.Sy,
+               a.xone);
+  }
   // workgroup reductions
   if (MODE == FM_HEUN2 || MODE == FM_ENERGY || MODE == FM_RK7) {
     const int nv = (MODE == FM_ENERGY) ? 5 : 1;
@@ -549,7 +636,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       __syncthreads();
     }
     if (threadIdx.x == 0) {
-      const size_t blk = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+      const size_t blk = (size_t)by * gridDim.x + bx;
       const size_t nblk = (size_t)gridDim.x * gridDim.y;
       if (MODE == FM_RK7) {
         const double e = red[0];

@@ -417,6 +417,7 @@ struct Epilogue {
   void* mout = nullptr;
   double e[7] = {0, 0, 0, 0, 0, 0, 0};
   int use_k_err = 0;
+  int fwd = 0;  // Heun modes: also write the half spectrum of the new state
 };
 
 template <typename T>
@@ -544,15 +545,19 @@ mmx_status launch_xfwd(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb
 template <typename T>
 mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb, const Epilogue& ep,
                       uint64_t step, double dt_th, const double* dtdev, double dth,
-                      const int* done, uint32_t terms_override = 0xFFFFFFFFu) {
+                      const int* done, uint32_t terms_override = 0xFFFFFFFFu,
+                      bool spec_ready = false) {
   uint32_t terms = (terms_override == 0xFFFFFFFFu) ? ctx->terms : terms_override;
   const bool demag = (terms & MMX_DEMAG) != 0;
   if (demag && !G.demag_built) return fail(MMX_ESTATE, "mmx_build_demag has not been called");
+  if (spec_ready && cb.mout) return fail(MMX_ESTATE, "spectrum of a combined state");
   hipStream_t s = ctx->stream;
   const T* mfield = mbase;
-  // stage 1: combine (+ x forward transform)
-  if (demag || cb.mout) {
-    MMX_TRY(launch_xfwd<T>(ctx, G, mbase, cb, demag, dtdev, dth, done));
+  // stage 1: combine (+ x forward transform, unless the previous epilogue
+  // already wrote the half spectrum of mbase)
+  const bool need_fft = demag && !spec_ready;
+  if (need_fft || cb.mout) {
+    MMX_TRY(launch_xfwd<T>(ctx, G, mbase, cb, need_fft, dtdev, dth, done));
     if (cb.mout) mfield = reinterpret_cast<const T*>(cb.mout);
   }
   // stage 2: y (and z) passes with the tensor product
@@ -617,6 +622,8 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
   a.mout = reinterpret_cast<T*>(ep.mout);
   for (int j = 0; j < 7; ++j) a.e[j] = ep.e[j];
   for (int j = 0; j < 6; ++j) a.kk[j] = G.k[j].as<T>();
+  a.fwd = ep.fwd;
+  a.plan_f = G.plan_x;
   a.st = ctx->st.as<RkState>();
   a.partial = G.partial.as<double>();
   if (!demag && ctx->hext) {
@@ -993,17 +1000,24 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       Group& G = *ctx->groups[gi];
       const int roff = roffs[gi];
       T* mg = mb + G.off;
+      // each epilogue x-transforms the state it writes, so both field
+      // evaluations start from a ready half spectrum (the first one of the
+      // call is prepared below)
       Epilogue e1;
       e1.mode = FM_HEUN1;
       e1.k1 = G.k[0].p;
       e1.mout = G.ms.p;
-      MMX_TRY(eval_group<T>(ctx, G, mg, Combine{}, e1, step, dt, nullptr, dt, nullptr));
+      e1.fwd = 1;
+      MMX_TRY(eval_group<T>(ctx, G, mg, Combine{}, e1, step, dt, nullptr, dt, nullptr,
+                            0xFFFFFFFFu, true));
       Epilogue e2;
       e2.mode = FM_HEUN2;
       e2.k1 = G.k[0].p;
       e2.m0 = mg;
       e2.mout = mg;
-      MMX_TRY(eval_group<T>(ctx, G, G.ms.as<T>(), Combine{}, e2, step, dt, nullptr, dt, nullptr));
+      e2.fwd = 1;
+      MMX_TRY(eval_group<T>(ctx, G, G.ms.as<T>(), Combine{}, e2, step, dt, nullptr, dt, nullptr,
+                            0xFFFFFFFFu, true));
       if (tsw_d) {
         ProfScope ps(ctx->prof, "k_switch_reduce", st);
         k_switch_reduce<<<(G.R + 63) / 64, 64, 0, st>>>(G.partial.as<double>(), G.nblk, G.R,
@@ -1018,6 +1032,12 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
     }
     return MMX_OK;
   };
+  if (n_steps > 0 && (ctx->terms & MMX_DEMAG)) {
+    for (int gi : staged) {  // half spectrum of the initial state
+      Group& G = *ctx->groups[gi];
+      MMX_TRY(launch_xfwd<T>(ctx, G, mb + G.off, Combine{}, true, nullptr, dt, nullptr));
+    }
+  }
   const int64_t chunk = 32;  // steps per captured graph
   int64_t done_steps = 0;
   if (n_steps >= 2 * chunk && !ctx->prof.on) {

@@ -38,11 +38,15 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
   __shared__ cpx<T> E[NC * N1 * STR];
   if (a.done && *a.done) return;
   const int lane = threadIdx.x, wc = lane / N1, q = lane - wc * N1;
-  const int kx = blockIdx.x * NC + wc;
+  // neighbouring column tiles of a replica share cache lines of the spectrum
+  // rows: keep them on one XCD
+  int tile, by, rep;
+  xcd_block(tile, by, rep);
+  const int kx = tile * NC + wc;
   const bool live = kx < a.Kx;
   const int Kx = a.Kx;
   const size_t plane = (size_t)a.Sy * Kx;  // one component of one replica (nz = 1)
-  cpx<T>* S = a.S + (size_t)blockIdx.z * 3 * plane + kx;
+  cpx<T>* S = a.S + (size_t)rep * 3 * plane + kx;
   cpx<T>* Ew = E + wc * N1 * STR;
   const cpx<T>* __restrict__ tw = a.tw;
   cpx<T> X[3][N2];

@@ -3,8 +3,8 @@ oracle (Methods, "Integrators" and "Replica batching"): Stratonovich Heun with
 the Brown field, switching times, adaptive Dormand-Prince 5(4) (independent
 runs and dt replay), energy and topological charge.
 
-Bars: FP64 max |dm| <= 1e-12, FP32 max |dm| <= 1e-5 (the north-star
-tolerances); batched versus per-trial runs bit-identical.
+Bars: FP64 max |dm| <= 1e-12, FP32 max |dm| <= 1e-5 (the parity
+tolerances of the precision forms); batched versus per-trial runs bit-identical.
 """
 import numpy as np
 import pytest
@@ -310,3 +310,38 @@ def test_uneven_groups_in_one_context(prec):
         assert np.array_equal(mine, single), c.n
         ref = oit.heun_run(m0, c.grid, c.material(), dt, nsteps, seed=np.array(c.seeds))
         assert np.abs(mine - ref).max() <= TOLM[prec], c.n
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_heun_resume_is_bitwise(prec):
+    """Checkpoint / resume of the thermal Heun run: the state is m and the
+    step index (the Philox counter), so N steps equal N/2 steps, a copy of m
+    to the host and back, and N/2 more steps from step index N/2, bit for bit
+    (switching times included)."""
+    import paper_2608_15253_amd as mmx
+    case = Case((32, 24, 1), (4e-9, 4e-9, 4e-9), R=3, alpha=0.5, Ku=1e5, B=(0, 0, -1.5),
+                T=300.0, seeds=list(replica_seeds(12, 3)),
+                terms=("exchange", "anisotropy", "zeeman", "demag", "thermal"))
+    m0 = _round(uniform(case.n, (0.05, 0.0, 1.0), replicas=case.R), prec)
+    n = 140
+    ctx = open_ctx(case, prec)
+    try:
+        md = dev(m0, prec)
+        ts = dev(-np.ones(case.R), 2)
+        mmx.mmx_heun(ctx, md, 1e-13, n, 0, ts)
+        full, tfull = host(md), host(ts)
+        md = dev(m0, prec)
+        ts = dev(-np.ones(case.R), 2)
+        mmx.mmx_heun(ctx, md, 1e-13, n // 2, 0, ts)
+        saved, tsaved = host(md), host(ts)
+    finally:
+        mmx.mmx_destroy(ctx)
+    ctx = open_ctx(case, prec)       # a fresh context, as after a restart
+    try:
+        md, ts = dev(saved, prec), dev(tsaved, 2)
+        mmx.mmx_heun(ctx, md, 1e-13, n - n // 2, n // 2, ts)
+        resumed, tres = host(md), host(ts)
+    finally:
+        mmx.mmx_destroy(ctx)
+    assert np.array_equal(full, resumed)
+    assert np.array_equal(tfull, tres)
