@@ -197,9 +197,9 @@ __global__ void __launch_bounds__(kFusedBlock) k_heun_fused(HeunFusedArgs<T> a) 
         if (active_col && y < ny) {
           const size_t cell = (size_t)x + (size_t)nx * y;
           T mc[3];
-          ld3(src, rb, f.N, cell, mc);
+          ld3(src + rb, (unsigned)f.N, (unsigned)cell, mc);
           T Hex[3], Hdm[3], Han[3], Hz[3];
-          local_terms(f, src, rb, cell, x, y, 0, mc, f.kbc, Hex, Hdm, Han, Hz);
+          local_terms(f, src + rb, (unsigned)cell, x, y, 0, mc, f.kbc, Hex, Hdm, Han, Hz);
           T Hdd[3] = {0, 0, 0};
           if (demag) {
 #pragma unroll
@@ -225,8 +225,8 @@ __global__ void __launch_bounds__(kFusedBlock) k_heun_fused(HeunFusedArgs<T> a) 
           } else {
             // own cell of m is read and written only by this thread here
             T mo[3], k1v[3], mn[3];
-            ld3(a.m, rb, f.N, cell, mo);
-            ld3(a.k1, rb, f.N, cell, k1v);
+            ld3(a.m + rb, (unsigned)f.N, (unsigned)cell, mo);
+            ld3(a.k1 + rb, (unsigned)f.N, (unsigned)cell, k1v);
 #pragma unroll
             for (int c = 0; c < 3; ++c) mn[c] = mo[c] + T(0.5) * dt * (k1v[c] + k[c]);
             const T inv = T(1) / sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);

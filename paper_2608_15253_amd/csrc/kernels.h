@@ -389,10 +389,13 @@ struct FArgs {
 };
 
 template <typename T>
-__device__ inline void ld3(const T* __restrict__ m, size_t rb, int N, size_t cell, T v[3]) {
-  v[0] = m[rb + cell];
-  v[1] = m[rb + N + cell];
-  v[2] = m[rb + 2 * (size_t)N + cell];
+// Offsets within one replica are 32-bit (3 N < 2^32): with the replica's base
+// pointer uniform across the workgroup the loads take the scalar-base plus
+// 32-bit vector-offset form instead of 64-bit address arithmetic per lane.
+__device__ inline void ld3(const T* __restrict__ mr, unsigned N, unsigned cell, T v[3]) {
+  v[0] = mr[cell];
+  v[1] = mr[N + cell];
+  v[2] = mr[2 * N + cell];
 }
 
 // Exchange (six-point Laplacian), interfacial DMI (central differences), both
@@ -400,13 +403,14 @@ __device__ inline void ld3(const T* __restrict__ m, size_t rb, int N, size_t cel
 // open x/y edges (Neumann along z), uniaxial anisotropy and Zeeman field of
 // the cell at (x, y, z) with magnetisation mc; neighbours read from m.
 template <typename T>
-__device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ m, size_t rb,
-                                   size_t cell, int x, int y, int z, const T mc[3], T kbc,
-                                   T Hex[3], T Hdm[3], T Han[3], T Hz[3]) {
+__device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, unsigned cell,
+                                   int x, int y, int z, const T mc[3], T kbc, T Hex[3],
+                                   T Hdm[3], T Han[3], T Hz[3]) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) { Hex[c] = 0; Hdm[c] = 0; Han[c] = 0; Hz[c] = 0; }
   const int coord[3] = {x, y, z};
-  const size_t stride[3] = {1, (size_t)a.nx, (size_t)a.nx * a.ny};
+  const unsigned stride[3] = {1u, (unsigned)a.nx, (unsigned)(a.nx * a.ny)};
+  const unsigned N = (unsigned)a.N;
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     if (a.nax[ax] == 1) continue;
@@ -417,11 +421,11 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ m, s
     if (ax == 0) { ev[0] = mc[2]; ev[2] = -mc[0]; }
     if (ax == 1) { ev[1] = mc[2]; ev[2] = -mc[1]; }
     const T g = (ax < 2) ? a.hd[ax] * kbc : T(0);
-    if (coord[ax] > 0) ld3(m, rb, a.N, cell - stride[ax], mm);
-    else if (a.pbc[ax]) ld3(m, rb, a.N, cell + (size_t)(n - 1) * stride[ax], mm);
+    if (coord[ax] > 0) ld3(mr, N, cell - stride[ax], mm);
+    else if (a.pbc[ax]) ld3(mr, N, cell + (unsigned)(n - 1) * stride[ax], mm);
     else { for (int c = 0; c < 3; ++c) mm[c] = mc[c] - g * ev[c]; }
-    if (coord[ax] < n - 1) ld3(m, rb, a.N, cell + stride[ax], mp);
-    else if (a.pbc[ax]) ld3(m, rb, a.N, cell - (size_t)(n - 1) * stride[ax], mp);
+    if (coord[ax] < n - 1) ld3(mr, N, cell + stride[ax], mp);
+    else if (a.pbc[ax]) ld3(mr, N, cell - (unsigned)(n - 1) * stride[ax], mp);
     else { for (int c = 0; c < 3; ++c) mp[c] = mc[c] + g * ev[c]; }
     if (a.terms & T_EXCH) {
 #pragma unroll
@@ -526,26 +530,32 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
     if (Tr > 0) sigma = (T)sqrt(a.sig2pref * Tr / a.dt_th);
   }
   const T kbc = a.kbc;  // free-edge condition of the material's D (0 when D = 0)
+  const unsigned N = (unsigned)a.N;
+  const T* __restrict__ mr = a.m + rb;  // replica bases (uniform per workgroup)
+  T* out_r = a.out ? a.out + rb : nullptr;
+  T* mout_r = a.mout ? a.mout + rb : nullptr;
+  T* k1_r = a.k1 ? a.k1 + rb : nullptr;
+  const uint64_t step_now = a.stepdev ? *a.stepdev : a.step;
   double acc[5] = {0, 0, 0, 0, 0};
   for (int t = threadIdx.x; t < ncell_blk; t += blockDim.x) {
     const int l = udiv(t, a.nx), x = t - l * a.nx, y = y0 + l;
     if (y >= a.ny) continue;
-    const size_t cell = (size_t)x + (size_t)a.nx * (y + (size_t)a.ny * z);
+    const unsigned cell = (unsigned)x + (unsigned)a.nx * (unsigned)(y + a.ny * z);
     T mc[3];
-    ld3(a.m, rb, a.N, cell, mc);
+    ld3(mr, N, cell, mc);
     T Hex[3], Hdm[3], Han[3], Hz[3];
-    local_terms(a, a.m, rb, cell, x, y, z, mc, kbc, Hex, Hdm, Han, Hz);
+    local_terms(a, mr, cell, x, y, z, mc, kbc, Hex, Hdm, Han, Hz);
     T Hdd[3] = {0, 0, 0};
     if (demag) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) Hdd[c] = Hd[(c * L + l) * 2 * hx + x];
       if (a.hd_out) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.hd_out[rb + (size_t)c * a.N + cell] = Hdd[c];
+        for (int c = 0; c < 3; ++c) a.hd_out[rb + c * N + cell] = Hdd[c];
       }
     } else if (a.hext) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) Hdd[c] = a.hext_scale * (T)a.hext[rb + (size_t)c * a.N + cell];
+      for (int c = 0; c < 3; ++c) Hdd[c] = a.hext_scale * (T)a.hext[rb + c * N + cell];
       Hdd[2] += a.hext_mz * mc[2];
     }
     if (MODE == FM_ENERGY) {
@@ -561,51 +571,51 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
     for (int c = 0; c < 3; ++c) H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + Hdd[c];
     if (sigma != T(0)) {
       T eta[3];
-      thermal_eta<T>(a.seeds[r], (uint32_t)cell, a.stepdev ? *a.stepdev : a.step, eta);
+      thermal_eta<T>(a.seeds[r], (uint32_t)cell, step_now, eta);
 #pragma unroll
       for (int c = 0; c < 3; ++c) H[c] += sigma * eta[c];
     }
     if (MODE == FM_FIELD) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.out[rb + (size_t)c * a.N + cell] = H[c];
+      for (int c = 0; c < 3; ++c) out_r[c * N + cell] = H[c];
       continue;
     }
     T k[3];
     llg_torque(mc, H, a.gpm, a.alpha, k);
     if (MODE == FM_TORQUE || MODE == FM_RKK) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.out[rb + (size_t)c * a.N + cell] = k[c];
+      for (int c = 0; c < 3; ++c) out_r[c * N + cell] = k[c];
     } else if (MODE == FM_HEUN1) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const T mn = mc[c] + dt * k[c];
-        a.k1[rb + (size_t)c * a.N + cell] = k[c];
-        a.mout[rb + (size_t)c * a.N + cell] = mn;
+        k1_r[c * N + cell] = k[c];
+        mout_r[c * N + cell] = mn;
         if (fwd) F[(c * L + l) * 2 * hx + x] = mn;
       }
     } else if (MODE == FM_HEUN2) {
       T mo[3], k1v[3];
-      ld3(a.m0, rb, a.N, cell, mo);
-      ld3(a.k1, rb, a.N, cell, k1v);
+      ld3(a.m0 + rb, N, cell, mo);
+      ld3(k1_r, N, cell, k1v);
       T mn[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) mn[c] = mo[c] + T(0.5) * dt * (k1v[c] + k[c]);
       const T inv = T(1) / sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        a.mout[rb + (size_t)c * a.N + cell] = mn[c] * inv;
+        mout_r[c * N + cell] = mn[c] * inv;
         if (fwd) F[(c * L + l) * 2 * hx + x] = mn[c] * inv;
       }
       acc[0] += (double)(mn[2] * inv);
     } else if (MODE == FM_RK7) {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.out[rb + (size_t)c * a.N + cell] = k[c];
+      for (int c = 0; c < 3; ++c) out_r[c * N + cell] = k[c];
       double d2 = 0;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         double s = a.e[6] * (double)k[c];
         for (int j = 0; j < 6; ++j)
-          if (a.e[j] != 0.0) s += a.e[j] * (double)a.kk[j][rb + (size_t)c * a.N + cell];
+          if (a.e[j] != 0.0) s += a.e[j] * (double)a.kk[j][rb + c * N + cell];
         s *= dt_state;
         d2 += s * s;
       }

@@ -50,19 +50,21 @@ struct BoxMuller<double> {
   }
 };
 
+// FP32: the hardware transcendental units do Box-Muller directly: v_log_f32
+// is log2 and v_sin_f32 / v_cos_f32 take their argument in turns, so
+// sin(2 pi u) is one instruction (u in (0, 1); results within a few ulp).
 template <>
 struct BoxMuller<float> {
   static __device__ inline void eta(const uint32_t w[4], float out[3]) {
     const float s = 2.3283064365386962890625e-10f;
     const float u0 = fmaf((float)w[0], s, 0.5f * s), u1 = fmaf((float)w[1], s, 0.5f * s);
     const float u2 = fmaf((float)w[2], s, 0.5f * s), u3 = fmaf((float)w[3], s, 0.5f * s);
-    const float r01 = sqrtf(-2.0f * logf(u0));
-    const float r23 = sqrtf(-2.0f * logf(u2));
-    float sn, cs;
-    sincospif(2.0f * u1, &sn, &cs);
-    out[0] = r01 * cs;
-    out[1] = r01 * sn;
-    out[2] = r23 * cospif(2.0f * u3);
+    const float m2ln2 = -1.38629436111989061883f;  // -2 ln 2
+    const float r01 = sqrtf(m2ln2 * __builtin_amdgcn_logf(u0));
+    const float r23 = sqrtf(m2ln2 * __builtin_amdgcn_logf(u2));
+    out[0] = r01 * __builtin_amdgcn_cosf(u1);
+    out[1] = r01 * __builtin_amdgcn_sinf(u1);
+    out[2] = r23 * __builtin_amdgcn_cosf(u3);
   }
 };
 
