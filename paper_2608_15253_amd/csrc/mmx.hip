@@ -16,6 +16,7 @@
 #include "kernels.h"
 #include "setup_kernels.h"
 #include "yconv_reg.h"
+#include "rows_reg.h"
 
 using namespace mmx;
 
@@ -136,7 +137,8 @@ struct Group {
   size_t off = 0;  // element offset of this group in caller arrays
   // device buffers
   DevBuf tw_x, wpost, tw_y, tw_z, Nt, S, ms, m7, k[7], Trep, seeds, partial, E;
-  int nblk = 1;  // k_fields workgroups per replica
+  int nblk = 1;       // k_fields workgroups per replica
+  int nblk_last = 1;  // workgroups per replica of the last field-kernel launch
   int demag_built = 0;
   int fused_faster = 0;  // set by mmx_autotune when the replica-resident path timed faster
 };
@@ -328,7 +330,8 @@ mmx_status setup_group(mmx_ctx* ctx, Group& G) {
   HIP_TRY(G.ms.alloc(st));
   HIP_TRY(G.k[0].alloc(st));
   HIP_TRY(G.S.alloc((size_t)G.R * 3 * G.nz * G.Sy * G.Kx * cpxb<T>()));
-  HIP_TRY(G.partial.alloc((size_t)G.R * G.nblk * 5 * sizeof(double)));
+  // sized for one grid row per workgroup, the finest split any field kernel uses
+  HIP_TRY(G.partial.alloc((size_t)G.R * G.ny * G.nz * 5 * sizeof(double)));
   HIP_TRY(G.E.alloc((size_t)G.R * 6 * sizeof(double)));
   std::vector<double> T0(G.R, 0.0);
   std::vector<uint64_t> s0(G.R, 0);
@@ -461,8 +464,45 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   return a;
 }
 
+// Heun stages of FP32 films whose x half-length is 16 or 64 (4 x 4, 8 x 8):
+// the register row kernel; false if not applicable.  (16 x 16 rows would
+// need more registers than a lane has and spill.)
+template <typename T>
+bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return false;
+  } else {
+    if (!(mode == FM_HEUN1 || mode == FM_HEUN2) || !(a.terms & T_DEMAG) || !a.fwd) return false;
+    if (G.xone || a.hext || a.hd_out) return false;
+    hipStream_t s = ctx->stream;
+    auto go = [&](auto kern, int rpw) {
+      const int gx = (G.ny + rpw - 1) / rpw;
+      G.nblk_last = gx * G.nz;
+      kern<<<dim3(gx, G.nz, G.R), 64, 0, s>>>(a);
+      return true;
+    };
+    const bool h1 = mode == FM_HEUN1;
+    switch (G.hx) {
+      case 16: return h1 ? go(k_rows_reg<float, 4, FM_HEUN1>, 16)
+                         : go(k_rows_reg<float, 4, FM_HEUN2>, 16);
+      case 64: return h1 ? go(k_rows_reg<float, 8, FM_HEUN1>, 8)
+                         : go(k_rows_reg<float, 8, FM_HEUN2>, 8);
+      default: return false;
+    }
+  }
+}
+
 template <typename T>
 mmx_status launch_fields(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
+  static const char* kname_reg[] = {"", "", "k_fields_heun1", "k_fields_heun2"};
+  if (mode == FM_HEUN1 || mode == FM_HEUN2) {
+    ProfScope ps(ctx->prof, kname_reg[mode], ctx->stream);
+    if (launch_rows_reg<T>(ctx, G, a, mode)) {
+      HIP_TRY(hipGetLastError());
+      return MMX_OK;
+    }
+  }
+  G.nblk_last = G.nblk;
   dim3 grid((G.ny + G.L - 1) / G.L, G.nz, G.R);
   const size_t lds = (a.terms & T_DEMAG) ? (2 * (size_t)3 * G.L * G.hx + G.hx) * cpxb<T>() : 0;
   hipStream_t s = ctx->stream;
@@ -1020,7 +1060,7 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
                             0xFFFFFFFFu, true));
       if (tsw_d) {
         ProfScope ps(ctx->prof, "k_switch_reduce", st);
-        k_switch_reduce<<<(G.R + 63) / 64, 64, 0, st>>>(G.partial.as<double>(), G.nblk, G.R,
+        k_switch_reduce<<<(G.R + 63) / 64, 64, 0, st>>>(G.partial.as<double>(), G.nblk_last, G.R,
                                                          G.N, tsw_d + roff, (double)(step + 1) * dt,
                                                          ctx->cur_stepdev, dt);
         HIP_TRY(hipGetLastError());
