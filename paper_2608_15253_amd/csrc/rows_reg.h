@@ -94,7 +94,18 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
       v[c][b] = Zv;
     }
   row_transform_step<T, NR>(v, E, q, tw, 1, true);
-  // lane q now holds z[q + NR d] = H_demag at cells x = 2 (q + NR d) + {0, 1}
+  // lane q now holds z[q + NR d] = H_demag at cells x = 2 (q + NR d) + {0, 1};
+  // the row's field goes to LDS (real view, [c][x]) so that the cell loop
+  // below holds one cell at a time and each lane takes the cells x = q + NR j
+  T* Hs = reinterpret_cast<T*>(E);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = 0; d < NR; ++d) {
+      Hs[c * 2 * hx + 2 * (q + NR * d)] = v[c][d].re;
+      Hs[c * 2 * hx + 2 * (q + NR * d) + 1] = v[c][d].im;
+    }
+  __syncthreads();
   const T dt = (T)a.dth;
   T sigma = 0;
   if ((a.terms & T_THERMAL) && a.Trep) {
@@ -106,63 +117,61 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   T* mout_r = a.mout + rb;
   T* k1_r = a.k1 + rb;
   double acc = 0;
+#pragma unroll 2
+  for (int j = 0; j < 2 * NR; ++j) {
+    const int x = q + NR * j;
+    T mn_out[3] = {0, 0, 0};
+    if (live && x < a.nx) {
+      const unsigned cell = (unsigned)x + (unsigned)a.nx * (unsigned)(y + a.ny * z);
+      T mc[3];
+      ld3(mr, N, cell, mc);
+      T Hex[3], Hdm[3], Han[3], Hz[3];
+      local_terms(a, mr, cell, x, y, z, mc, a.kbc, Hex, Hdm, Han, Hz);
+      T H[3];
 #pragma unroll
-  for (int d = 0; d < NR; ++d) {
-    const int k = q + NR * d;
+      for (int c = 0; c < 3; ++c) H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + Hs[c * 2 * hx + x];
+      if (sigma != T(0)) {
+        T eta[3];
+        thermal_eta<T>(a.seeds[r], (uint32_t)cell, step_now, eta);
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int x = 2 * k + h;
-      T mn_out[3] = {0, 0, 0};
-      if (live && x < a.nx) {
-        const unsigned cell = (unsigned)x + (unsigned)a.nx * (unsigned)(y + a.ny * z);
-        T mc[3];
-        ld3(mr, N, cell, mc);
-        T Hex[3], Hdm[3], Han[3], Hz[3];
-        local_terms(a, mr, cell, x, y, z, mc, a.kbc, Hex, Hdm, Han, Hz);
-        T H[3];
+        for (int c = 0; c < 3; ++c) H[c] += sigma * eta[c];
+      }
+      T kv[3];
+      llg_torque(mc, H, a.gpm, a.alpha, kv);
+      if (MODE == FM_HEUN1) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          const T hd = h ? v[c][d].im : v[c][d].re;
-          H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + hd;
+          mn_out[c] = mc[c] + dt * kv[c];
+          k1_r[c * N + cell] = kv[c];
+          mout_r[c * N + cell] = mn_out[c];
         }
-        if (sigma != T(0)) {
-          T eta[3];
-          thermal_eta<T>(a.seeds[r], (uint32_t)cell, step_now, eta);
+      } else {
+        T mo[3], k1v[3], mn[3];
+        ld3(a.m0 + rb, N, cell, mo);
+        ld3(k1_r, N, cell, k1v);
 #pragma unroll
-          for (int c = 0; c < 3; ++c) H[c] += sigma * eta[c];
+        for (int c = 0; c < 3; ++c) mn[c] = mo[c] + T(0.5) * dt * (k1v[c] + kv[c]);
+        const T inv = T(1) / sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          mn_out[c] = mn[c] * inv;
+          mout_r[c * N + cell] = mn_out[c];
         }
-        T kv[3];
-        llg_torque(mc, H, a.gpm, a.alpha, kv);
-        if (MODE == FM_HEUN1) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            mn_out[c] = mc[c] + dt * kv[c];
-            k1_r[c * N + cell] = kv[c];
-            mout_r[c * N + cell] = mn_out[c];
-          }
-        } else {
-          T mo[3], k1v[3], mn[3];
-          ld3(a.m0 + rb, N, cell, mo);
-          ld3(k1_r, N, cell, k1v);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) mn[c] = mo[c] + T(0.5) * dt * (k1v[c] + kv[c]);
-          const T inv = T(1) / sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            mn_out[c] = mn[c] * inv;
-            mout_r[c * N + cell] = mn_out[c];
-          }
-          acc += (double)mn_out[2];
-        }
-      }
-      // the new state, packed, is the forward transform's input (zero
-      // beyond the last cell)
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if (h) v[c][d].im = mn_out[c]; else v[c][d].re = mn_out[c];
+        acc += (double)mn_out[2];
       }
     }
+    // the new state is the forward transform's input (zero beyond the last
+    // cell); it replaces the field value of the same cell
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Hs[c * 2 * hx + x] = mn_out[c];
   }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int d = 0; d < NR; ++d)
+      v[c][d] = {Hs[c * 2 * hx + 2 * (q + NR * d)], Hs[c * 2 * hx + 2 * (q + NR * d) + 1]};
+  __syncthreads();
   // 2. forward x transform of the new state; lane q ends with X[q + NR d']
   row_transform_step<T, NR>(v, E, q, tw, 1, false);
   // 3. real-to-complex split S[kx] = E + conj(W^kx) O, kx = q + NR d' and
