@@ -464,31 +464,43 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   return a;
 }
 
-// Heun stages of FP32 films whose x half-length is 16 or 64 (4 x 4, 8 x 8):
-// the register row kernel; false if not applicable.  (16 x 16 rows would
-// need more registers than a lane has and spill.)
+// Heun stages of FP32 films whose x half-length is 16, 32, 64, 128 or 256
+// (4 x 4, 4 x 8, 8 x 8, 8 x 16, 16 x 16): the register row kernel (mode
+// FM_HEUN1 / FM_HEUN2) or its forward-only part (mode -1, the half spectrum
+// of the state a.m); false if not applicable.
 template <typename T>
 bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
   if constexpr (!std::is_same<T, float>::value) {
     return false;
   } else {
-    if (!(mode == FM_HEUN1 || mode == FM_HEUN2) || !(a.terms & T_DEMAG) || !a.fwd) return false;
+    if (!(mode == FM_HEUN1 || mode == FM_HEUN2 || mode == -1) || !(a.terms & T_DEMAG)) return false;
+    if (mode != -1 && !a.fwd) return false;
     if (G.xone || a.hext || a.hd_out) return false;
     hipStream_t s = ctx->stream;
-    auto go = [&](auto kern, int rpw) {
+    auto go = [&](auto k1, auto k2, auto kf, int rpw) {
       const int gx = (G.ny + rpw - 1) / rpw;
+      const dim3 grid(gx, G.nz, G.R);
+      if (mode == -1) {
+        kf<<<grid, 64, 0, s>>>(a);
+        return true;
+      }
       G.nblk_last = gx * G.nz;
-      kern<<<dim3(gx, G.nz, G.R), 64, 0, s>>>(a);
+      if (mode == FM_HEUN1) k1<<<grid, 64, 0, s>>>(a);
+      else k2<<<grid, 64, 0, s>>>(a);
       return true;
     };
-    const bool h1 = mode == FM_HEUN1;
+#define MMX_ROWS(N1, N2, RPW)                                                   \
+  go(k_rows_reg<float, N1, N2, FM_HEUN1>, k_rows_reg<float, N1, N2, FM_HEUN2>, \
+     k_rows_fwd<float, N1, N2>, RPW)
     switch (G.hx) {
-      case 16: return h1 ? go(k_rows_reg<float, 4, FM_HEUN1>, 16)
-                         : go(k_rows_reg<float, 4, FM_HEUN2>, 16);
-      case 64: return h1 ? go(k_rows_reg<float, 8, FM_HEUN1>, 8)
-                         : go(k_rows_reg<float, 8, FM_HEUN2>, 8);
+      case 16: return MMX_ROWS(4, 4, 16);
+      case 32: return MMX_ROWS(4, 8, 16);
+      case 64: return MMX_ROWS(8, 8, 8);
+      case 128: return MMX_ROWS(8, 16, 8);
+      case 256: return MMX_ROWS(16, 16, 4);
       default: return false;
     }
+#undef MMX_ROWS
   }
 }
 
@@ -1075,7 +1087,18 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
   if (n_steps > 0 && (ctx->terms & MMX_DEMAG)) {
     for (int gi : staged) {  // half spectrum of the initial state
       Group& G = *ctx->groups[gi];
-      MMX_TRY(launch_xfwd<T>(ctx, G, mb + G.off, Combine{}, true, nullptr, dt, nullptr));
+      // with the arithmetic of the row kernel where that kernel will run, so
+      // that a run split over several calls equals one call bit for bit
+      FArgs<T> fa = field_args<T>(ctx, G, ctx->terms);
+      fa.m = mb + G.off;
+      bool done_fwd = false;
+      {
+        ProfScope ps(ctx->prof, "k_xfwd", s);
+        done_fwd = launch_rows_reg<T>(ctx, G, fa, -1);
+        if (done_fwd) HIP_TRY(hipGetLastError());
+      }
+      if (!done_fwd)
+        MMX_TRY(launch_xfwd<T>(ctx, G, mb + G.off, Combine{}, true, nullptr, dt, nullptr));
     }
   }
   const int64_t chunk = 32;  // steps per captured graph

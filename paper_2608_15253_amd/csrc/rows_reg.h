@@ -1,21 +1,22 @@
-// Row pass of the stochastic Heun stages with the rows held in registers
-// (device code): inverse x transform of the demag spectrum, local fields,
-// torque, predictor or corrector update, and the forward x transform of the
-// state just written, for films whose half-length x transform has
-// hx = NR * NR points (NR = 4 or 8).
+// Row pass of the stochastic Heun stages with the rows' transforms in
+// registers (device code): inverse x transform of the demag spectrum, local
+// fields, torque, predictor or corrector update, and the forward x transform
+// of the state just written, for films whose half-length x transform has
+// hx = N1 * N2 points (4 x 4, 4 x 8, 8 x 8, 8 x 16, 16 x 16).
 //
-// One wave holds RPW = 64 / NR grid rows; lane q of a row owns the packed
-// positions k = q + NR d (d < NR), i.e. the cells x = 2k and 2k + 1, for all
-// three components.  A transform of the row, X[c + NR d'] = sum_k x[k]
-// w^(+-k (c + NR d')), splits k = a + NR b: lane q = a takes the NR-point
-// DFT over b in registers, multiplies by w^(+-a c), the values are transposed
-// through LDS so that lane c holds all a, and an NR-point DFT over a leaves
-// lane c the outputs c + NR d'.  With the square split the outputs of the
-// inverse transform sit in the lanes that own the cells, and the new state
-// of those cells is already in the input layout of the forward transform,
-// so a row crosses LDS once per direction (plus one exchange to pair X[k]
-// with X[hx - k] for the real-to-complex split).  The cell arithmetic is the
-// one of k_fields; only the butterfly order of the transforms differs.
+// One wave holds RPW = 64 / N1 grid rows, N1 lanes per row.  A transform of
+// a row, X[c + N1 d] = sum_k x[k] w^(+-k (c + N1 d)), splits k = a + N2 b:
+// lane q takes the N1-point DFTs over b for a = q, q + N1, ... in registers,
+// multiplies by w^(+-a c), the values are transposed through LDS so that lane
+// c holds all a, and an N2-point DFT over a leaves lane c the outputs
+// c + N1 d.  The inverse transform's output (the demag field of the row) is
+// staged in LDS, the lanes take the row's cells in coalesced order (x = q +
+// N1 j) and overwrite each cell's field with its new state, which is then
+// read back in the input order of the forward transform; one more LDS
+// exchange pairs X[k] with X[hx - k] for the real-to-complex split.  A row
+// thus crosses LDS a fixed handful of times instead of once per radix pass.
+// The cell arithmetic is the one of k_fields; only the butterfly order of
+// the transforms differs.
 #pragma once
 #include "common.h"
 #include "fft_lds.h"
@@ -25,47 +26,122 @@
 
 namespace mmx {
 
-template <typename T, int NR>
-__device__ inline void row_transform_step(cpx<T> (&v)[3][NR], cpx<T>* E, int q,
-                                          const cpx<T>* __restrict__ tw, int tw_stride,
-                                          bool inv) {
-  constexpr int STR = NR + 1;
-  // NR-point DFTs over b (lane q = a), twiddles w^(+-a c), transpose
+// One N1 x N2 transform of a line held by N1 lanes: in, v[s N1 + b] =
+// x[q + N1 s + N2 b] (s < N2 / N1, b < N1); out, v[d] = X[q + N1 d]
+// (d < N2).  E: N1 (N2 + 1) LDS slots of this line (workgroup barriers).
+template <typename T, int N1, int N2, bool INV>
+__device__ inline void line_transform(cpx<T> (&v)[N2], cpx<T>* E, int q,
+                                      const cpx<T>* __restrict__ tw) {
+  constexpr int n = N1 * N2, S2 = N2 / N1, STR = N2 + 1;
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    if (inv) dft_reg<T, true, NR>(v[c]); else dft_reg<T, false, NR>(v[c]);
+  for (int s = 0; s < S2; ++s) {
+    const int av = q + N1 * s;
+    dft_reg<T, INV, N1>(&v[s * N1]);
+    E[av] = v[s * N1];
 #pragma unroll
-    for (int cc = 1; cc < NR; ++cc) {
-      const cpx<T> w = tw[((q * cc) & (NR * NR - 1)) * tw_stride];
-      v[c][cc] = inv ? cmulc(v[c][cc], w) : cmul(v[c][cc], w);
+    for (int cc = 1; cc < N1; ++cc) {
+      const cpx<T> w = tw[(av * cc) & (n - 1)];
+      E[cc * STR + av] = INV ? cmulc(v[s * N1 + cc], w) : cmul(v[s * N1 + cc], w);
     }
-#pragma unroll
-    for (int cc = 0; cc < NR; ++cc) E[(c * NR + cc) * STR + q] = v[c][cc];
   }
   __syncthreads();
+#pragma unroll
+  for (int av = 0; av < N2; ++av) v[av] = E[q * STR + av];
+  __syncthreads();
+  dft_reg<T, INV, N2>(v);
+}
+
+// Real-to-complex split S[kx] = E + conj(W^kx) O of a row whose half-length
+// transform X sits in the lanes as v[c][d] = X[q + N1 d]: lane q stores
+// kx = q + N1 d and (lane 0) kx = hx; the partner X[hx - kx] comes through
+// LDS.  Followed by no barrier: E is reused only after the next one.
+template <typename T, int N1, int N2>
+__device__ inline void rows_store_spectrum(const cpx<T> (&v)[3][N2], cpx<T>* E, int q, bool live,
+                                           cpx<T>* __restrict__ Srow, size_t cstride,
+                                           const cpx<T>* __restrict__ wpost) {
+  constexpr int hx = N1 * N2;
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int av = 0; av < NR; ++av) v[c][av] = E[(c * NR + q) * STR + av];
+    for (int d = 0; d < N2; ++d) E[c * hx + q + N1 * d] = v[c][d];
   __syncthreads();
+  if (!live) return;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    if (inv) dft_reg<T, true, NR>(v[c]); else dft_reg<T, false, NR>(v[c]);
+#pragma unroll
+    for (int d = 0; d <= N2; ++d) {
+      const int kx = (d < N2) ? q + N1 * d : hx;
+      if (d == N2 && q != 0) continue;
+      const cpx<T> Zk = E[c * hx + (kx == hx ? 0 : kx)];
+      cpx<T> Zc = E[c * hx + (kx == 0 ? 0 : hx - kx)];
+      Zc.im = -Zc.im;
+      const cpx<T> Ev = {T(0.5) * (Zk.re + Zc.re), T(0.5) * (Zk.im + Zc.im)};
+      const cpx<T> O = {T(0.5) * (Zk.re - Zc.re), T(0.5) * (Zk.im - Zc.im)};
+      const cpx<T> w = wpost[kx];
+      Srow[c * cstride + kx] = {Ev.re + (w.re * O.im + w.im * O.re),
+                                Ev.im - (w.re * O.re - w.im * O.im)};
+    }
   }
 }
 
-template <typename T, int NR, int MODE>
-__global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
-  static_assert(MODE == FM_HEUN1 || MODE == FM_HEUN2, "Heun stages only");
-  constexpr int hx = NR * NR, RPW = 64 / NR, STR = NR + 1;
-  __shared__ cpx<T> Es[RPW * 3 * NR * STR];
-  __shared__ double red[64];
-  const int lane = threadIdx.x, row = lane / NR, q = lane - row * NR;
+// The half spectrum of state m for the films of k_rows_reg, with the same
+// transform arithmetic as its forward part: a Heun run can then start (or
+// resume) from a state in global memory and take bit for bit the steps that
+// an uninterrupted run takes.
+template <typename T, int N1, int N2>
+__global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
+  static_assert(N2 % N1 == 0 && 64 % N1 == 0, "row split");
+  constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = N2 / N1;
+  constexpr int RS = 3 * hx;
+  __shared__ cpx<T> Es[RPW * RS];
+  const int lane = threadIdx.x, row = lane / N1, q = lane - row * N1;
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int r = bz, z = by, y = bx * RPW + row;
   const bool live = y < a.ny;
-  cpx<T>* E = Es + row * 3 * NR * STR;
+  cpx<T>* E = Es + row * RS;
+  const size_t rb = (size_t)r * 3 * a.N;
+  const unsigned N = (unsigned)a.N;
+  const int Kx = a.Kx;
+  cpx<T>* Srow = a.S + (((size_t)r * 3 * a.nz + z) * a.Sy + (live ? y : 0)) * Kx;
+  const size_t cstride = (size_t)a.nz * a.Sy * Kx;
+  const T* __restrict__ mr = a.m + rb;
+  const unsigned row0 = (unsigned)a.nx * (unsigned)(y + a.ny * z);
+  cpx<T> v[3][N2];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int s = 0; s < S2; ++s)
+#pragma unroll
+      for (int b = 0; b < N1; ++b) {
+        const int k = q + N1 * s + N2 * b;
+        const int x = 2 * k;
+        cpx<T> p = {0, 0};
+        if (live && x < a.nx) p.re = mr[c * N + row0 + x];
+        if (live && x + 1 < a.nx) p.im = mr[c * N + row0 + x + 1];
+        v[c][s * N1 + b] = p;
+      }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) line_transform<T, N1, N2, false>(v[c], E, q, a.tw);
+  rows_store_spectrum<T, N1, N2>(v, E, q, live, Srow, cstride, a.wpost);
+}
+
+template <typename T, int N1, int N2, int MODE>
+__global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
+  static_assert(MODE == FM_HEUN1 || MODE == FM_HEUN2, "Heun stages only");
+  static_assert(N2 % N1 == 0 && 64 % N1 == 0, "row split");
+  constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = N2 / N1;
+  constexpr int RS = 3 * hx;  // LDS per row (complex): the row's field, 3 components
+  static_assert(RS >= N1 * (N2 + 1), "transpose slots fit the row's LDS");
+  __shared__ cpx<T> Es[RPW * RS];
+  __shared__ double red[64];
+  const int lane = threadIdx.x, row = lane / N1, q = lane - row * N1;
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int r = bz, z = by, y = bx * RPW + row;
+  const bool live = y < a.ny;
+  cpx<T>* E = Es + row * RS;
+  T* Hs = reinterpret_cast<T*>(E);  // real view [c][x], 2 hx per component
   const size_t rb = (size_t)r * 3 * a.N;
   const unsigned N = (unsigned)a.N;
   const int Kx = a.Kx;
@@ -73,37 +149,38 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   cpx<T>* Srow = a.S + (((size_t)r * 3 * a.nz + z) * a.Sy + (live ? y : 0)) * Kx;
   const size_t cstride = (size_t)a.nz * a.Sy * Kx;
   const cpx<T>* __restrict__ tw = a.tw;  // exp(-2 pi i k / hx), k < hx
-  // 1. inverse x transform of the demag spectrum: lane q loads the packed
-  //    inputs Z[q + NR b] (complex-to-real combination of S[k], S[hx - k])
-  cpx<T> v[3][NR];
+  // 1. inverse x transform of the demag spectrum: inputs Z[k] at k = q + N1 s
+  //    + N2 b (complex-to-real combination of S[k] and S[hx - k])
+  cpx<T> v[3][N2];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int b = 0; b < NR; ++b) {
-      const int k = q + NR * b;
-      cpx<T> Zv = {0, 0};
-      if (live) {
-        const cpx<T> Xk = Srow[c * cstride + k];
-        cpx<T> Xc = Srow[c * cstride + (hx - k)];
-        Xc.im = -Xc.im;
-        const cpx<T> Ev = cadd(Xk, Xc);
-        const cpx<T> D = csub(Xk, Xc);
-        const cpx<T> O = cmulc(D, a.wpost[k]);  // D * conj(W^k)
-        Zv = {Ev.re - O.im, Ev.im + O.re};
+    for (int s = 0; s < S2; ++s)
+#pragma unroll
+      for (int b = 0; b < N1; ++b) {
+        const int k = q + N1 * s + N2 * b;
+        cpx<T> Zv = {0, 0};
+        if (live) {
+          const cpx<T> Xk = Srow[c * cstride + k];
+          cpx<T> Xc = Srow[c * cstride + (hx - k)];
+          Xc.im = -Xc.im;
+          const cpx<T> Ev = cadd(Xk, Xc);
+          const cpx<T> D = csub(Xk, Xc);
+          const cpx<T> O = cmulc(D, a.wpost[k]);  // D * conj(W^k)
+          Zv = {Ev.re - O.im, Ev.im + O.re};
+        }
+        v[c][s * N1 + b] = Zv;
       }
-      v[c][b] = Zv;
-    }
-  row_transform_step<T, NR>(v, E, q, tw, 1, true);
-  // lane q now holds z[q + NR d] = H_demag at cells x = 2 (q + NR d) + {0, 1};
-  // the row's field goes to LDS (real view, [c][x]) so that the cell loop
-  // below holds one cell at a time and each lane takes the cells x = q + NR j
-  T* Hs = reinterpret_cast<T*>(E);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) line_transform<T, N1, N2, true>(v[c], E, q, tw);
+  // lane q holds z[q + N1 d] = H_demag at cells x = 2 (q + N1 d) + {0, 1};
+  // stage the row's field in LDS
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int d = 0; d < NR; ++d) {
-      Hs[c * 2 * hx + 2 * (q + NR * d)] = v[c][d].re;
-      Hs[c * 2 * hx + 2 * (q + NR * d) + 1] = v[c][d].im;
+    for (int d = 0; d < N2; ++d) {
+      Hs[c * 2 * hx + 2 * (q + N1 * d)] = v[c][d].re;
+      Hs[c * 2 * hx + 2 * (q + N1 * d) + 1] = v[c][d].im;
     }
   __syncthreads();
   const T dt = (T)a.dth;
@@ -118,8 +195,8 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   T* k1_r = a.k1 + rb;
   double acc = 0;
 #pragma unroll 2
-  for (int j = 0; j < 2 * NR; ++j) {
-    const int x = q + NR * j;
+  for (int j = 0; j < 2 * N2; ++j) {
+    const int x = q + N1 * j;
     T mn_out[3] = {0, 0, 0};
     if (live && x < a.nx) {
       const unsigned cell = (unsigned)x + (unsigned)a.nx * (unsigned)(y + a.ny * z);
@@ -166,39 +243,21 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
     for (int c = 0; c < 3; ++c) Hs[c * 2 * hx + x] = mn_out[c];
   }
   __syncthreads();
+  // 2. forward x transform of the new state, inputs at k = q + N1 s + N2 b
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
-    for (int d = 0; d < NR; ++d)
-      v[c][d] = {Hs[c * 2 * hx + 2 * (q + NR * d)], Hs[c * 2 * hx + 2 * (q + NR * d) + 1]};
-  __syncthreads();
-  // 2. forward x transform of the new state; lane q ends with X[q + NR d']
-  row_transform_step<T, NR>(v, E, q, tw, 1, false);
-  // 3. real-to-complex split S[kx] = E + conj(W^kx) O, kx = q + NR d' and
-  //    (lane 0) kx = hx; the partner X[hx - kx] comes through LDS
+    for (int s = 0; s < S2; ++s)
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int d = 0; d < NR; ++d) E[c * hx + q + NR * d] = v[c][d];
-  __syncthreads();
-  if (live) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-#pragma unroll
-      for (int d = 0; d <= NR; ++d) {
-        const int kx = (d < NR) ? q + NR * d : hx;
-        if (d == NR && q != 0) continue;
-        const cpx<T> Zk = E[c * hx + (kx == hx ? 0 : kx)];
-        cpx<T> Zc = E[c * hx + (kx == 0 ? 0 : hx - kx)];
-        Zc.im = -Zc.im;
-        const cpx<T> Ev = {T(0.5) * (Zk.re + Zc.re), T(0.5) * (Zk.im + Zc.im)};
-        const cpx<T> O = {T(0.5) * (Zk.re - Zc.re), T(0.5) * (Zk.im - Zc.im)};
-        const cpx<T> w = a.wpost[kx];
-        Srow[c * cstride + kx] = {Ev.re + (w.re * O.im + w.im * O.re),
-                                  Ev.im - (w.re * O.re - w.im * O.im)};
+      for (int b = 0; b < N1; ++b) {
+        const int k = q + N1 * s + N2 * b;
+        v[c][s * N1 + b] = {Hs[c * 2 * hx + 2 * k], Hs[c * 2 * hx + 2 * k + 1]};
       }
-    }
-  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 3; ++c) line_transform<T, N1, N2, false>(v[c], E, q, tw);
+  // 3. the half spectrum of the new state
+  rows_store_spectrum<T, N1, N2>(v, E, q, live, Srow, cstride, a.wpost);
   if (MODE == FM_HEUN2) {
     // per-workgroup sum of m_z (fixed order) for the switching detector
     red[lane] = acc;
