@@ -13,6 +13,7 @@ constexpr double kMu0 = 4.0e-7 * kPi;
 constexpr double kKB = 1.380649e-23;
 
 constexpr int kMaxPass = 16;
+constexpr int kTensorStride = 8;  // reals per frequency of the tensor spectrum
 
 template <typename T>
 struct cpx {

@@ -28,7 +28,7 @@ struct HeunFusedArgs {
   const cpx<T>* tw_x;
   const cpx<T>* wpost;
   const cpx<T>* tw_y;
-  const T* Nt;          // [comp][Ty][Kx], 2-D: xx, yy, zz, xy
+  const T* Nt;          // [Ty][Kx][kTensorStride], 2-D: xx, yy, zz, xy used
   int Ty, Py;
   T* m;                 // state, updated in place
   T* ms;                // predictor state (stencil source of the corrector)
@@ -95,7 +95,6 @@ __device__ inline void fused_forward(const HeunFusedArgs<T>& a, const T* __restr
   }
   // phase 2: y transform, tensor product, inverse y transform on column chunks
   const int W = a.W, Py = a.Py;
-  const size_t cs = (size_t)a.Ty * Kx;
   for (int kx0 = 0; kx0 < Kx; kx0 += W) {
     for (int t = threadIdx.x; t < 3 * W * Py; t += blockDim.x) {
       const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, Py), c = udiv(rest, Py);
@@ -112,7 +111,7 @@ __device__ inline void fused_forward(const HeunFusedArgs<T>& a, const T* __restr
       const bool lo = 2 * ky <= Py;
       const int ty = lo ? ky : Py - ky;
       const T sy = lo ? T(1) : T(-1);
-      tensor_apply(a.Nt, cs, (size_t)ty * Kx + kx, sy, T(1), sy, false, Y[(0 * W + w) * Py + ky],
+      tensor_apply(a.Nt, (size_t)ty * Kx + kx, sy, T(1), sy, false, Y[(0 * W + w) * Py + ky],
                    Y[(1 * W + w) * Py + ky], Y[(2 * W + w) * Py + ky]);
     }
     __syncthreads();

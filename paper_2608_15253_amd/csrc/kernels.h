@@ -197,16 +197,19 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
 // ---------------------------------------------------------------------------
 // spectral tensor product helpers
 // ---------------------------------------------------------------------------
+// H = N M at one frequency; Nt points at its kTensorStride reals (xx, yy,
+// zz, xy, xz, yz); s.. restore the signs of the odd components per octant.
 template <typename T>
-__device__ inline void tensor_apply(const T* __restrict__ Nt, size_t cstride, size_t idx, T sxy,
-                                    T sxz, T syz, bool full, cpx<T>& X, cpx<T>& Y, cpx<T>& Z) {
-  const T nxx = Nt[idx], nyy = Nt[cstride + idx], nzz = Nt[2 * cstride + idx];
-  const T nxy = sxy * Nt[3 * cstride + idx];
+__device__ inline void tensor_apply(const T* __restrict__ Nt, size_t idx, T sxy, T sxz, T syz,
+                                    bool full, cpx<T>& X, cpx<T>& Y, cpx<T>& Z) {
+  const T* __restrict__ n = Nt + idx * kTensorStride;
+  const T nxx = n[0], nyy = n[1], nzz = n[2];
+  const T nxy = sxy * n[3];
   cpx<T> hx = {nxx * X.re + nxy * Y.re, nxx * X.im + nxy * Y.im};
   cpx<T> hy = {nxy * X.re + nyy * Y.re, nxy * X.im + nyy * Y.im};
   cpx<T> hz = {nzz * Z.re, nzz * Z.im};
   if (full) {
-    const T nxz = sxz * Nt[4 * cstride + idx], nyz = syz * Nt[5 * cstride + idx];
+    const T nxz = sxz * n[4], nyz = syz * n[5];
     hx.re += nxz * Z.re; hx.im += nxz * Z.im;
     hy.re += nyz * Z.re; hy.im += nyz * Z.im;
     hz.re += nxz * X.re + nyz * Y.re;
@@ -248,7 +251,6 @@ __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
   __syncthreads();
   cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, tw);
   cpx<T>* scratch = (X == A) ? Bf : A;
-  const size_t cs = (size_t)a.Tz * a.Ty * a.Kx;
   for (int t = threadIdx.x; t < W * Py; t += blockDim.x) {
     const int w = umod(t, W), ky = udiv(t, W), kx = kx0 + w;
     if (kx >= a.Kx) continue;
@@ -258,7 +260,7 @@ __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
     cpx<T>& Mx = X[(0 * W + w) * Py + ky];
     cpx<T>& My = X[(1 * W + w) * Py + ky];
     cpx<T>& Mz = X[(2 * W + w) * Py + ky];
-    tensor_apply(a.Nt, cs, (size_t)ty * a.Kx + kx, sy, T(1), sy, false, Mx, My, Mz);
+    tensor_apply(a.Nt, (size_t)ty * a.Kx + kx, sy, T(1), sy, false, Mx, My, Mz);
   }
   __syncthreads();
   const cpx<T>* Y = lds_fft<T, true>(X, scratch, nl, a.pi, tw);
@@ -321,7 +323,6 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
   __syncthreads();
   cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, tw);
   cpx<T>* scratch = (X == A) ? Bf : A;
-  const size_t cs = (size_t)a.Tz * a.Ty * a.Kx;
   const bool ylo = 2 * ky <= a.Py;
   const int ty = ylo ? ky : a.Py - ky;
   const T sy = ylo ? T(1) : T(-1);
@@ -334,7 +335,7 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
     cpx<T>& Mx = X[(0 * W + w) * Pz + kz];
     cpx<T>& My = X[(1 * W + w) * Pz + kz];
     cpx<T>& Mz = X[(2 * W + w) * Pz + kz];
-    tensor_apply(a.Nt, cs, ((size_t)tz * a.Ty + ty) * a.Kx + kx, sy, sz, sy * sz, true, Mx, My,
+    tensor_apply(a.Nt, ((size_t)tz * a.Ty + ty) * a.Kx + kx, sy, sz, sy * sz, true, Mx, My,
                  Mz);
   }
   __syncthreads();

@@ -391,7 +391,7 @@ mmx_status build_demag_group(mmx_ctx* ctx, Group& G) {
   MMX_TRY(line_fft(G.Py, Py * Px, 1, Px, (unsigned)Px, (unsigned)(6 * Pz)));     // columns
   MMX_TRY(line_fft(G.Pz, Pz * Py * Px, 1, Py * Px, (unsigned)(Py * Px), 6u));    // pillars
   const double scale = -G.mat.Ms / ((double)G.Px * G.Py * G.Pz);
-  HIP_TRY(G.Nt.alloc((size_t)6 * G.Tz * G.Ty * G.Kx * sizeof(T)));
+  HIP_TRY(G.Nt.alloc((size_t)kTensorStride * G.Tz * G.Ty * G.Kx * sizeof(T)));
   const long tot = (long)6 * G.Tz * G.Ty * G.Kx;
   k_compress<T><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(G.Nt.as<T>(), K.as<cpx<double>>(), G.Px,
                                                              G.Py, G.Pz, G.Kx, G.Ty, G.Tz, scale);

@@ -105,6 +105,12 @@ __global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
   const int Kx = a.Kx;
   cpx<T>* Srow = a.S + (((size_t)r * 3 * a.nz + z) * a.Sy + (live ? y : 0)) * Kx;
   const size_t cstride = (size_t)a.nz * a.Sy * Kx;
+  __shared__ cpx<T> twl[hx], wpl[hx + 1];  // transform and split tables
+  for (int i = lane; i <= hx; i += 64) {
+    if (i < hx) twl[i] = a.tw[i];
+    wpl[i] = a.wpost[i];
+  }
+  __syncthreads();
   const T* __restrict__ mr = a.m + rb;
   const unsigned row0 = (unsigned)a.nx * (unsigned)(y + a.ny * z);
   cpx<T> v[3][N2];
@@ -122,8 +128,8 @@ __global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
         v[c][s * N1 + b] = p;
       }
 #pragma unroll
-  for (int c = 0; c < 3; ++c) line_transform<T, N1, N2, false>(v[c], E, q, a.tw);
-  rows_store_spectrum<T, N1, N2>(v, E, q, live, Srow, cstride, a.wpost);
+  for (int c = 0; c < 3; ++c) line_transform<T, N1, N2, false>(v[c], E, q, twl);
+  rows_store_spectrum<T, N1, N2>(v, E, q, live, Srow, cstride, wpl);
 }
 
 template <typename T, int N1, int N2, int MODE>
@@ -148,7 +154,13 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   // spectrum row of component c: S[(((r 3 + c) nz + z) Sy + y) Kx + kx]
   cpx<T>* Srow = a.S + (((size_t)r * 3 * a.nz + z) * a.Sy + (live ? y : 0)) * Kx;
   const size_t cstride = (size_t)a.nz * a.Sy * Kx;
-  const cpx<T>* __restrict__ tw = a.tw;  // exp(-2 pi i k / hx), k < hx
+  __shared__ cpx<T> twl[hx], wpl[hx + 1];  // transform and split tables
+  for (int i = lane; i <= hx; i += 64) {
+    if (i < hx) twl[i] = a.tw[i];
+    wpl[i] = a.wpost[i];
+  }
+  __syncthreads();
+  const cpx<T>* tw = twl;  // exp(-2 pi i k / hx), k < hx
   // 1. inverse x transform of the demag spectrum: inputs Z[k] at k = q + N1 s
   //    + N2 b (complex-to-real combination of S[k] and S[hx - k])
   cpx<T> v[3][N2];
@@ -166,7 +178,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
           Xc.im = -Xc.im;
           const cpx<T> Ev = cadd(Xk, Xc);
           const cpx<T> D = csub(Xk, Xc);
-          const cpx<T> O = cmulc(D, a.wpost[k]);  // D * conj(W^k)
+          const cpx<T> O = cmulc(D, wpl[k]);  // D * conj(W^k)
           Zv = {Ev.re - O.im, Ev.im + O.re};
         }
         v[c][s * N1 + b] = Zv;
@@ -257,7 +269,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) line_transform<T, N1, N2, false>(v[c], E, q, tw);
   // 3. the half spectrum of the new state
-  rows_store_spectrum<T, N1, N2>(v, E, q, live, Srow, cstride, a.wpost);
+  rows_store_spectrum<T, N1, N2>(v, E, q, live, Srow, cstride, wpl);
   if (MODE == FM_HEUN2) {
     // per-workgroup sum of m_z (fixed order) for the switching detector
     red[lane] = acc;

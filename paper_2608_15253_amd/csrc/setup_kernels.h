@@ -72,7 +72,9 @@ __global__ void k_line_fft(cpx<double>* data, long os, long is, long stride, Fft
   for (int k = threadIdx.x; k < plan.n; k += blockDim.x) data[base + k * stride] = X[k];
 }
 
-// Nt[c][tz][ty][kx] = scale * Re Khat[c][tz][ty][kx] for kx <= Px/2, ty <= Py/2, tz <= Pz/2.
+// Nt[((tz Ty + ty) Kx + kx) 8 + c] = scale * Re Khat[c][tz][ty][kx] for
+// kx <= Px/2, ty <= Py/2, tz <= Pz/2: the six components of one frequency are
+// adjacent (slots 6, 7 unused), one aligned vector load per frequency.
 template <typename T>
 __global__ void k_compress(T* Nt, const cpx<double>* K, int Px, int Py, int Pz, int Kx, int Ty,
                            int Tz, double scale) {
@@ -84,7 +86,8 @@ __global__ void k_compress(T* Nt, const cpx<double>* K, int Px, int Py, int Pz, 
   const int tz = (id / ((long)Kx * Ty)) % Tz;
   const int c = id / ((long)Kx * Ty * Tz);
   const long full = (long)Px * Py * Pz;
-  Nt[id] = (T)(scale * K[(size_t)c * full + ((long)tz * Py + ty) * Px + kx].re);
+  const long f = ((long)tz * Ty + ty) * Kx + kx;
+  Nt[f * kTensorStride + c] = (T)(scale * K[(size_t)c * full + ((long)tz * Py + ty) * Px + kx].re);
 }
 
 // ---------------------------------------------------------------------------

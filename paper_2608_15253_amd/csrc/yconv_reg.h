@@ -48,7 +48,11 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
   const size_t plane = (size_t)a.Sy * Kx;  // one component of one replica (nz = 1)
   cpx<T>* S = a.S + (size_t)rep * 3 * plane + kx;
   cpx<T>* Ew = E + wc * N1 * STR;
-  const cpx<T>* __restrict__ tw = a.tw;
+  // twiddle table exp(-2 pi i k / n) staged in LDS (broadcast reads)
+  __shared__ cpx<T> twl[n];
+  for (int i = lane; i < n; i += 64) twl[i] = a.tw[i];
+  __syncthreads();
+  const cpx<T>* tw = twl;
   cpx<T> X[3][N2];
   // forward, step 1 per component (the next component's loads are issued
   // before the transpose of the current one): N1-point transforms over b for
@@ -83,14 +87,13 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) dft_reg<T, false, N2>(X[c]);
   if (live) {
-    const size_t cs = (size_t)a.Tz * a.Ty * Kx;
 #pragma unroll
     for (int d = 0; d < N2; ++d) {
       const int ky = q + N1 * d;
       const bool lo = 2 * ky <= n;
       const int ty = lo ? ky : n - ky;
       const T sy = lo ? T(1) : T(-1);
-      tensor_apply(a.Nt, cs, (size_t)ty * Kx + kx, sy, T(1), sy, false, X[0][d], X[1][d],
+      tensor_apply(a.Nt, (size_t)ty * Kx + kx, sy, T(1), sy, false, X[0][d], X[1][d],
                    X[2][d]);
     }
   }
