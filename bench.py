@@ -158,14 +158,22 @@ def traffic_summary(fetch_csv, write_csv, cmd, R):
         "traffic / algorithmic | value |",
         "|---|---|---|---|---|---|---|",
     ]
-    for short in ("k_xfwd", "k_yconv", "k_fields_heun1", "k_fields_heun2",
-                  "k_fields<float, 2>", "k_fields<float, 3>"):
-        f = find(fetch, short)
-        w = find(write, short)
+    # kernel names as the profiler reports them -> the names of the HIP-event
+    # profile (the Heun stages run as k_rows_reg<float, N1, N2, 2 | 3> where
+    # the register row kernel applies, else as k_fields<float, 2 | 3>)
+    def find_re(table, pattern):
+        for k, v in table.items():
+            if re.search(pattern, k):
+                return v
+        return None
+    patterns = [("k_xfwd", r"k_xfwd<|k_rows_fwd<"), ("k_yconv", r"k_yconv"),
+                ("k_fields_heun1", r"k_rows_reg<float, \d+, \d+, 2>|k_fields<float, 2>"),
+                ("k_fields_heun2", r"k_rows_reg<float, \d+, \d+, 3>|k_fields<float, 3>")]
+    for label, pat in patterns:
+        f = find_re(fetch, pat)
+        w = find_re(write, pat)
         if not f or not w:
             continue
-        label = {"k_fields<float, 2>": "k_fields_heun1",
-                 "k_fields<float, 3>": "k_fields_heun2"}.get(short, short)
         traffic = f[0] * 1024 * sf + w[0] * 1024 * sw
         alg = algorithmic_bytes(label, R, 64, 64, 4)
         ratio = f"{traffic / alg:.2f}" if alg else "-"
