@@ -342,6 +342,8 @@ def cpu_baseline(seconds: float = 12.0):
     from oracle import Grid, Material
     from oracle import integrators as oit
     from workloads import replica_seeds, uniform
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)  # the sample runs on one host core
     R = 16
     grid = Grid((64, 64, 1), (4e-9, 4e-9, 4e-9))
     mat = Material(Ms=8.0e5, A=1.3e-11, alpha=0.02, Ku=5e5, B=(0, 0, -0.15), T=300.0)
