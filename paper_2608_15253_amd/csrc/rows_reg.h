@@ -66,21 +66,28 @@ __device__ inline void rows_store_spectrum(const cpx<T> (&v)[3][N2], cpx<T>* E, 
     for (int d = 0; d < N2; ++d) E[c * hx + q + N1 * d] = v[c][d];
   __syncthreads();
   if (!live) return;
+  auto split = [&](int c, int kx) -> cpx<T> {
+    const cpx<T> Zk = E[c * hx + (kx == hx ? 0 : kx)];
+    cpx<T> Zc = E[c * hx + (kx == 0 ? 0 : hx - kx)];
+    Zc.im = -Zc.im;
+    const cpx<T> Ev = {T(0.5) * (Zk.re + Zc.re), T(0.5) * (Zk.im + Zc.im)};
+    const cpx<T> O = {T(0.5) * (Zk.re - Zc.re), T(0.5) * (Zk.im - Zc.im)};
+    const cpx<T> w = wpost[kx];
+    return {Ev.re + (w.re * O.im + w.im * O.re), Ev.im - (w.re * O.re - w.im * O.im)};
+  };
+  // each lane stores two adjacent columns per instruction (a row's N1 lanes
+  // cover 2 N1 consecutive columns), lane 0 also the last column kx = hx
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
-    for (int d = 0; d <= N2; ++d) {
-      const int kx = (d < N2) ? q + N1 * d : hx;
-      if (d == N2 && q != 0) continue;
-      const cpx<T> Zk = E[c * hx + (kx == hx ? 0 : kx)];
-      cpx<T> Zc = E[c * hx + (kx == 0 ? 0 : hx - kx)];
-      Zc.im = -Zc.im;
-      const cpx<T> Ev = {T(0.5) * (Zk.re + Zc.re), T(0.5) * (Zk.im + Zc.im)};
-      const cpx<T> O = {T(0.5) * (Zk.re - Zc.re), T(0.5) * (Zk.im - Zc.im)};
-      const cpx<T> w = wpost[kx];
-      Srow[c * cstride + kx] = {Ev.re + (w.re * O.im + w.im * O.re),
-                                Ev.im - (w.re * O.re - w.im * O.im)};
+    for (int d = 0; d < N2 / 2; ++d) {
+      const int kx = 2 * q + 2 * N1 * d;
+      const cpx<T> s0 = split(c, kx), s1 = split(c, kx + 1);
+      cpx<T>* dst = Srow + c * cstride + kx;
+      dst[0] = s0;
+      dst[1] = s1;
     }
+    if (q == 0) Srow[c * cstride + hx] = split(c, hx);
   }
 }
 
