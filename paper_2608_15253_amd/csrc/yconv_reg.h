@@ -45,8 +45,16 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
   const int kx = tile * NC + wc;
   const bool live = kx < a.Kx;
   const int Kx = a.Kx;
-  const size_t plane = (size_t)a.Sy * Kx;  // one component of one replica (nz = 1)
-  cpx<T>* S = a.S + (size_t)rep * 3 * plane + kx;
+  // one component of one replica (nz = 1); offsets within the replica are
+  // 32-bit on a workgroup-uniform base pointer (one address register per
+  // access instead of a 64-bit pair)
+  const unsigned plane = (unsigned)a.Sy * (unsigned)Kx;
+  cpx<T>* __restrict__ S = a.S + (size_t)rep * 3 * plane;
+  const unsigned off0 = (unsigned)q * (unsigned)Kx + (unsigned)kx;
+  // element i of the replica's spectrum: 32-bit byte offset on the uniform base
+  auto at = [&](unsigned i) -> cpx<T>& {
+    return *reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(S) + i * (unsigned)sizeof(cpx<T>));
+  };
   cpx<T>* Ew = E + wc * N1 * STR;
   // twiddle table exp(-2 pi i k / n) staged in LDS (broadcast reads)
   __shared__ cpx<T> twl[n];
@@ -63,8 +71,9 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
     for (int s = 0; s < S2; ++s)
 #pragma unroll
       for (int b = 0; b < N1; ++b)
-        v[s][b] = (b < NB && live) ? S[c * plane + (size_t)(q + N1 * s + N2 * b) * Kx]
-                                   : cpx<T>{0, 0};
+        v[s][b] = (b < NB && live)
+                      ? at(off0 + (unsigned)c * plane + (unsigned)(N1 * s + N2 * b) * (unsigned)Kx)
+                      : cpx<T>{0, 0};
   };
   load(0);
 #pragma unroll
@@ -115,7 +124,8 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
       dft_reg<T, true, N1>(u);
       if (live) {
 #pragma unroll
-        for (int b = 0; b < NB; ++b) S[c * plane + (size_t)(av + N2 * b) * Kx] = u[b];
+        for (int b = 0; b < NB; ++b)
+          at(off0 + (unsigned)c * plane + (unsigned)(N1 * s + N2 * b) * (unsigned)Kx) = u[b];
       }
     }
     __syncthreads();
