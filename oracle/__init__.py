@@ -14,10 +14,10 @@ FFT and linear algebra serve as library primitives.
 Pins (``tests/test_oracle_*.py``, run with ``-m "not gpu"``) tie each part to
 something other than itself: closed forms (cube self-term 1/3, trace identities,
 point-dipole far field, whole-body identity, exact spin-wave dispersion, damped
-macrospin, Kittel, Langevin), brute force (direct O(N^2) convolution, 50-digit
+macrospin, Kittel, Langevin, exact precession of the rotation scheme), brute force (direct O(N^2) convolution, 50-digit
 mpmath Newell values) and invariants (|m| = 1, m . dm/dt = 0, energy decay).
-Parity unpinned: the exact Philox stream (no published known-answer vectors are
-available here; checked statistically and bit-for-bit against the GPU), the
+The Philox generator is pinned by the known-answer vectors published with it
+(Salmon et al. 2011).  Parity unpinned: the
 interfacial-DMI edge ghosts against another code (closed forms pin the bulk
 stencil only), long-horizon thermal trajectories (chaotic; statistical only),
 and the behaviour of trained network weights (the network's arithmetic and the
@@ -26,6 +26,8 @@ learned-stage attempt are pinned; what training reaches is not).
 from .constants import GAMMA0, MU0, KB
 from .problem import Grid, Material
 from . import newell, demag, fields, llg, philox, integrators, observables, fno, surrogate
+from . import rotation
 
 __all__ = ["GAMMA0", "MU0", "KB", "Grid", "Material", "newell", "demag",
-           "fields", "llg", "philox", "integrators", "observables", "fno", "surrogate"]
+           "fields", "llg", "philox", "integrators", "observables", "fno", "surrogate",
+           "rotation"]

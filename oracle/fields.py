@@ -126,16 +126,17 @@ def thermal_sigma(grid, mat, dt):
                      (MU0 ** 2 * mat.Ms * grid.volume * GAMMA0 * dt))
 
 
-def thermal_field(grid, mat, dt, seed, step):
+def thermal_field(grid, mat, dt, seed, step, gen=0):
     """Brown field for one replica (scalar ``seed``) or a batch (array of
-    per-replica seeds -> (R, 3, nz, ny, nx))."""
+    per-replica seeds -> (R, 3, nz, ny, nx)); ``gen`` is the trial generation
+    (counter word 3) of the retire/refill scheme."""
     nx, ny, nz = grid.n
     seeds = np.atleast_1d(np.asarray(seed, dtype=np.uint64))
     s = thermal_sigma(grid, mat, dt)
     if s == 0.0:
         out = np.zeros((seeds.size, 3, nz, ny, nx))
     else:
-        out = s * _philox.gaussian_eta(seeds, grid.ncells, step).reshape(seeds.size, 3, nz, ny, nx)
+        out = s * _philox.gaussian_eta(seeds, grid.ncells, step, gen).reshape(seeds.size, 3, nz, ny, nx)
     return out if np.ndim(seed) else out[0]
 
 

@@ -11,7 +11,8 @@ round key, and a Weyl increment of the key between rounds.
 
 Reading of the key/counter mapping (the paper does not fix it): key = the
 replica's 64-bit seed (low word, high word); counter = (cell index within the
-replica, step low word, step high word, 0).  Uniforms u = (x + 1/2) 2^-32;
+replica, step low word, step high word, trial generation g), with g = 0
+except for the refilled trials of the retire/refill scheme.  Uniforms u = (x + 1/2) 2^-32;
 Box-Muller on (u0, u1) and (u2, u3) gives four normals, of which the first three
 are the x, y, z components of eta.
 """
@@ -44,9 +45,9 @@ def philox4x32_10(ctr, key):
     return np.stack(c, axis=-1)
 
 
-def raw_words(seeds, ncell, step):
+def raw_words(seeds, ncell, step, gen=0):
     """Raw Philox output words (R, ncell, 4) for cells 0..ncell-1 of each
-    replica key in ``seeds`` (R,) at ``step``."""
+    replica key in ``seeds`` (R,) at ``step`` (trial generation ``gen``)."""
     seeds = np.atleast_1d(np.asarray(seeds, dtype=np.uint64))
     step = int(step)
     R = seeds.size
@@ -54,16 +55,17 @@ def raw_words(seeds, ncell, step):
     ctr[:, :, 0] = np.arange(ncell, dtype=np.uint64)[None, :]
     ctr[:, :, 1] = step & 0xFFFFFFFF
     ctr[:, :, 2] = (step >> 32) & 0xFFFFFFFF
+    ctr[:, :, 3] = int(gen) & 0xFFFFFFFF
     key = np.zeros((R, ncell, 2), dtype=np.uint64)
     key[:, :, 0] = (seeds & np.uint64(0xFFFFFFFF))[:, None]
     key[:, :, 1] = (seeds >> np.uint64(32))[:, None]
     return philox4x32_10(ctr, key)
 
 
-def gaussian_eta(seeds, ncell, step):
+def gaussian_eta(seeds, ncell, step, gen=0):
     """eta (R, 3, ncell) ~ N(0, 1) i.i.d. for the replica keys ``seeds`` at
-    ``step``."""
-    x = raw_words(seeds, ncell, step).astype(np.float64)
+    ``step`` (trial generation ``gen``)."""
+    x = raw_words(seeds, ncell, step, gen).astype(np.float64)
     u = (x + 0.5) * 2.0 ** -32
     r01 = np.sqrt(-2.0 * np.log(u[..., 0]))
     r23 = np.sqrt(-2.0 * np.log(u[..., 2]))

@@ -1,5 +1,6 @@
-"""Pins of the oracle's thermal noise: statistics of the counter-based
-Philox4x32-10 stream (Salmon et al. 2011) and the Langevin law of a thermal
+"""Pins of the oracle's thermal noise: the published known-answer vectors and
+the statistics of the counter-based Philox4x32-10 stream (Salmon et al. 2011),
+the trial-generation counter word, and the Langevin law of a thermal
 macrospin (Results, "A replica-batched engine": <m_z> = L(xi))."""
 import json
 import math
@@ -15,6 +16,28 @@ from oracle import philox
 from workloads import replica_seeds
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_philox_known_answer_vectors():
+    with open(os.path.join(GOLDEN, "philox_kat.json")) as fh:
+        kat = json.load(fh)["vectors"]
+    for v in kat:
+        ctr = np.array([int(x, 16) for x in v["ctr"]], dtype=np.uint64)
+        key = np.array([int(x, 16) for x in v["key"]], dtype=np.uint64)
+        out = philox.philox4x32_10(ctr, key)
+        assert ["%08x" % int(x) for x in out] == v["out"]
+
+
+def test_trial_generation_is_the_fourth_counter_word():
+    """Generation 0 is the plain stream; generation g sets counter word 3."""
+    seeds = np.array([7, 2 ** 40 + 3], dtype=np.uint64)
+    w0 = philox.raw_words(seeds, 16, 5)
+    assert np.array_equal(w0, philox.raw_words(seeds, 16, 5, gen=0))
+    w3 = philox.raw_words(seeds, 16, 5, gen=3)
+    ctr = np.array([2, 5, 0, 3], dtype=np.uint64)
+    key = np.array([3, 256], dtype=np.uint64)  # seed 2^40 + 3: low word 3, high word 2^8
+    assert np.array_equal(w3[1, 2], philox.philox4x32_10(ctr, key))
+    assert not np.array_equal(w0, w3)
 
 
 def test_philox_words_uniform_and_decorrelated():
