@@ -148,6 +148,36 @@ mmx_status mmx_torque(mmx_ctx* ctx, const void* m, void* dmdt, uint64_t step, do
 mmx_status mmx_heun(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
                     void* t_switch);
 
+/* n_steps steps of the norm-exact Depondt-Mertens rotation scheme (Results,
+ * "A replica-batched engine": Rodrigues update, |m| = 1 to round-off;
+ * Methods, "Integrators" and "Replica batching"), in place on m (device, D1).
+ * The LLG equation is taken as dm/dt = Omega x m, Omega = gamma' mu0 (H +
+ * alpha m x H).  Per step, with the thermal field drawn once (as mmx_heun):
+ * Omega_1 at m; predictor m~ = rotation of m about Omega_1 by |Omega_1| dt;
+ * Omega_2 at m~; the new state is the rotation of m about (Omega_1 +
+ * Omega_2)/2 by |Omega_1 + Omega_2| dt/2.  No normalisation.  Step numbering
+ * and t_switch as in mmx_heun.  Runs on the staged path (MMX_EUNSUP under
+ * MMX_PATH_FUSED). */
+mmx_status mmx_depondt(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
+                       void* t_switch);
+
+/* Retire/refill trials of the rotation scheme (Results, "A replica-batched
+ * engine": a trial that meets its stop condition is frozen and its slot
+ * restarts with a fresh noise stream).  Every replica r starts trial g = 0
+ * from m (device, D1) at step step0; after each step, a replica whose mean
+ * m_z is negative ends its trial: the trial's length (steps since its start
+ * + 1) * dt goes to times[r * cap + g] (device double[R_total][cap], entries
+ * set to -1 first, only the first cap trials recorded), counts[r] (device
+ * int32[R_total], set to 0 first) is incremented, and the replica restarts
+ * at the next step from its row of m_init (device, D1, not modified) with
+ * trial g + 1, whose thermal noise uses counter word 3 = g + 1 and step
+ * numbers counted from the trial's start (trial 0 is the noise of
+ * mmx_depondt).  Each call starts a fresh set of trials.  MMX_EINVAL for
+ * null m, m_init or counts, cap < 0, or null times with cap > 0. */
+mmx_status mmx_depondt_refill(mmx_ctx* ctx, void* m, const void* m_init, double dt,
+                              int64_t n_steps, uint64_t step0, void* times, int32_t cap,
+                              void* counts);
+
 /* Adaptive Dormand-Prince 5(4) relaxation (Methods, "Integrators") of m
  * (device, D1, in place) from t0 to t_end with absolute tolerance tol on the
  * max-over-cells Euclidean norm of the embedded error; first attempt dt0;

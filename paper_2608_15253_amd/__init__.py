@@ -82,6 +82,9 @@ _SIGS = {
     "mmx_field": [_P, _P, _P, ctypes.c_uint64, ctypes.c_double],
     "mmx_torque": [_P, _P, _P, ctypes.c_uint64, ctypes.c_double],
     "mmx_heun": [_P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P],
+    "mmx_depondt": [_P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P],
+    "mmx_depondt_refill": [_P, _P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P,
+                           ctypes.c_int32, _P],
     "mmx_rk45": [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                  ctypes.POINTER(ctypes.c_double), ctypes.c_int64, _P, ctypes.c_int64,
                  ctypes.POINTER(mmx_rk_stats)],
@@ -205,6 +208,17 @@ def mmx_torque(ctx, m, dmdt, step=0, dt=0.0) -> None:
 def mmx_heun(ctx, m, dt, n_steps, step0=0, t_switch=None) -> None:
     _check("mmx_heun", _lib.mmx_heun(ctx, _ptr(m), float(dt), int(n_steps), int(step0),
                                      _ptr(t_switch)))
+
+
+def mmx_depondt(ctx, m, dt, n_steps, step0=0, t_switch=None) -> None:
+    _check("mmx_depondt", _lib.mmx_depondt(ctx, _ptr(m), float(dt), int(n_steps), int(step0),
+                                           _ptr(t_switch)))
+
+
+def mmx_depondt_refill(ctx, m, m_init, dt, n_steps, times, cap, counts, step0=0) -> None:
+    _check("mmx_depondt_refill",
+           _lib.mmx_depondt_refill(ctx, _ptr(m), _ptr(m_init), float(dt), int(n_steps),
+                                   int(step0), _ptr(times), int(cap), _ptr(counts)))
 
 
 def mmx_rk45(ctx, m, t0, t_end, tol, dt0=1e-14, dt_replay=None, energy_trace=None,

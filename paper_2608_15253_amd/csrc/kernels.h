@@ -387,6 +387,9 @@ struct FArgs {
   int fwd;            // Heun epilogues: also x-transform the new state into S
   FftPlan plan_f;     // forward x plan (pruned like the one of k_xfwd)
   T* hd_out;          // if set: the exact demag field is also stored here
+  int rot;            // Heun epilogues take the rotation (Depondt-Mertens) update
+  const int* tgen;    // retire/refill: trial generation of each replica (noise word 3)
+  const unsigned long long* tstart;  // and the first step of its running trial
 };
 
 template <typename T>
@@ -459,6 +462,93 @@ __device__ inline void llg_torque(const T mc[3], const T H[3], T gpm, T alpha, T
   k[0] = -gpm * (cx + alpha * dx);
   k[1] = -gpm * (cy + alpha * dy);
   k[2] = -gpm * (cz + alpha * dz);
+}
+
+// The LLG equation as a rotation, dm/dt = Omega x m with Omega =
+// gamma' mu0 (H + alpha m x H) (Results, replica-batched engine: norm-exact
+// Depondt-Mertens rotation scheme).
+template <typename T>
+__device__ inline void llg_omega(const T mc[3], const T H[3], T gpm, T alpha, T o[3]) {
+  const T cx = mc[1] * H[2] - mc[2] * H[1];
+  const T cy = mc[2] * H[0] - mc[0] * H[2];
+  const T cz = mc[0] * H[1] - mc[1] * H[0];
+  o[0] = gpm * (H[0] + alpha * cx);
+  o[1] = gpm * (H[1] + alpha * cy);
+  o[2] = gpm * (H[2] + alpha * cz);
+}
+
+// Rodrigues rotation of v about w by the angle |w|:
+// v cos|w| + (w x v) sin|w|/|w| + w (w.v) (1 - cos|w|)/|w|^2, with
+// 1 - cos|w| = 2 sin^2(|w|/2) (no cancellation) and Taylor series of both
+// ratios below |w| = 1e-3.
+template <typename T>
+__device__ inline void rodrigues(const T v[3], const T w[3], T out[3]) {
+  const T t2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
+  T s1, s2;  // sin|w| / |w|, (1 - cos|w|) / |w|^2
+  if (t2 < T(1e-6)) {
+    s1 = T(1) - t2 * (T(1) / T(6) - t2 * (T(1) / T(120)));
+    s2 = T(0.5) - t2 * (T(1) / T(24) - t2 * (T(1) / T(720)));
+  } else {
+    const T t = sqrt(t2);
+    const T sh = sin(T(0.5) * t);
+    s1 = sin(t) / t;
+    s2 = T(2) * sh * sh / t2;
+  }
+  const T c = T(1) - t2 * s2;  // cos|w|
+  const T wv = w[0] * v[0] + w[1] * v[1] + w[2] * v[2];
+  out[0] = c * v[0] + s1 * (w[1] * v[2] - w[2] * v[1]) + s2 * wv * w[0];
+  out[1] = c * v[1] + s1 * (w[2] * v[0] - w[0] * v[2]) + s2 * wv * w[1];
+  out[2] = c * v[2] + s1 * (w[0] * v[1] - w[1] * v[0]) + s2 * wv * w[2];
+}
+
+// Heun-stage epilogues shared by the field kernels.  Predictor: k1 <- slope,
+// m~ = m + dt k (Heun) or k1 <- Omega, m~ = rotation of m by dt Omega.
+// Corrector from the saved state mo and k1: normalised m + dt/2 (k1 + k)
+// (Heun) or the rotation of mo by dt/2 (Omega_1 + Omega_2), not normalised.
+template <typename T>
+__device__ inline void heun_predict(const FArgs<T>& a, bool rot, const T mc[3], const T H[3],
+                                    const T k[3], T dt, T k1v[3], T mn[3]) {
+  if (rot) {
+    T w[3];
+    llg_omega(mc, H, a.gpm, a.alpha, k1v);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[c] = dt * k1v[c];
+    rodrigues(mc, w, mn);
+  } else {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      k1v[c] = k[c];
+      mn[c] = mc[c] + dt * k[c];
+    }
+  }
+}
+
+template <typename T>
+__device__ inline void heun_correct(const FArgs<T>& a, bool rot, const T mc[3], const T H[3],
+                                    const T k[3], const T mo[3], const T k1v[3], T dt, T mn[3]) {
+  if (rot) {
+    T o[3], w[3];
+    llg_omega(mc, H, a.gpm, a.alpha, o);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) w[c] = T(0.5) * dt * (k1v[c] + o[c]);
+    rodrigues(mo, w, mn);
+  } else {
+    T u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) u[c] = mo[c] + T(0.5) * dt * (k1v[c] + k[c]);
+    const T inv = T(1) / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mn[c] = u[c] * inv;
+  }
+}
+
+// Step index and trial generation of the thermal noise of replica r.
+template <typename T>
+__device__ inline uint64_t noise_step(const FArgs<T>& a, int r, uint64_t step_now, uint32_t& gen) {
+  gen = 0;
+  if (!a.tgen) return step_now;
+  gen = (uint32_t)a.tgen[r];
+  return step_now - a.tstart[r];
 }
 
 template <typename T, int MODE>
@@ -572,7 +662,9 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
     for (int c = 0; c < 3; ++c) H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + Hdd[c];
     if (sigma != T(0)) {
       T eta[3];
-      thermal_eta<T>(a.seeds[r], (uint32_t)cell, step_now, eta);
+      uint32_t gen;
+      const uint64_t sn = noise_step(a, r, step_now, gen);
+      thermal_eta<T>(a.seeds[r], (uint32_t)cell, sn, eta, gen);
 #pragma unroll
       for (int c = 0; c < 3; ++c) H[c] += sigma * eta[c];
     }
@@ -587,27 +679,26 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) out_r[c * N + cell] = k[c];
     } else if (MODE == FM_HEUN1) {
+      T k1v[3], mn[3];
+      heun_predict(a, a.rot != 0, mc, H, k, dt, k1v, mn);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const T mn = mc[c] + dt * k[c];
-        k1_r[c * N + cell] = k[c];
-        mout_r[c * N + cell] = mn;
-        if (fwd) F[(c * L + l) * 2 * hx + x] = mn;
+        k1_r[c * N + cell] = k1v[c];
+        mout_r[c * N + cell] = mn[c];
+        if (fwd) F[(c * L + l) * 2 * hx + x] = mn[c];
       }
     } else if (MODE == FM_HEUN2) {
       T mo[3], k1v[3];
       ld3(a.m0 + rb, N, cell, mo);
       ld3(k1_r, N, cell, k1v);
       T mn[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) mn[c] = mo[c] + T(0.5) * dt * (k1v[c] + k[c]);
-      const T inv = T(1) / sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
+      heun_correct(a, a.rot != 0, mc, H, k, mo, k1v, dt, mn);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        mout_r[c * N + cell] = mn[c] * inv;
-        if (fwd) F[(c * L + l) * 2 * hx + x] = mn[c] * inv;
+        mout_r[c * N + cell] = mn[c];
+        if (fwd) F[(c * L + l) * 2 * hx + x] = mn[c];
       }
-      acc[0] += (double)(mn[2] * inv);
+      acc[0] += (double)mn[2];
     } else if (MODE == FM_RK7) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) out_r[c * N + cell] = k[c];

@@ -121,6 +121,7 @@ struct DevBuf {
     if (b == 0) return hipSuccess;
     return hipMalloc(&p, b);
   }
+  hipError_t ensure(size_t b) { return (p && bytes == b) ? hipSuccess : alloc(b); }
   template <typename U> U* as() const { return reinterpret_cast<U*>(p); }
 };
 
@@ -137,6 +138,7 @@ struct Group {
   size_t off = 0;  // element offset of this group in caller arrays
   // device buffers
   DevBuf tw_x, wpost, tw_y, tw_z, Nt, S, ms, m7, k[7], Trep, seeds, partial, E;
+  DevBuf tgen, tstart, tflag, S_init;  // retire/refill trials
   int nblk = 1;       // k_fields workgroups per replica
   int nblk_last = 1;  // workgroups per replica of the last field-kernel launch
   int demag_built = 0;
@@ -246,6 +248,8 @@ struct mmx_ctx {
   double hext_scale = 0, hext_mz = 0;
   void* hd_out = nullptr;
   DevBuf sg_h, sg_hd, sg_part, sg_err;  // surrogate integrator buffers
+  int rot = 0;     // Heun epilogues take the rotation update (mmx_depondt*)
+  int refill = 0;  // per-replica trial generation and start step (mmx_depondt_refill)
 };
 
 namespace {
@@ -461,6 +465,11 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   a.plan = G.plan_xi;  // inverse transform: full input
   a.tw = G.tw_x.as<cpx<T>>();
   a.wpost = G.wpost.as<cpx<T>>();
+  a.rot = ctx->rot;
+  if (ctx->refill) {
+    a.tgen = G.tgen.as<int>();
+    a.tstart = G.tstart.as<unsigned long long>();
+  }
   return a;
 }
 
@@ -477,7 +486,7 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
     if (mode != -1 && !a.fwd) return false;
     if (G.xone || a.hext || a.hd_out) return false;
     hipStream_t s = ctx->stream;
-    auto go = [&](auto k1, auto k2, auto kf, int rpw) {
+    auto go = [&](auto k1, auto k2, auto r1, auto r2, auto kf, int rpw) {
       const int gx = (G.ny + rpw - 1) / rpw;
       const dim3 grid(gx, G.nz, G.R);
       if (mode == -1) {
@@ -485,12 +494,18 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
         return true;
       }
       G.nblk_last = gx * G.nz;
-      if (mode == FM_HEUN1) k1<<<grid, 64, 0, s>>>(a);
-      else k2<<<grid, 64, 0, s>>>(a);
+      if (mode == FM_HEUN1) {
+        if (a.rot) r1<<<grid, 64, 0, s>>>(a);
+        else k1<<<grid, 64, 0, s>>>(a);
+      } else {
+        if (a.rot) r2<<<grid, 64, 0, s>>>(a);
+        else k2<<<grid, 64, 0, s>>>(a);
+      }
       return true;
     };
-#define MMX_ROWS(N1, N2, RPW)                                                   \
-  go(k_rows_reg<float, N1, N2, FM_HEUN1>, k_rows_reg<float, N1, N2, FM_HEUN2>, \
+#define MMX_ROWS(N1, N2, RPW)                                                                   \
+  go(k_rows_reg<float, N1, N2, FM_HEUN1, false>, k_rows_reg<float, N1, N2, FM_HEUN2, false>, \
+     k_rows_reg<float, N1, N2, FM_HEUN1, true>, k_rows_reg<float, N1, N2, FM_HEUN2, true>,   \
      k_rows_fwd<float, N1, N2>, RPW)
     switch (G.hx) {
       case 16: return MMX_ROWS(4, 4, 16);
@@ -1007,14 +1022,42 @@ mmx_status heun_fused(mmx_ctx* ctx, Group& G, const FusedTiles& ft, T* mg, doubl
   return MMX_OK;
 }
 
+// Retire/refill trials of the rotation scheme: every replica restarts from
+// its row of m_init (device, D1) after the step at which its mean m_z turns
+// negative; times (device double[R_total][cap]) and counts (device
+// int[R_total]) receive the trial durations and the number of finished trials.
+struct RefillArgs {
+  const void* m_init = nullptr;
+  double* times = nullptr;
+  int* counts = nullptr;
+  int cap = 0;
+};
+
+// Sets ctx->rot / ctx->refill for the duration of one integrator call.
+struct SchemeScope {
+  mmx_ctx* c;
+  SchemeScope(mmx_ctx* ctx, int rot, int refill) : c(ctx) {
+    c->rot = rot;
+    c->refill = refill;
+  }
+  ~SchemeScope() {
+    c->rot = 0;
+    c->refill = 0;
+  }
+};
+
 template <typename T>
 mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
-                     void* tsw) {
+                     void* tsw, int rot = 0, const RefillArgs* rf = nullptr) {
   if (!(dt > 0)) return fail(MMX_EINVAL, "dt must be > 0");
   if (n_steps < 0) return fail(MMX_EINVAL, "n_steps must be >= 0");
   hipStream_t s = ctx->stream;
   T* mb = reinterpret_cast<T*>(m);
   double* tsw_d = reinterpret_cast<double*>(tsw);
+  const bool refill = rf != nullptr;
+  if ((rot || refill) && ctx->path == MMX_PATH_FUSED)
+    return fail(MMX_EUNSUP, "the rotation scheme runs on the staged path only");
+  SchemeScope scheme(ctx, rot, refill ? 1 : 0);
   // groups on the replica-resident path advance all steps at once
   std::vector<int> staged;
   {
@@ -1024,8 +1067,9 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       const FusedTiles ft = fused_tiles<T>(ctx, G);
       if (ctx->path == MMX_PATH_FUSED && !ft.ok)
         return fail(MMX_EUNSUP, "group does not fit the replica-resident path");
-      const bool use_fused = ft.ok && (ctx->path == MMX_PATH_FUSED ||
-                                       (ctx->path == MMX_PATH_AUTO && G.fused_faster));
+      const bool use_fused = !rot && !refill && ft.ok &&
+                             (ctx->path == MMX_PATH_FUSED ||
+                              (ctx->path == MMX_PATH_AUTO && G.fused_faster));
       if (use_fused) {
         MMX_TRY(heun_fused<T>(ctx, G, ft, mb + G.off, dt, n_steps, step0,
                               tsw_d ? tsw_d + roff : nullptr));
@@ -1070,6 +1114,23 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       e2.fwd = 1;
       MMX_TRY(eval_group<T>(ctx, G, G.ms.as<T>(), Combine{}, e2, step, dt, nullptr, dt, nullptr,
                             0xFFFFFFFFu, true));
+      if (refill) {
+        ProfScope ps(ctx->prof, "k_refill", st);
+        k_refill_check<<<(G.R + 63) / 64, 64, 0, st>>>(
+            G.partial.as<double>(), G.nblk_last, G.R, G.N, G.tgen.as<int>(),
+            G.tstart.as<unsigned long long>(), G.tflag.as<int>(), rf->counts + roff,
+            rf->times + (size_t)roff * rf->cap, rf->cap, (unsigned long long)step,
+            ctx->cur_stepdev, dt);
+        HIP_TRY(hipGetLastError());
+        const size_t n = (size_t)3 * G.N;
+        const size_t ns = (ctx->terms & MMX_DEMAG) ? (size_t)3 * G.nz * G.Sy * G.Kx : 0;
+        const size_t big = std::max(n, ns);
+        const dim3 grid((unsigned)std::min<size_t>((big + 255) / 256, 64), (unsigned)G.R);
+        k_refill_copy<T><<<grid, 256, 0, st>>>(
+            G.tflag.as<int>(), mg, reinterpret_cast<const T*>(rf->m_init) + G.off, n,
+            ns ? G.S.as<cpx<T>>() : nullptr, ns ? G.S_init.as<cpx<T>>() : nullptr, ns);
+        HIP_TRY(hipGetLastError());
+      }
       if (tsw_d) {
         ProfScope ps(ctx->prof, "k_switch_reduce", st);
         k_switch_reduce<<<(G.R + 63) / 64, 64, 0, st>>>(G.partial.as<double>(), G.nblk_last, G.R,
@@ -1084,21 +1145,52 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
     }
     return MMX_OK;
   };
+  // half spectrum of a state, with the arithmetic of the row kernel where
+  // that kernel will run, so that a run split over several calls equals one
+  // call bit for bit
+  auto spectrum_of = [&](Group& G, const T* src) -> mmx_status {
+    FArgs<T> fa = field_args<T>(ctx, G, ctx->terms);
+    fa.m = src;
+    bool done_fwd = false;
+    {
+      ProfScope ps(ctx->prof, "k_xfwd", s);
+      done_fwd = launch_rows_reg<T>(ctx, G, fa, -1);
+      if (done_fwd) HIP_TRY(hipGetLastError());
+    }
+    if (!done_fwd) MMX_TRY(launch_xfwd<T>(ctx, G, src, Combine{}, true, nullptr, dt, nullptr));
+    return MMX_OK;
+  };
+  if (refill) {
+    // every replica starts trial 0 at step step0; the initial states' half
+    // spectra are kept for the resets
+    for (int gi : staged) {
+      Group& G = *ctx->groups[gi];
+      const int roff = roffs[gi];
+      HIP_TRY(G.tgen.ensure((size_t)G.R * sizeof(int)));
+      HIP_TRY(G.tflag.ensure((size_t)G.R * sizeof(int)));
+      HIP_TRY(G.tstart.ensure((size_t)G.R * sizeof(unsigned long long)));
+      const unsigned nb = (unsigned)((G.R + 255) / 256);
+      k_fill_i32<<<nb, 256, 0, s>>>(G.tgen.as<int>(), G.R, 0);
+      k_fill_i32<<<nb, 256, 0, s>>>(G.tflag.as<int>(), G.R, 0);
+      k_fill_i32<<<nb, 256, 0, s>>>(rf->counts + roff, G.R, 0);
+      k_fill_u64<<<nb, 256, 0, s>>>(G.tstart.as<unsigned long long>(), G.R,
+                                    (unsigned long long)step0);
+      const size_t nt = (size_t)G.R * rf->cap;
+      if (nt)
+        k_fill_f64<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(
+            rf->times + (size_t)roff * rf->cap, nt, -1.0);
+      HIP_TRY(hipGetLastError());
+      if (n_steps > 0 && (ctx->terms & MMX_DEMAG)) {
+        HIP_TRY(G.S_init.ensure(G.S.bytes));
+        MMX_TRY(spectrum_of(G, reinterpret_cast<const T*>(rf->m_init) + G.off));
+        HIP_TRY(hipMemcpyAsync(G.S_init.p, G.S.p, G.S.bytes, hipMemcpyDeviceToDevice, s));
+      }
+    }
+  }
   if (n_steps > 0 && (ctx->terms & MMX_DEMAG)) {
     for (int gi : staged) {  // half spectrum of the initial state
       Group& G = *ctx->groups[gi];
-      // with the arithmetic of the row kernel where that kernel will run, so
-      // that a run split over several calls equals one call bit for bit
-      FArgs<T> fa = field_args<T>(ctx, G, ctx->terms);
-      fa.m = mb + G.off;
-      bool done_fwd = false;
-      {
-        ProfScope ps(ctx->prof, "k_xfwd", s);
-        done_fwd = launch_rows_reg<T>(ctx, G, fa, -1);
-        if (done_fwd) HIP_TRY(hipGetLastError());
-      }
-      if (!done_fwd)
-        MMX_TRY(launch_xfwd<T>(ctx, G, mb + G.off, Combine{}, true, nullptr, dt, nullptr));
+      MMX_TRY(spectrum_of(G, mb + G.off));
     }
   }
   const int64_t chunk = 32;  // steps per captured graph
@@ -1510,6 +1602,32 @@ mmx_status mmx_heun(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t 
   if (!m) return fail(MMX_EINVAL, "null array");
   return ctx->prec == MMX_F64 ? heun_impl<double>(ctx, m, dt, n_steps, step0, t_switch)
                               : heun_impl<float>(ctx, m, dt, n_steps, step0, t_switch);
+}
+
+mmx_status mmx_depondt(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
+                       void* t_switch) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  if (!m) return fail(MMX_EINVAL, "null array");
+  return ctx->prec == MMX_F64 ? heun_impl<double>(ctx, m, dt, n_steps, step0, t_switch, 1)
+                              : heun_impl<float>(ctx, m, dt, n_steps, step0, t_switch, 1);
+}
+
+mmx_status mmx_depondt_refill(mmx_ctx* ctx, void* m, const void* m_init, double dt,
+                              int64_t n_steps, uint64_t step0, void* times, int32_t cap,
+                              void* counts) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  if (!m || !m_init || !counts) return fail(MMX_EINVAL, "null array");
+  if (cap < 0) return fail(MMX_EINVAL, "cap must be >= 0");
+  if (cap > 0 && !times) return fail(MMX_EINVAL, "null times array");
+  RefillArgs rf;
+  rf.m_init = m_init;
+  rf.times = reinterpret_cast<double*>(times);
+  rf.counts = reinterpret_cast<int*>(counts);
+  rf.cap = cap;
+  return ctx->prec == MMX_F64 ? heun_impl<double>(ctx, m, dt, n_steps, step0, nullptr, 1, &rf)
+                              : heun_impl<float>(ctx, m, dt, n_steps, step0, nullptr, 1, &rf);
 }
 
 mmx_status mmx_rk45(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, double dt0,

@@ -5,7 +5,8 @@
 // products of counter words 0 and 2 with the published multipliers, mixes
 // their high halves with the other counter words and the round key, and the
 // key is advanced by the published Weyl constants between rounds.
-// Key = replica seed (low, high); counter = (cell, step low, step high, 0).
+// Key = replica seed (low, high); counter = (cell, step low, step high, g),
+// g = trial generation (0 except for refilled retire/refill trials).
 // Uniforms (x + 1/2) 2^-32, Box-Muller on (u0, u1) and (u2, u3); the first
 // three normals are the x, y, z components.
 #pragma once
@@ -70,8 +71,9 @@ struct BoxMuller<float> {
 };
 
 template <typename T>
-__device__ inline void thermal_eta(uint64_t seed, uint32_t cell, uint64_t step, T out[3]) {
-  uint32_t c[4] = {cell, (uint32_t)(step & 0xFFFFFFFFull), (uint32_t)(step >> 32), 0u};
+__device__ inline void thermal_eta(uint64_t seed, uint32_t cell, uint64_t step, T out[3],
+                                   uint32_t gen = 0u) {
+  uint32_t c[4] = {cell, (uint32_t)(step & 0xFFFFFFFFull), (uint32_t)(step >> 32), gen};
   philox4x32_10(c, (uint32_t)(seed & 0xFFFFFFFFull), (uint32_t)(seed >> 32));
   BoxMuller<T>::eta(c, out);
 }

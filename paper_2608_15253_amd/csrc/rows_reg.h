@@ -1,6 +1,7 @@
-// Row pass of the stochastic Heun stages with the rows' transforms in
-// registers (device code): inverse x transform of the demag spectrum, local
-// fields, torque, predictor or corrector update, and the forward x transform
+// Row pass of the stochastic Heun stages (ROT: of the rotation scheme) with
+// the rows' transforms in registers (device code): inverse x transform of the
+// demag spectrum, local fields, torque, predictor or corrector update, and the
+// forward x transform
 // of the state just written, for films whose half-length x transform has
 // hx = N1 * N2 points (4 x 4, 4 x 8, 8 x 8, 8 x 16, 16 x 16).
 //
@@ -139,7 +140,7 @@ __global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
   rows_store_spectrum<T, N1, N2>(v, E, q, live, Srow, cstride, wpl);
 }
 
-template <typename T, int N1, int N2, int MODE>
+template <typename T, int N1, int N2, int MODE, bool ROT>
 __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   static_assert(MODE == FM_HEUN1 || MODE == FM_HEUN2, "Heun stages only");
   static_assert(N2 % N1 == 0 && 64 % N1 == 0, "row split");
@@ -228,31 +229,29 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
       for (int c = 0; c < 3; ++c) H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + Hs[c * 2 * hx + x];
       if (sigma != T(0)) {
         T eta[3];
-        thermal_eta<T>(a.seeds[r], (uint32_t)cell, step_now, eta);
+        uint32_t gen;
+        const uint64_t sn = noise_step(a, r, step_now, gen);
+        thermal_eta<T>(a.seeds[r], (uint32_t)cell, sn, eta, gen);
 #pragma unroll
         for (int c = 0; c < 3; ++c) H[c] += sigma * eta[c];
       }
       T kv[3];
       llg_torque(mc, H, a.gpm, a.alpha, kv);
       if (MODE == FM_HEUN1) {
+        T k1v[3];
+        heun_predict(a, ROT, mc, H, kv, dt, k1v, mn_out);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          mn_out[c] = mc[c] + dt * kv[c];
-          k1_r[c * N + cell] = kv[c];
+          k1_r[c * N + cell] = k1v[c];
           mout_r[c * N + cell] = mn_out[c];
         }
       } else {
-        T mo[3], k1v[3], mn[3];
+        T mo[3], k1v[3];
         ld3(a.m0 + rb, N, cell, mo);
         ld3(k1_r, N, cell, k1v);
+        heun_correct(a, ROT, mc, H, kv, mo, k1v, dt, mn_out);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) mn[c] = mo[c] + T(0.5) * dt * (k1v[c] + kv[c]);
-        const T inv = T(1) / sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          mn_out[c] = mn[c] * inv;
-          mout_r[c * N + cell] = mn_out[c];
-        }
+        for (int c = 0; c < 3; ++c) mout_r[c * N + cell] = mn_out[c];
         acc += (double)mn_out[2];
       }
     }

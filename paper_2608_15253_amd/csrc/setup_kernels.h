@@ -157,6 +157,61 @@ __global__ void k_switch_reduce(const double* partial, int nblk, int R, int N, d
   if (tsw[r] < 0 && s / N < 0) tsw[r] = t;
 }
 
+// Retire/refill bookkeeping after a step (one thread per replica): a replica
+// whose mean m_z is negative ends its trial, records the trial's duration
+// (while fewer than cap are recorded), starts trial g + 1 at the next step and
+// is flagged for a reset to its initial state.
+__global__ void k_refill_check(const double* partial, int nblk, int R, int N, int* tgen,
+                               unsigned long long* tstart, int* flag, int* counts, double* times,
+                               int cap, unsigned long long step_host,
+                               const unsigned long long* stepdev, double dt) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += partial[(size_t)r * nblk + b];
+  const unsigned long long step = stepdev ? *stepdev : step_host;
+  int f = 0;
+  if (s / N < 0) {
+    const int c = counts[r];
+    if (c < cap) times[(size_t)r * cap + c] = (double)(step + 1 - tstart[r]) * dt;
+    counts[r] = c + 1;
+    tgen[r] += 1;
+    tstart[r] = step + 1;
+    f = 1;
+  }
+  flag[r] = f;
+}
+
+// Reset of flagged replicas: state (n per replica) and, if present, its half
+// spectrum (ns per replica) from the saved initial copies.  Grid (x, R).
+template <typename T>
+__global__ void k_refill_copy(const int* flag, T* m, const T* m_init, size_t n, cpx<T>* S,
+                              const cpx<T>* S_init, size_t ns) {
+  const int r = blockIdx.y;
+  if (!flag[r]) return;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    m[(size_t)r * n + i] = m_init[(size_t)r * n + i];
+  if (S)
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < ns; i += stride)
+      S[(size_t)r * ns + i] = S_init[(size_t)r * ns + i];
+}
+
+__global__ void k_fill_i32(int* p, size_t n, int v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ void k_fill_f64(double* p, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // step counter of captured graphs: set before a replay, advanced inside it
 __global__ void k_set_u64(unsigned long long* p, unsigned long long v) { *p = v; }
 __global__ void k_inc_u64(unsigned long long* p, unsigned long long d) { *p += d; }
