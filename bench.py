@@ -320,6 +320,54 @@ def bench_skyrmion512(args):
             "rel_dE_total": abs(e32[5] - e64[5]) / abs(e64[5]), "dQ": abs(q32 - q64)}
 
 
+def bench_depondt(args):
+    """The switching film (1024 replicas of 64x64x1, T = 300 K, B_z = -0.15 T)
+    advanced by the norm-exact rotation scheme, plain and with retire/refill
+    trials: cell-steps/s of both, per-kernel times, and the norm drift."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import replica_seeds, uniform
+    R, dt, cap = args.replicas, 1e-14, 4
+    N = 64 * 64
+    seeds = replica_seeds(3, R)
+    ctx = setup(R, mmx.MMX_F32, seeds)
+    m0 = uniform((64, 64, 1), replicas=R)
+    m = torch.tensor(m0, dtype=torch.float32, device="cuda:0").contiguous()
+    m_init = m.clone()
+    mmx.mmx_depondt(ctx, m, dt, args.warmup, 0, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mmx.mmx_depondt(ctx, m, dt, args.steps, args.warmup, None)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    drift = float((m.view(R, 3, N).norm(dim=1) - 1).abs().max())
+    mmx.mmx_profile_enable(ctx, 1)
+    mmx.mmx_depondt(ctx, m, dt, args.prof_steps, args.warmup + args.steps, None)
+    prof = mmx.mmx_profile_get(ctx)
+    mmx.mmx_profile_enable(ctx, 0)
+    kernels = {k: {"avg_us": v[0] / v[1] * 1e3, "launches": v[1]} for k, v in prof.items()}
+    times = torch.empty(R * cap, dtype=torch.float64, device="cuda:0")
+    counts = torch.zeros(R, dtype=torch.int32, device="cuda:0")
+    mr = m_init.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mmx.mmx_depondt_refill(ctx, mr, m_init, dt, args.steps, times, cap, counts)
+    torch.cuda.synchronize()
+    el_r = time.perf_counter() - t0
+    finished = int(counts.sum())
+    mmx.mmx_destroy(ctx)
+    return {"metric": "LLG cell-steps/s, rotation (Depondt-Mertens) scheme, batched replicas",
+            "value": R * N * args.steps / el, "unit": "cell-steps/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
+            "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "thermal_switching_64x64x1_R1024_depondt", "replicas": R,
+                       "dt_s": dt, "T_K": 300},
+            "norm_drift": drift, "kernels": kernels,
+            "refill": {"value": R * N * args.steps / el_r, "unit": "cell-steps/s",
+                       "ms_per_step": el_r / args.steps * 1e3, "finished_trials": finished,
+                       "cap": cap}}
+
+
 def setup(R, prec, seeds, n=(64, 64, 1)):
     import torch
     import paper_2608_15253_amd as mmx
@@ -380,7 +428,7 @@ def main():
                     help="write the HBM traffic table from two rocprofv3 --pmc runs")
     ap.add_argument("--traffic-cmd", default="", help="command line recorded in the summary")
     ap.add_argument("--workload", default="switching",
-                    choices=["switching", "uneven", "closure", "skyrmion512"],
+                    choices=["switching", "uneven", "closure", "skyrmion512", "depondt"],
                     help="switching: the benchmark line; the others measure the other "
                          "workload configurations (one JSON line each)")
     ap.add_argument("--t-end", type=float, default=None,
@@ -397,7 +445,8 @@ def main():
         return
     if args.workload != "switching":
         print(json.dumps({"uneven": bench_uneven, "closure": bench_closure,
-                          "skyrmion512": bench_skyrmion512}[args.workload](args)))
+                          "skyrmion512": bench_skyrmion512,
+                          "depondt": bench_depondt}[args.workload](args)))
         return
     import torch
     import paper_2608_15253_amd as mmx

@@ -1124,8 +1124,9 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
         HIP_TRY(hipGetLastError());
         const size_t n = (size_t)3 * G.N;
         const size_t ns = (ctx->terms & MMX_DEMAG) ? (size_t)3 * G.nz * G.Sy * G.Kx : 0;
-        const size_t big = std::max(n, ns);
-        const dim3 grid((unsigned)std::min<size_t>((big + 255) / 256, 64), (unsigned)G.R);
+        // one workgroup per replica: resets are rare, so the launch is kept
+        // small rather than wide
+        const dim3 grid(1, (unsigned)G.R);
         k_refill_copy<T><<<grid, 256, 0, st>>>(
             G.tflag.as<int>(), mg, reinterpret_cast<const T*>(rf->m_init) + G.off, n,
             ns ? G.S.as<cpx<T>>() : nullptr, ns ? G.S_init.as<cpx<T>>() : nullptr, ns);
