@@ -14,8 +14,9 @@ FFT and linear algebra serve as library primitives.
 Pins (``tests/test_oracle_*.py``, run with ``-m "not gpu"``) tie each part to
 something other than itself: closed forms (cube self-term 1/3, trace identities,
 point-dipole far field, whole-body identity, exact spin-wave dispersion, damped
-macrospin, Kittel, Langevin, exact precession of the rotation scheme), brute force (direct O(N^2) convolution, 50-digit
-mpmath Newell values) and invariants (|m| = 1, m . dm/dt = 0, energy decay).
+macrospin, Kittel, Langevin, exact precession of the rotation scheme,
+spin-transfer antidamping and precession of a free macrospin, J_c0), brute force (direct O(N^2) convolution, 50-digit
+mpmath Newell values, a linear solve of the Gilbert-form spin-transfer torque) and invariants (|m| = 1, m . dm/dt = 0, energy decay).
 The Philox generator is pinned by the known-answer vectors published with it
 (Salmon et al. 2011).  Parity unpinned: the
 interfacial-DMI edge ghosts against another code (closed forms pin the bulk

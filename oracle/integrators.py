@@ -24,7 +24,7 @@ from fractions import Fraction as F
 import numpy as np
 
 from . import fields as _fields
-from .llg import llg_rhs, normalise
+from .llg import llg_rhs, normalise, stt_torque
 from . import observables as _obs
 
 # Dormand-Prince 5(4) tableau (Dormand & Prince 1980).
@@ -48,7 +48,11 @@ DT_MIN = 1e-20
 
 
 def rhs(m, grid, mat, H_th=None):
-    return llg_rhs(m, _fields.effective_field(m, grid, mat, H_th), mat.alpha)
+    """LLG right-hand side at m, with the spin-transfer torque when set."""
+    k = llg_rhs(m, _fields.effective_field(m, grid, mat, H_th), mat.alpha)
+    if mat.stt:
+        k = k + stt_torque(m, mat, grid.n[2] * grid.cell[2])
+    return k
 
 
 # ----------------------------------------------------------------------------

@@ -49,3 +49,16 @@ class Material:
     B: tuple = (0.0, 0.0, 0.0)  # applied field, tesla
     T: float = 0.0           # kelvin
     demag: bool = True
+    # Slonczewski spin-transfer torque: current density (A/m^2; a scalar or
+    # one value per replica of a batch), fixed-layer direction, polarisation,
+    # asymmetry Lambda and secondary (field-like) coefficient eps'
+    stt_J: object = 0.0
+    stt_p: tuple = (0.0, 0.0, 1.0)
+    stt_P: float = 0.0
+    stt_lambda: float = 1.0
+    stt_eps2: float = 0.0
+
+    @property
+    def stt(self) -> bool:
+        import numpy as np
+        return self.stt_P != 0.0 and bool(np.any(np.asarray(self.stt_J) != 0.0))

@@ -16,6 +16,8 @@ keeps |m| = 1 to round-off) without writing it out.  Readings:
   No normalisation: a rotation preserves the norm.
 * The Brown field is drawn once per step and used in both evaluations
   (Stratonovich, as for Heun).
+* A spin-transfer torque tau (perpendicular to m) enters as m x tau added to
+  Omega, since (m x tau) x m = tau.
 * Rodrigues' formula for the rotation of v about the vector w by |w|:
   v cos|w| + (w x v) sin|w| / |w| + w (w . v) (1 - cos|w|) / |w|^2.
 * Retire/refill (reading): slot r runs trials g = 0, 1, ...; trial g starts
@@ -32,6 +34,7 @@ import numpy as np
 
 from . import fields as _fields
 from .constants import GAMMA0, MU0
+from .llg import stt_torque
 
 
 def omega(m, H, alpha):
@@ -50,15 +53,22 @@ def rotate(v, w):
     return np.cos(th) * v + s1 * np.cross(w, v, axis=-4) + s2 * wv * w
 
 
+def _omega_total(m, grid, mat, H_th):
+    """Omega of the LLG equation plus, with a spin-transfer torque tau (which
+    is perpendicular to m), m x tau: (m x tau) x m = tau."""
+    o = omega(m, _fields.effective_field(m, grid, mat, H_th), mat.alpha)
+    if mat.stt:
+        o = o + np.cross(m, stt_torque(m, mat, grid.n[2] * grid.cell[2]), axis=-4)
+    return o
+
+
 def depondt_step(m, grid, mat, dt, seed=0, step=0, gen=0):
     """One rotation step of one replica (3, nz, ny, nx) or of a batch (R, 3, nz,
     ny, nx) with per-replica seeds."""
     H_th = _fields.thermal_field(grid, mat, dt, seed, step, gen) if mat.T > 0 else None
-    H1 = _fields.effective_field(m, grid, mat, H_th)
-    o1 = omega(m, H1, mat.alpha)
+    o1 = _omega_total(m, grid, mat, H_th)
     mp = rotate(m, dt * o1)
-    H2 = _fields.effective_field(mp, grid, mat, H_th)
-    o2 = omega(mp, H2, mat.alpha)
+    o2 = _omega_total(mp, grid, mat, H_th)
     return rotate(m, 0.5 * dt * (o1 + o2))
 
 
