@@ -159,7 +159,7 @@ def traffic_summary(fetch_csv, write_csv, cmd, R):
         "|---|---|---|---|---|---|---|",
     ]
     # kernel names as the profiler reports them -> the names of the HIP-event
-    # profile (the Heun stages run as k_rows_reg<float, N1, N2, 2 | 3, false> where
+    # profile (the Heun stages run as k_rows_reg<float, N1, N2, 2 | 3, false, false> where
     # the register row kernel applies, else as k_fields<float, 2 | 3>)
     def find_re(table, pattern):
         for k, v in table.items():
@@ -167,8 +167,8 @@ def traffic_summary(fetch_csv, write_csv, cmd, R):
                 return v
         return None
     patterns = [("k_xfwd", r"k_xfwd<|k_rows_fwd<"), ("k_yconv", r"k_yconv"),
-                ("k_fields_heun1", r"k_rows_reg<float, \d+, \d+, 2(, false)?>|k_fields<float, 2>"),
-                ("k_fields_heun2", r"k_rows_reg<float, \d+, \d+, 3(, false)?>|k_fields<float, 3>")]
+                ("k_fields_heun1", r"k_rows_reg<float, \d+, \d+, 2(, false)*>|k_fields<float, 2>"),
+                ("k_fields_heun2", r"k_rows_reg<float, \d+, \d+, 3(, false)*>|k_fields<float, 3>")]
     for label, pat in patterns:
         f = find_re(fetch, pat)
         w = find_re(write, pat)

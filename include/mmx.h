@@ -60,7 +60,8 @@ enum {
   MMX_ZEEMAN = 8,          /* applied field                                    */
   MMX_DEMAG = 16,          /* Newell-tensor FFT demagnetisation                */
   MMX_THERMAL = 32,        /* Brown thermal field (Philox4x32-10 noise)        */
-  MMX_ALL_TERMS = 63
+  MMX_STT = 64,            /* Slonczewski spin-transfer torque (mmx_set_stt)   */
+  MMX_ALL_TERMS = 127
 };
 
 /* One geometry advanced for `replicas` independent replicas. */
@@ -128,6 +129,25 @@ mmx_status mmx_set_thermal(mmx_ctx* ctx, int32_t group, const double* T_per_repl
  * (Px/2+1)(Py/2+1)(Pz/2+1) block per component and rounded to the context
  * precision.  Requires the material to be set.  Synchronous. */
 mmx_status mmx_build_demag(mmx_ctx* ctx);
+
+/* Slonczewski spin-transfer torque of group `group` (Methods, "Physics and
+ * discretization": spin torques added per integrator stage; Results, the
+ * replica-batched STT switching sweep with a current density per replica).
+ * J: host double[R] current densities (A/m^2), copied; p: fixed-layer
+ * direction (normalised here); P: polarisation; Lambda > 0: asymmetry;
+ * eps_prime: field-like coefficient.  With MMX_STT in the term mask every
+ * torque evaluation (mmx_torque, all integrators) adds, in the
+ * Landau-Lifshitz form of the LLG equation,
+ *   gamma' mu0 b_J [(eps - alpha eps') m x (m x p) - (eps' + alpha eps) m x p],
+ *   b_J = hbar J / (mu0 e Ms d), eps = P Lambda^2 / ((Lambda^2 + 1) +
+ *   (Lambda^2 - 1) m.p), d = the group's thickness n_z cell_z,
+ * i.e. the Gilbert-form torque gamma0 mu0 b_J [eps m x (m x p) - eps' m x p]:
+ * J > 0 drives m away from p.  It does not enter mmx_field or mmx_energy.
+ * Runs on the staged path (mmx_heun returns MMX_EUNSUP under
+ * MMX_PATH_FUSED).  Synchronous.  MMX_EINVAL for null pointers, p = 0,
+ * Lambda <= 0 or non-finite values. */
+mmx_status mmx_set_stt(mmx_ctx* ctx, int32_t group, const double* J, const double p[3],
+                       double P, double Lambda, double eps_prime);
 
 /* Effective field H (A/m, device, layout D1) at state m (device, D1) for
  * all groups, with the enabled terms; the thermal term uses `step` and `dt`.

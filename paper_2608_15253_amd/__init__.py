@@ -30,7 +30,8 @@ STATUS = {0: "MMX_OK", -1: "MMX_EINVAL", -2: "MMX_ESHAPE", -3: "MMX_EHIP",
           -4: "MMX_ESTATE", -5: "MMX_EUNSUP", -6: "MMX_ENONFINITE", -8: "MMX_EDTMIN"}
 MMX_EXCH, MMX_DMI_INTERFACIAL, MMX_ANIS_UNIAXIAL = 1, 2, 4
 MMX_ZEEMAN, MMX_DEMAG, MMX_THERMAL = 8, 16, 32
-MMX_ALL_TERMS = 63
+MMX_STT = 64
+MMX_ALL_TERMS = 127
 DEFAULT_TERMS = MMX_EXCH | MMX_DMI_INTERFACIAL | MMX_ANIS_UNIAXIAL | MMX_ZEEMAN | MMX_DEMAG
 
 
@@ -83,6 +84,8 @@ _SIGS = {
     "mmx_torque": [_P, _P, _P, ctypes.c_uint64, ctypes.c_double],
     "mmx_heun": [_P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P],
     "mmx_depondt": [_P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P],
+    "mmx_set_stt": [_P, ctypes.c_int32, _P, _P, ctypes.c_double, ctypes.c_double,
+                    ctypes.c_double],
     "mmx_depondt_refill": [_P, _P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P,
                            ctypes.c_int32, _P],
     "mmx_rk45": [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -208,6 +211,14 @@ def mmx_torque(ctx, m, dmdt, step=0, dt=0.0) -> None:
 def mmx_heun(ctx, m, dt, n_steps, step0=0, t_switch=None) -> None:
     _check("mmx_heun", _lib.mmx_heun(ctx, _ptr(m), float(dt), int(n_steps), int(step0),
                                      _ptr(t_switch)))
+
+
+def mmx_set_stt(ctx, group, J, p=(0.0, 0.0, 1.0), P=0.0, Lambda=1.0, eps_prime=0.0) -> None:
+    Ja = np.ascontiguousarray(np.asarray(J, dtype=np.float64).ravel())
+    pa = (ctypes.c_double * 3)(*[float(x) for x in p])
+    _check("mmx_set_stt", _lib.mmx_set_stt(ctx, int(group),
+                                           Ja.ctypes.data_as(ctypes.c_void_p), pa, float(P),
+                                           float(Lambda), float(eps_prime)))
 
 
 def mmx_depondt(ctx, m, dt, n_steps, step0=0, t_switch=None) -> None:

@@ -11,6 +11,8 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr double kGamma0 = 1.7595e11;
 constexpr double kMu0 = 4.0e-7 * kPi;
 constexpr double kKB = 1.380649e-23;
+constexpr double kHbar = 6.62607015e-34 / (2.0 * kPi);  // exact SI h / 2 pi
+constexpr double kQe = 1.602176634e-19;                 // exact SI elementary charge
 
 constexpr int kMaxPass = 16;
 constexpr int kTensorStride = 8;  // reals per frequency of the tensor spectrum

@@ -25,7 +25,7 @@
 namespace mmx {
 
 enum : unsigned {
-  T_EXCH = 1, T_DMI = 2, T_ANIS = 4, T_ZEEMAN = 8, T_DEMAG = 16, T_THERMAL = 32
+  T_EXCH = 1, T_DMI = 2, T_ANIS = 4, T_ZEEMAN = 8, T_DEMAG = 16, T_THERMAL = 32, T_STT = 64
 };
 
 enum FieldMode { FM_FIELD = 0, FM_TORQUE, FM_HEUN1, FM_HEUN2, FM_RKK, FM_RK7, FM_ENERGY };
@@ -390,6 +390,11 @@ struct FArgs {
   int rot;            // Heun epilogues take the rotation (Depondt-Mertens) update
   const int* tgen;    // retire/refill: trial generation of each replica (noise word 3)
   const unsigned long long* tstart;  // and the first step of its running trial
+  // Slonczewski spin-transfer torque: b_J = stt_c J[r] (A/m), fixed-layer unit
+  // vector, polarisation, Lambda^2 and the field-like coefficient eps'
+  const double* Jrep;
+  double stt_c;
+  T sttp[3], stt_P, stt_L2, stt_e2;
 };
 
 template <typename T>
@@ -464,6 +469,45 @@ __device__ inline void llg_torque(const T mc[3], const T H[3], T gpm, T alpha, T
   k[2] = -gpm * (cz + alpha * dz);
 }
 
+// Slonczewski spin-transfer torque in the Landau-Lifshitz form of the LLG
+// equation (Methods, "Physics and discretization": spin torques are added per
+// integrator stage): the Gilbert-form torque gamma0 mu0 b_J [eps m x (m x p)
+// - eps' m x p] becomes
+//   tau = gamma' mu0 b_J [(eps - alpha eps') m x (m x p) - (eps' + alpha eps) m x p],
+//   eps = P Lambda^2 / ((Lambda^2 + 1) + (Lambda^2 - 1) m.p).
+template <typename T>
+__device__ inline void stt_tau(const FArgs<T>& a, T bJ, const T m[3], T tau[3]) {
+  const T* p = a.sttp;
+  const T mp = m[0] * p[0] + m[1] * p[1] + m[2] * p[2];
+  const T eps = a.stt_P * a.stt_L2 / ((a.stt_L2 + T(1)) + (a.stt_L2 - T(1)) * mp);
+  const T x[3] = {m[1] * p[2] - m[2] * p[1], m[2] * p[0] - m[0] * p[2], m[0] * p[1] - m[1] * p[0]};
+  const T xx[3] = {m[1] * x[2] - m[2] * x[1], m[2] * x[0] - m[0] * x[2], m[0] * x[1] - m[1] * x[0]};
+  const T c1 = a.gpm * bJ * (eps - a.alpha * a.stt_e2);
+  const T c2 = a.gpm * bJ * (a.stt_e2 + a.alpha * eps);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) tau[c] = c1 * xx[c] - c2 * x[c];
+}
+
+// b_J of replica r (0 without the spin-transfer term)
+template <typename T>
+__device__ inline T stt_bj(const FArgs<T>& a, int r) {
+  return (a.terms & T_STT) ? (T)(a.stt_c * a.Jrep[r]) : T(0);
+}
+
+// Torque of the cell with the spin-transfer term added; tau receives that
+// term alone (zero without it) for the rotation scheme.
+template <typename T>
+__device__ inline void cell_torque(const FArgs<T>& a, T bJ, const T mc[3], const T H[3], T k[3],
+                                   T tau[3]) {
+  llg_torque(mc, H, a.gpm, a.alpha, k);
+  tau[0] = tau[1] = tau[2] = T(0);
+  if (bJ != T(0)) {
+    stt_tau(a, bJ, mc, tau);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) k[c] += tau[c];
+  }
+}
+
 // The LLG equation as a rotation, dm/dt = Omega x m with Omega =
 // gamma' mu0 (H + alpha m x H) (Results, replica-batched engine: norm-exact
 // Depondt-Mertens rotation scheme).
@@ -501,16 +545,26 @@ __device__ inline void rodrigues(const T v[3], const T w[3], T out[3]) {
   out[2] = c * v[2] + s1 * (w[0] * v[1] - w[1] * v[0]) + s2 * wv * w[2];
 }
 
+// o += m x t
+template <typename T>
+__device__ inline void add_cross(const T m[3], const T t[3], T o[3]) {
+  o[0] += m[1] * t[2] - m[2] * t[1];
+  o[1] += m[2] * t[0] - m[0] * t[2];
+  o[2] += m[0] * t[1] - m[1] * t[0];
+}
+
 // Heun-stage epilogues shared by the field kernels.  Predictor: k1 <- slope,
 // m~ = m + dt k (Heun) or k1 <- Omega, m~ = rotation of m by dt Omega.
 // Corrector from the saved state mo and k1: normalised m + dt/2 (k1 + k)
 // (Heun) or the rotation of mo by dt/2 (Omega_1 + Omega_2), not normalised.
+// tau: spin-transfer torque at (mc), entering Omega as mc x tau
 template <typename T>
 __device__ inline void heun_predict(const FArgs<T>& a, bool rot, const T mc[3], const T H[3],
-                                    const T k[3], T dt, T k1v[3], T mn[3]) {
+                                    const T k[3], const T tau[3], T dt, T k1v[3], T mn[3]) {
   if (rot) {
     T w[3];
     llg_omega(mc, H, a.gpm, a.alpha, k1v);
+    add_cross(mc, tau, k1v);
 #pragma unroll
     for (int c = 0; c < 3; ++c) w[c] = dt * k1v[c];
     rodrigues(mc, w, mn);
@@ -525,10 +579,12 @@ __device__ inline void heun_predict(const FArgs<T>& a, bool rot, const T mc[3], 
 
 template <typename T>
 __device__ inline void heun_correct(const FArgs<T>& a, bool rot, const T mc[3], const T H[3],
-                                    const T k[3], const T mo[3], const T k1v[3], T dt, T mn[3]) {
+                                    const T k[3], const T tau[3], const T mo[3], const T k1v[3],
+                                    T dt, T mn[3]) {
   if (rot) {
     T o[3], w[3];
     llg_omega(mc, H, a.gpm, a.alpha, o);
+    add_cross(mc, tau, o);
 #pragma unroll
     for (int c = 0; c < 3; ++c) w[c] = T(0.5) * dt * (k1v[c] + o[c]);
     rodrigues(mo, w, mn);
@@ -627,6 +683,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
   T* mout_r = a.mout ? a.mout + rb : nullptr;
   T* k1_r = a.k1 ? a.k1 + rb : nullptr;
   const uint64_t step_now = a.stepdev ? *a.stepdev : a.step;
+  const T bJ = stt_bj(a, r);
   double acc[5] = {0, 0, 0, 0, 0};
   for (int t = threadIdx.x; t < ncell_blk; t += blockDim.x) {
     const int l = udiv(t, a.nx), x = t - l * a.nx, y = y0 + l;
@@ -673,14 +730,14 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       for (int c = 0; c < 3; ++c) out_r[c * N + cell] = H[c];
       continue;
     }
-    T k[3];
-    llg_torque(mc, H, a.gpm, a.alpha, k);
+    T k[3], tau[3];
+    cell_torque(a, bJ, mc, H, k, tau);
     if (MODE == FM_TORQUE || MODE == FM_RKK) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) out_r[c * N + cell] = k[c];
     } else if (MODE == FM_HEUN1) {
       T k1v[3], mn[3];
-      heun_predict(a, a.rot != 0, mc, H, k, dt, k1v, mn);
+      heun_predict(a, a.rot != 0, mc, H, k, tau, dt, k1v, mn);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         k1_r[c * N + cell] = k1v[c];
@@ -692,7 +749,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       ld3(a.m0 + rb, N, cell, mo);
       ld3(k1_r, N, cell, k1v);
       T mn[3];
-      heun_correct(a, a.rot != 0, mc, H, k, mo, k1v, dt, mn);
+      heun_correct(a, a.rot != 0, mc, H, k, tau, mo, k1v, dt, mn);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         mout_r[c * N + cell] = mn[c];

@@ -139,6 +139,8 @@ struct Group {
   // device buffers
   DevBuf tw_x, wpost, tw_y, tw_z, Nt, S, ms, m7, k[7], Trep, seeds, partial, E;
   DevBuf tgen, tstart, tflag, S_init;  // retire/refill trials
+  DevBuf Jrep;  // spin-transfer current density per replica (A/m^2)
+  double stt_p[3] = {0, 0, 1}, stt_P = 0, stt_lambda = 1, stt_eps2 = 0;
   int nblk = 1;       // k_fields workgroups per replica
   int nblk_last = 1;  // workgroups per replica of the last field-kernel launch
   int demag_built = 0;
@@ -465,6 +467,17 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   a.plan = G.plan_xi;  // inverse transform: full input
   a.tw = G.tw_x.as<cpx<T>>();
   a.wpost = G.wpost.as<cpx<T>>();
+  if ((t & T_STT) && G.Jrep.p && G.stt_P != 0) {
+    const double d = G.g.cell[2] * G.nz;  // free-layer thickness
+    a.Jrep = G.Jrep.as<double>();
+    a.stt_c = kHbar / (kMu0 * kQe * G.mat.Ms * d);
+    for (int c = 0; c < 3; ++c) a.sttp[c] = (T)G.stt_p[c];
+    a.stt_P = (T)G.stt_P;
+    a.stt_L2 = (T)(G.stt_lambda * G.stt_lambda);
+    a.stt_e2 = (T)G.stt_eps2;
+  } else {
+    a.terms &= ~(unsigned)T_STT;
+  }
   a.rot = ctx->rot;
   if (ctx->refill) {
     a.tgen = G.tgen.as<int>();
@@ -486,7 +499,9 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
     if (mode != -1 && !a.fwd) return false;
     if (G.xone || a.hext || a.hd_out) return false;
     hipStream_t s = ctx->stream;
-    auto go = [&](auto k1, auto k2, auto r1, auto r2, auto kf, int rpw) {
+    // variants: [stage][rotation][spin-transfer]
+    using RowKernel = void (*)(FArgs<float>);
+    auto go = [&](const RowKernel (&k)[2][2][2], auto kf, int rpw) {
       const int gx = (G.ny + rpw - 1) / rpw;
       const dim3 grid(gx, G.nz, G.R);
       if (mode == -1) {
@@ -494,19 +509,19 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
         return true;
       }
       G.nblk_last = gx * G.nz;
-      if (mode == FM_HEUN1) {
-        if (a.rot) r1<<<grid, 64, 0, s>>>(a);
-        else k1<<<grid, 64, 0, s>>>(a);
-      } else {
-        if (a.rot) r2<<<grid, 64, 0, s>>>(a);
-        else k2<<<grid, 64, 0, s>>>(a);
-      }
+      const RowKernel kern = k[mode == FM_HEUN1 ? 0 : 1][a.rot ? 1 : 0][(a.terms & T_STT) ? 1 : 0];
+      kern<<<grid, 64, 0, s>>>(a);
       return true;
     };
-#define MMX_ROWS(N1, N2, RPW)                                                                   \
-  go(k_rows_reg<float, N1, N2, FM_HEUN1, false>, k_rows_reg<float, N1, N2, FM_HEUN2, false>, \
-     k_rows_reg<float, N1, N2, FM_HEUN1, true>, k_rows_reg<float, N1, N2, FM_HEUN2, true>,   \
-     k_rows_fwd<float, N1, N2>, RPW)
+#define MMX_ROWS_V(N1, N2, M) \
+  {{k_rows_reg<float, N1, N2, M, false, false>, k_rows_reg<float, N1, N2, M, false, true>}, \
+   {k_rows_reg<float, N1, N2, M, true, false>, k_rows_reg<float, N1, N2, M, true, true>}}
+#define MMX_ROWS(N1, N2, RPW)                                                                 \
+  [&]() {                                                                                   \
+    static const RowKernel k[2][2][2] = {MMX_ROWS_V(N1, N2, FM_HEUN1),                      \
+                                         MMX_ROWS_V(N1, N2, FM_HEUN2)};                     \
+    return go(k, k_rows_fwd<float, N1, N2>, RPW);                                           \
+  }()
     switch (G.hx) {
       case 16: return MMX_ROWS(4, 4, 16);
       case 32: return MMX_ROWS(4, 8, 16);
@@ -516,6 +531,7 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
       default: return false;
     }
 #undef MMX_ROWS
+#undef MMX_ROWS_V
   }
 }
 
@@ -1067,7 +1083,10 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       const FusedTiles ft = fused_tiles<T>(ctx, G);
       if (ctx->path == MMX_PATH_FUSED && !ft.ok)
         return fail(MMX_EUNSUP, "group does not fit the replica-resident path");
-      const bool use_fused = !rot && !refill && ft.ok &&
+      const bool stt = (ctx->terms & MMX_STT) && G.Jrep.p && G.stt_P != 0;
+      if (stt && ctx->path == MMX_PATH_FUSED)
+        return fail(MMX_EUNSUP, "the spin-transfer torque runs on the staged path only");
+      const bool use_fused = !rot && !refill && !stt && ft.ok &&
                              (ctx->path == MMX_PATH_FUSED ||
                               (ctx->path == MMX_PATH_AUTO && G.fused_faster));
       if (use_fused) {
@@ -1566,6 +1585,27 @@ mmx_status mmx_set_thermal(mmx_ctx* ctx, int32_t group, const double* T, const u
   HIP_TRY(hipMemcpyAsync(G.seeds.p, seeds, G.R * sizeof(uint64_t), hipMemcpyHostToDevice,
                          ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return MMX_OK;
+}
+
+mmx_status mmx_set_stt(mmx_ctx* ctx, int32_t group, const double* J, const double p[3],
+                       double P, double Lambda, double eps_prime) {
+  MMX_TRY(check_group_idx(ctx, group));
+  if (!J || !p) return fail(MMX_EINVAL, "J and p must not be null");
+  const double pn = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+  if (!(pn > 0) || !std::isfinite(pn)) return fail(MMX_EINVAL, "p must be a nonzero vector");
+  if (!(Lambda > 0) || !std::isfinite(P) || !std::isfinite(eps_prime))
+    return fail(MMX_EINVAL, "Lambda must be > 0, P and eps' finite");
+  Group& G = *ctx->groups[group];
+  for (int r = 0; r < G.R; ++r)
+    if (!std::isfinite(J[r])) return fail(MMX_EINVAL, "current densities must be finite");
+  HIP_TRY(G.Jrep.ensure((size_t)G.R * sizeof(double)));
+  HIP_TRY(hipMemcpyAsync(G.Jrep.p, J, G.R * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  for (int c = 0; c < 3; ++c) G.stt_p[c] = p[c] / pn;
+  G.stt_P = P;
+  G.stt_lambda = Lambda;
+  G.stt_eps2 = eps_prime;
   return MMX_OK;
 }
 

@@ -1,4 +1,5 @@
-// Row pass of the stochastic Heun stages (ROT: of the rotation scheme) with
+// Row pass of the stochastic Heun stages (ROT: of the rotation scheme; STT:
+// with the spin-transfer torque) with
 // the rows' transforms in registers (device code): inverse x transform of the
 // demag spectrum, local fields, torque, predictor or corrector update, and the
 // forward x transform
@@ -140,7 +141,7 @@ __global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
   rows_store_spectrum<T, N1, N2>(v, E, q, live, Srow, cstride, wpl);
 }
 
-template <typename T, int N1, int N2, int MODE, bool ROT>
+template <typename T, int N1, int N2, int MODE, bool ROT, bool STT>
 __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   static_assert(MODE == FM_HEUN1 || MODE == FM_HEUN2, "Heun stages only");
   static_assert(N2 % N1 == 0 && 64 % N1 == 0, "row split");
@@ -210,6 +211,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
     if (Tr > 0) sigma = (T)sqrt(a.sig2pref * Tr / a.dt_th);
   }
   const uint64_t step_now = a.stepdev ? *a.stepdev : a.step;
+  const T bJ = STT ? stt_bj(a, r) : T(0);
   const T* __restrict__ mr = a.m + rb;
   T* mout_r = a.mout + rb;
   T* k1_r = a.k1 + rb;
@@ -235,11 +237,12 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) H[c] += sigma * eta[c];
       }
-      T kv[3];
-      llg_torque(mc, H, a.gpm, a.alpha, kv);
+      T kv[3], tau[3] = {0, 0, 0};
+      if (STT) cell_torque(a, bJ, mc, H, kv, tau);
+      else llg_torque(mc, H, a.gpm, a.alpha, kv);
       if (MODE == FM_HEUN1) {
         T k1v[3];
-        heun_predict(a, ROT, mc, H, kv, dt, k1v, mn_out);
+        heun_predict(a, ROT, mc, H, kv, tau, dt, k1v, mn_out);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           k1_r[c * N + cell] = k1v[c];
@@ -249,7 +252,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
         T mo[3], k1v[3];
         ld3(a.m0 + rb, N, cell, mo);
         ld3(k1_r, N, cell, k1v);
-        heun_correct(a, ROT, mc, H, kv, mo, k1v, dt, mn_out);
+        heun_correct(a, ROT, mc, H, kv, tau, mo, k1v, dt, mn_out);
 #pragma unroll
         for (int c = 0; c < 3; ++c) mout_r[c * N + cell] = mn_out[c];
         acc += (double)mn_out[2];
