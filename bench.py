@@ -19,6 +19,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import re
 import sys
@@ -368,6 +369,83 @@ def bench_depondt(args):
                        "cap": cap}}
 
 
+def _stt_macrospin_ctx(J, seeds, prec):
+    """Single-cell macrospins (10 nm cube, Ms 1.1e6 A/m, Ku 5e5 J/m^3 along z:
+    K V / kB T = 121 at 300 K, alpha 0.05), Slonczewski torque with p = +z,
+    P = 0.6, Lambda = 1, one current density per replica, T = 300 K."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    R = len(J)
+    ctx = mmx.mmx_create([mmx.make_group((1, 1, 1), (10e-9, 10e-9, 10e-9), replicas=R)], prec)
+    mmx.mmx_set_stream(ctx, torch.cuda.current_stream().cuda_stream)
+    mmx.mmx_set_material(ctx, 0, Ms=1.1e6, A=0.0, alpha=0.05, Ku=5e5, u=(0, 0, 1), D=0.0)
+    mmx.mmx_set_thermal(ctx, 0, [300.0] * R, seeds)
+    mmx.mmx_set_stt(ctx, 0, J, p=(0, 0, 1), P=0.6, Lambda=1.0, eps_prime=0.0)
+    mmx.mmx_set_terms(ctx, mmx.MMX_ANIS_UNIAXIAL | mmx.MMX_THERMAL | mmx.MMX_STT)
+    return ctx
+
+
+def bench_stt(args):
+    """Thermally assisted spin-transfer switching sweep of single-cell
+    macrospins with the rotation scheme: 25 current densities J / J_c0 in
+    [0.5, 1.5] x 400 trials = 10 000 replicas, 20 000 steps of 0.1 ps (2 ns),
+    FP32; replica-steps/s of the batched run and of a per-trial loop over 32
+    single-replica contexts, and the switching probability per current."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import replica_seeds
+    HBAR, MU0, QE = 6.62607015e-34 / (2 * math.pi), 4e-7 * math.pi, 1.602176634e-19
+    npts, per = 25, 400
+    R = npts * per
+    Ms, Ku, alpha, d, P = 1.1e6, 5e5, 0.05, 10e-9, 0.6
+    Hk = 2 * Ku / (MU0 * Ms)
+    Jc0 = alpha * Hk * MU0 * QE * Ms * d / (HBAR * (P / 2))
+    ratios = np.linspace(0.5, 1.5, npts)
+    J = np.repeat(ratios * Jc0, per)
+    seeds = replica_seeds(11, R)
+    dt, steps = 1e-13, args.steps if args.steps != 2000 else 20000
+    ctx = _stt_macrospin_ctx(J, seeds, mmx.MMX_F32)
+    m = torch.zeros((R, 3), dtype=torch.float32, device="cuda:0")
+    m[:, 2] = 1.0
+    tsw = torch.full((R,), -1.0, dtype=torch.float64, device="cuda:0")
+    mmx.mmx_depondt(ctx, m.clone(), dt, 64, 0, None)  # warm-up of the launch paths
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mmx.mmx_depondt(ctx, m, dt, steps, 0, tsw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    psw = (tsw.view(npts, per) > 0).double().mean(dim=1).cpu().numpy()
+    mmx.mmx_destroy(ctx)
+    # per-trial loop: 32 single-replica contexts, one call per step each
+    trials, tsteps = 32, 200
+    tctx = [_stt_macrospin_ctx(J[r:r + 1], seeds[r:r + 1], mmx.MMX_F32) for r in range(trials)]
+    tm = [torch.tensor([[0.0, 0.0, 1.0]], dtype=torch.float32, device="cuda:0")
+          for _ in range(trials)]
+    for r in range(trials):
+        mmx.mmx_depondt(tctx[r], tm[r].clone(), dt, 1, 0, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(tsteps):
+        for r in range(trials):
+            mmx.mmx_depondt(tctx[r], tm[r], dt, 1, k, None)
+    torch.cuda.synchronize()
+    el_t = time.perf_counter() - t0
+    for c in tctx:
+        mmx.mmx_destroy(c)
+    return {"metric": "replica-steps/s, STT switching sweep of thermal macrospins (rotation scheme)",
+            "value": R * steps / el, "unit": "replica-steps/s", "n_gpus": 1, "steps": steps,
+            "warmup": 64, "ms_per_step": el / steps * 1e3, "higher_is_better": True,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "stt_sweep_macrospin_R10000", "replicas": R, "dt_s": dt,
+                       "T_K": 300, "points": npts, "trials_per_point": per, "Jc0_A_m2": Jc0},
+            "seconds": el,
+            "per_trial": {"value": trials * tsteps / el_t, "unit": "replica-steps/s",
+                          "trials": trials, "steps": tsteps},
+            "speedup_vs_per_trial": (R * steps / el) / (trials * tsteps / el_t),
+            "p_switch": {"J_over_Jc0": [round(float(x), 4) for x in ratios],
+                         "P_sw": [round(float(x), 4) for x in psw]}}
+
+
 def setup(R, prec, seeds, n=(64, 64, 1)):
     import torch
     import paper_2608_15253_amd as mmx
@@ -428,7 +506,7 @@ def main():
                     help="write the HBM traffic table from two rocprofv3 --pmc runs")
     ap.add_argument("--traffic-cmd", default="", help="command line recorded in the summary")
     ap.add_argument("--workload", default="switching",
-                    choices=["switching", "uneven", "closure", "skyrmion512", "depondt"],
+                    choices=["switching", "uneven", "closure", "skyrmion512", "depondt", "stt"],
                     help="switching: the benchmark line; the others measure the other "
                          "workload configurations (one JSON line each)")
     ap.add_argument("--t-end", type=float, default=None,
@@ -446,7 +524,7 @@ def main():
     if args.workload != "switching":
         print(json.dumps({"uneven": bench_uneven, "closure": bench_closure,
                           "skyrmion512": bench_skyrmion512,
-                          "depondt": bench_depondt}[args.workload](args)))
+                          "depondt": bench_depondt, "stt": bench_stt}[args.workload](args)))
         return
     import torch
     import paper_2608_15253_amd as mmx

@@ -13,6 +13,7 @@
 #include "../../include/mmx.h"
 #include "common.h"
 #include "fused.h"
+#include "macrospin.h"
 #include "kernels.h"
 #include "setup_kernels.h"
 #include "yconv_reg.h"
@@ -1062,6 +1063,30 @@ struct SchemeScope {
   }
 };
 
+// Single-cell groups without demag: every replica advances all steps in the
+// registers of one thread (k_macrospin), in launches of at most 8192 steps.
+template <typename T>
+mmx_status heun_macrospin(mmx_ctx* ctx, Group& G, T* mg, double dt, int64_t n_steps,
+                          uint64_t step0, double* tsw, int rot) {
+  FArgs<T> a = field_args<T>(ctx, G, ctx->terms);
+  a.dth = dt;
+  a.dt_th = dt;
+  const dim3 grid((unsigned)((G.R + 255) / 256));
+  for (int64_t done = 0; done < n_steps;) {
+    const int n = (int)std::min<int64_t>(n_steps - done, 8192);
+    ProfScope ps(ctx->prof, "k_macrospin", ctx->stream);
+    if (rot)
+      k_macrospin<T, true><<<grid, 256, 0, ctx->stream>>>(a, mg, dt, n, step0 + (uint64_t)done,
+                                                          tsw, G.R);
+    else
+      k_macrospin<T, false><<<grid, 256, 0, ctx->stream>>>(a, mg, dt, n, step0 + (uint64_t)done,
+                                                           tsw, G.R);
+    HIP_TRY(hipGetLastError());
+    done += n;
+  }
+  return MMX_OK;
+}
+
 template <typename T>
 mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
                      void* tsw, int rot = 0, const RefillArgs* rf = nullptr) {
@@ -1080,6 +1105,12 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
     int roff = 0;
     for (size_t gi = 0; gi < ctx->groups.size(); ++gi) {
       Group& G = *ctx->groups[gi];
+      if (G.N == 1 && !(ctx->terms & MMX_DEMAG) && !refill && ctx->path != MMX_PATH_STAGED) {
+        MMX_TRY(heun_macrospin<T>(ctx, G, mb + G.off, dt, n_steps, step0,
+                                  tsw_d ? tsw_d + roff : nullptr, rot));
+        roff += G.R;
+        continue;
+      }
       const FusedTiles ft = fused_tiles<T>(ctx, G);
       if (ctx->path == MMX_PATH_FUSED && !ft.ok)
         return fail(MMX_EUNSUP, "group does not fit the replica-resident path");

@@ -126,3 +126,64 @@ def test_stt_rk45_takes_the_oracle_steps_fp64():
     assert np.abs(got[0] - rep.m).max() <= 1e-12
     own = oit.rk45_run(m0[0], case.grid, mat, 0.0, t_end, tol, 1e-13)
     assert abs(own.accepted - st.accepted) <= 2
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_stt_thermal_macrospins_rotation(prec):
+    """Single-cell macrospins with one current density each (the sweep's
+    replicas), rotation scheme, 200 thermal steps."""
+    import paper_2608_15253_amd as mmx
+    R = 4
+    case = Case((1, 1, 1), (10e-9, 10e-9, 10e-9), R=R, Ms=1.1e6, A=0.0, alpha=0.05, Ku=5e5,
+                T=300.0, seeds=list(replica_seeds(43, R)), terms=("anisotropy", "thermal"))
+    J = (0.0, 1e12, 2.6e12, 4e12)
+    m0 = uniform(case.n, (0.05, 0.0, 1.0), replicas=R)
+    ctx = open_ctx(case, prec)
+    try:
+        _with_stt(ctx, case, J)
+        md = dev(m0, prec)
+        mmx.mmx_depondt(ctx, md, 1e-13, 200, 0)
+        got = host(md)
+    finally:
+        mmx.mmx_destroy(ctx)
+    ref = orot.depondt_run(m0, case.grid, _oracle_material(case, J), 1e-13, 200,
+                           seed=np.array(case.seeds))
+    err = np.abs(got - ref).max()
+    print(f"max |dm| {err:.2e}")
+    assert err <= (1e-12 if prec == 2 else 2e-5), err
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+@pytest.mark.parametrize("scheme", ["heun", "rotation"])
+def test_single_cell_resident_path_equals_staged_path_bitwise(prec, scheme):
+    """Single-cell groups without demag run every step of a replica in one
+    thread; the result equals the staged field-kernel path (400 steps: the
+    staged path replays a captured graph) to round-off (the two kernels may
+    contract multiply-adds differently) and the switching times agree."""
+    import paper_2608_15253_amd as mmx
+    R = 300
+    case = Case((1, 1, 1), (10e-9, 10e-9, 10e-9), R=R, Ms=1.1e6, A=0.0, alpha=0.5, Ku=5e5,
+                B=(0.0, 0.0, -3.0), T=300.0, seeds=list(replica_seeds(44, R)),
+                terms=("anisotropy", "zeeman", "thermal"))
+    J = np.linspace(0.0, 6e12, R)
+    m0 = uniform(case.n, (0.1, 0.0, 1.0), replicas=R)
+    out = {}
+    for path in (mmx.MMX_PATH_AUTO, mmx.MMX_PATH_STAGED):
+        ctx = open_ctx(case, prec)
+        try:
+            _with_stt(ctx, case, J)
+            mmx.mmx_set_path(ctx, path)
+            md = dev(m0, prec)
+            ts = dev(-np.ones(R), 2)
+            step = mmx.mmx_heun if scheme == "heun" else mmx.mmx_depondt
+            step(ctx, md, 1e-13, 400, 3, ts)
+            out[path] = (host(md), host(ts))
+        finally:
+            mmx.mmx_destroy(ctx)
+    a, b = out[mmx.MMX_PATH_AUTO], out[mmx.MMX_PATH_STAGED]
+    err = np.abs(a[0] - b[0]).max()
+    print(f"resident vs staged: max |dm| {err:.2e}")
+    assert err <= (1e-12 if prec == 2 else 1e-5)
+    assert (a[1] > 0).sum() > R // 10  # many replicas switched
+    same = a[1] == b[1]
+    assert same.mean() >= 0.99 and np.abs(a[1] - b[1]).max() <= 1.5e-13
