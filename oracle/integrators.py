@@ -19,6 +19,7 @@ engine").
 from __future__ import annotations
 
 from dataclasses import dataclass, field
+from dataclasses import replace as dataclass_replace
 from fractions import Fraction as F
 
 import numpy as np
@@ -49,7 +50,7 @@ DT_MIN = 1e-20
 
 def rhs(m, grid, mat, H_th=None):
     """LLG right-hand side at m, with the spin-transfer torque when set."""
-    k = llg_rhs(m, _fields.effective_field(m, grid, mat, H_th), mat.alpha)
+    k = llg_rhs(m, _fields.effective_field(m, grid, mat, H_th), mat.alpha, mat.precess)
     if mat.stt:
         k = k + stt_torque(m, mat, grid.n[2] * grid.cell[2])
     return k
@@ -133,6 +134,7 @@ class RKResult:
     m: np.ndarray
     t: float
     dt: float
+    dt_next: float = 0.0  # the controller's last proposal before clipping to t_end
     accepted: int = 0
     rejected: int = 0
     dts: list = field(default_factory=list)
@@ -179,6 +181,7 @@ def rk45_run(m0, grid, mat, t0, t_end, tol, dt0=1e-14, dt_replay=None,
             res.rejected += 1
         # the step that reaches t_end exactly is clipped and marked final
         dt = min(new_dt, DT_MAX)
+        res.dt_next = dt
         final = t + dt >= t_end
         if final:
             dt = t_end - t
@@ -186,6 +189,56 @@ def rk45_run(m0, grid, mat, t0, t_end, tol, dt0=1e-14, dt_replay=None,
             raise FloatingPointError("step size underflow")
     res.m, res.t, res.dt = m, t, dt
     return res
+
+
+# ----------------------------------------------------------------------------
+# Classical fourth-order Runge-Kutta, fixed step (Methods, "Integrators": RK4)
+# ----------------------------------------------------------------------------
+def rk4_run(m0, grid, mat, dt, nsteps):
+    """``nsteps`` classical RK4 steps: k1 = f(m), k2 = f(m + dt/2 k1),
+    k3 = f(m + dt/2 k2), k4 = f(m + dt k3), m <- m + dt/6 (k1 + 2 k2 + 2 k3 +
+    k4), normalised at the end of each step (reading, as for the corrector of
+    Heun and the accepted RK45 state; the stage states are not normalised)."""
+    m = m0.copy()
+    for _ in range(nsteps):
+        k1 = rhs(m, grid, mat)
+        k2 = rhs(m + 0.5 * dt * k1, grid, mat)
+        k3 = rhs(m + 0.5 * dt * k2, grid, mat)
+        k4 = rhs(m + dt * k3, grid, mat)
+        m = normalise(m + dt / 6.0 * (k1 + 2.0 * k2 + 2.0 * k3 + k4))
+    return m
+
+
+# ----------------------------------------------------------------------------
+# Damping-only relaxation (Methods, "Integrators": damping-only relax)
+# ----------------------------------------------------------------------------
+RELAX_CHUNK = 1e-11  # simulated time between convergence checks (s)
+
+
+def max_torque(m, grid, mat):
+    """max over cells (and replicas) of |dm/dt| of the damping-only dynamics."""
+    k = rhs(m, grid, dataclass_replace(mat, precess=False))
+    return float(np.sqrt(np.sum(k * k, axis=-4)).max())
+
+
+def relax_run(m0, grid, mat, torque_tol, t_max, tol, dt0=1e-14):
+    """Reading of the damping-only relaxer: the precession term is dropped
+    and the adaptive DOPRI5 above integrates in chunks of RELAX_CHUNK of
+    simulated time (each chunk starts with the controller's last proposal of
+    the previous chunk, before its clipping to the chunk's end) until the max-over-cells |dm/dt| after a chunk is <= torque_tol or
+    t_max is reached.  Returns (m, t, accepted, rejected, max |dm/dt|)."""
+    md = dataclass_replace(mat, precess=False)
+    m, t, dt = m0.copy(), 0.0, dt0
+    acc = rej = 0
+    tq = max_torque(m, grid, md)
+    while tq > torque_tol and t < t_max:
+        t1 = min(t + RELAX_CHUNK, t_max)
+        res = rk45_run(m, grid, md, t, t1, tol, dt)
+        m, t, dt = res.m, res.t, res.dt_next
+        acc += res.accepted
+        rej += res.rejected
+        tq = max_torque(m, grid, md)
+    return m, t, acc, rej, tq
 
 
 def dopri5_fixed(m0, f, dt, nsteps):

@@ -11,12 +11,17 @@ import numpy as np
 from .constants import GAMMA0, HBAR, MU0, QE
 
 
-def llg_rhs(m, H, alpha):
+def llg_rhs(m, H, alpha, precess=True):
     """Torque for arrays with the vector component on axis 0 (single replica)
-    or axis 1 (batch: leading replica axis)."""
+    or axis 1 (batch: leading replica axis).  ``precess=False`` drops the
+    precession term: -gamma' mu0 alpha m x (m x H), the damping-only dynamics
+    of the relaxer (Methods, "Integrators": damping-only relax; reading: the
+    same gamma' = gamma0 / (1 + alpha^2))."""
     gp = GAMMA0 / (1.0 + alpha * alpha)
     mxH = np.cross(m, H, axis=-4)
     mxmxH = np.cross(m, mxH, axis=-4)
+    if not precess:
+        return -gp * MU0 * alpha * mxmxH
     return -gp * MU0 * (mxH + alpha * mxmxH)
 
 

@@ -57,6 +57,9 @@ class Material:
     stt_P: float = 0.0
     stt_lambda: float = 1.0
     stt_eps2: float = 0.0
+    # False: damping-only dynamics (the precession term of the LLG equation
+    # dropped), the relaxation dynamics
+    precess: bool = True
 
     @property
     def stt(self) -> bool:
