@@ -198,6 +198,34 @@ mmx_status mmx_depondt_refill(mmx_ctx* ctx, void* m, const void* m_init, double 
                               int64_t n_steps, uint64_t step0, void* times, int32_t cap,
                               void* counts);
 
+/* n_steps classical fourth-order Runge-Kutta steps of fixed size dt
+ * (Methods, "Integrators": RK4, four field evaluations per step), in place
+ * on m (device, D1): k1 = f(m), k2 = f(m + dt/2 k1), k3 = f(m + dt/2 k2),
+ * k4 = f(m + dt k3), m <- normalise(m + dt (k1/6 + k2/3 + k3/3 + k4/6)); the
+ * stage states are not normalised.  Thermal terms are rejected
+ * (MMX_EUNSUP). */
+mmx_status mmx_rk4(mmx_ctx* ctx, void* m, double dt, int64_t n_steps);
+
+/* on = 0: damping-only dynamics (the relaxation dynamics of the Methods'
+ * damping-only relaxer): every torque evaluation of mmx_torque, mmx_rk45 and
+ * mmx_rk4 drops the precession term, dm/dt = -gamma' mu0 alpha m x (m x H)
+ * (gamma' unchanged); mmx_heun and mmx_depondt* return MMX_EUNSUP.  on = 1
+ * (default): the full LLG equation. */
+mmx_status mmx_set_precession(mmx_ctx* ctx, int32_t on);
+
+/* Damping-only relaxation (Methods, "Integrators": damping-only relax) of m
+ * (device, D1, in place): mmx_rk45 on the damping-only dynamics with
+ * tolerance tol, in chunks of 10 ps of simulated time (each chunk starts from
+ * the controller's last proposal before it was clipped to the chunk's end,
+ * the first with 1e-14 s), until the max over all replicas and cells of
+ * |dm/dt| is <= torque_tol (1/s) or the time reaches t_max.  stats (host,
+ * nullable): final time, last proposal, last error, summed step counts;
+ * max_torque (host, nullable): the final max |dm/dt|.  Synchronous; thermal
+ * terms are rejected (MMX_EUNSUP); MMX_EINVAL for torque_tol < 0, t_max <= 0
+ * or tol <= 0. */
+mmx_status mmx_relax(mmx_ctx* ctx, void* m, double torque_tol, double t_max, double tol,
+                     mmx_rk_stats* stats, double* max_torque);
+
 /* Adaptive Dormand-Prince 5(4) relaxation (Methods, "Integrators") of m
  * (device, D1, in place) from t0 to t_end with absolute tolerance tol on the
  * max-over-cells Euclidean norm of the embedded error; first attempt dt0;

@@ -86,6 +86,9 @@ _SIGS = {
     "mmx_depondt": [_P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P],
     "mmx_set_stt": [_P, ctypes.c_int32, _P, _P, ctypes.c_double, ctypes.c_double,
                     ctypes.c_double],
+    "mmx_rk4": [_P, _P, ctypes.c_double, ctypes.c_int64],
+    "mmx_set_precession": [_P, ctypes.c_int32],
+    "mmx_relax": [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P],
     "mmx_depondt_refill": [_P, _P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P,
                            ctypes.c_int32, _P],
     "mmx_rk45": [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -219,6 +222,23 @@ def mmx_set_stt(ctx, group, J, p=(0.0, 0.0, 1.0), P=0.0, Lambda=1.0, eps_prime=0
     _check("mmx_set_stt", _lib.mmx_set_stt(ctx, int(group),
                                            Ja.ctypes.data_as(ctypes.c_void_p), pa, float(P),
                                            float(Lambda), float(eps_prime)))
+
+
+def mmx_rk4(ctx, m, dt, n_steps) -> None:
+    _check("mmx_rk4", _lib.mmx_rk4(ctx, _ptr(m), float(dt), int(n_steps)))
+
+
+def mmx_set_precession(ctx, on) -> None:
+    _check("mmx_set_precession", _lib.mmx_set_precession(ctx, int(bool(on))))
+
+
+def mmx_relax(ctx, m, torque_tol, t_max, tol=1e-6):
+    """Returns (stats, final max |dm/dt|)."""
+    st = mmx_rk_stats()
+    tq = ctypes.c_double(0.0)
+    _check("mmx_relax", _lib.mmx_relax(ctx, _ptr(m), float(torque_tol), float(t_max), float(tol),
+                                       ctypes.byref(st), ctypes.byref(tq)))
+    return st, tq.value
 
 
 def mmx_depondt(ctx, m, dt, n_steps, step0=0, t_switch=None) -> None:

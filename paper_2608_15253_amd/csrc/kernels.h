@@ -37,6 +37,7 @@ struct RkState {
   double t, dt, t_end, tol, dt_max, dt_min;
   unsigned long long err_bits;  // max error of the current attempt (bit pattern)
   double last_err;
+  double dt_prop;  // the controller's last proposal before clipping to t_end
   long long accepted, rejected, n_replay, replay_idx;
   int done, accepted_flag, final_flag, nonfinite, dtmin_hit, pad;
 };
@@ -392,6 +393,7 @@ struct FArgs {
   const unsigned long long* tstart;  // and the first step of its running trial
   // Slonczewski spin-transfer torque: b_J = stt_c J[r] (A/m), fixed-layer unit
   // vector, polarisation, Lambda^2 and the field-like coefficient eps'
+  int noprec;         // damping-only dynamics: the precession term is dropped
   const double* Jrep;
   double stt_c;
   T sttp[3], stt_P, stt_L2, stt_e2;
@@ -500,6 +502,15 @@ template <typename T>
 __device__ inline void cell_torque(const FArgs<T>& a, T bJ, const T mc[3], const T H[3], T k[3],
                                    T tau[3]) {
   llg_torque(mc, H, a.gpm, a.alpha, k);
+  if (a.noprec) {
+    // damping-only dynamics: -gamma' mu0 alpha m x (m x H)
+    const T cx = mc[1] * H[2] - mc[2] * H[1];
+    const T cy = mc[2] * H[0] - mc[0] * H[2];
+    const T cz = mc[0] * H[1] - mc[1] * H[0];
+    k[0] = -a.gpm * (a.alpha * (mc[1] * cz - mc[2] * cy));
+    k[1] = -a.gpm * (a.alpha * (mc[2] * cx - mc[0] * cz));
+    k[2] = -a.gpm * (a.alpha * (mc[0] * cy - mc[1] * cx));
+  }
   tau[0] = tau[1] = tau[2] = T(0);
   if (bJ != T(0)) {
     stt_tau(a, bJ, mc, tau);

@@ -251,6 +251,8 @@ struct mmx_ctx {
   double hext_scale = 0, hext_mz = 0;
   void* hd_out = nullptr;
   DevBuf sg_h, sg_hd, sg_part, sg_err;  // surrogate integrator buffers
+  int noprec = 0;  // damping-only dynamics (mmx_set_precession(ctx, 0), mmx_relax)
+  DevBuf maxbuf;   // max-reduction partials (mmx_relax)
   int rot = 0;     // Heun epilogues take the rotation update (mmx_depondt*)
   int refill = 0;  // per-replica trial generation and start step (mmx_depondt_refill)
 };
@@ -479,6 +481,7 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   } else {
     a.terms &= ~(unsigned)T_STT;
   }
+  a.noprec = ctx->noprec;
   a.rot = ctx->rot;
   if (ctx->refill) {
     a.tgen = G.tgen.as<int>();
@@ -766,6 +769,7 @@ mmx_status rk_begin(mmx_ctx* ctx, double t0, double t_end, double tol, double dt
     h.n_replay = n_replay;
   } else {
     h.dt = std::min(dt0, h.dt_max);
+    h.dt_prop = h.dt;
     h.final_flag = (t0 + h.dt >= t_end) ? 1 : 0;
     if (h.final_flag) h.dt = t_end - t0;
   }
@@ -870,7 +874,7 @@ mmx_status rk_first_stage(mmx_ctx* ctx, T* mb) {
 template <typename T>
 mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, double dt0,
                      const double* replay, int64_t n_replay, void* trace, int64_t cap,
-                     mmx_rk_stats* stats) {
+                     mmx_rk_stats* stats, double* dt_prop = nullptr) {
   RkState h;
   MMX_TRY(rk_begin<T>(ctx, t0, t_end, tol, dt0, replay, n_replay, h));
   hipStream_t s = ctx->stream;
@@ -953,6 +957,7 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
     }
   }
   ctx->last_accepted = h.accepted;
+  if (dt_prop) *dt_prop = h.dt_prop;
   if (stats) {
     stats->t = h.t;
     stats->dt = h.dt;
@@ -1096,6 +1101,8 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
   T* mb = reinterpret_cast<T*>(m);
   double* tsw_d = reinterpret_cast<double*>(tsw);
   const bool refill = rf != nullptr;
+  if (ctx->noprec)
+    return fail(MMX_EUNSUP, "damping-only dynamics are for RK45, RK4 and the relaxer");
   if ((rot || refill) && ctx->path == MMX_PATH_FUSED)
     return fail(MMX_EUNSUP, "the rotation scheme runs on the staged path only");
   SchemeScope scheme(ctx, rot, refill ? 1 : 0);
@@ -1287,6 +1294,114 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
     HIP_TRY(hipStreamWaitEvent(user, ctx->ev_cap, 0));
   }
   for (int64_t i = done_steps; i < n_steps; ++i) MMX_TRY(one_step(step0 + (uint64_t)i));
+  return MMX_OK;
+}
+
+// Classical fourth-order Runge-Kutta (fixed dt): stage states m + dt/2 k1,
+// m + dt/2 k2, m + dt k3 (not normalised); the new state m + dt (k1/6 + k2/3
+// + k3/3 + k4/6) is normalised.
+template <typename T>
+mmx_status rk4_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps) {
+  if (!(dt > 0)) return fail(MMX_EINVAL, "dt must be > 0");
+  if (n_steps < 0) return fail(MMX_EINVAL, "n_steps must be >= 0");
+  if (ctx->terms & MMX_THERMAL) return fail(MMX_EUNSUP, "thermal field with RK4");
+  for (auto& gp : ctx->groups) MMX_TRY(ensure_rk_buffers<T>(*gp));
+  T* mb = reinterpret_cast<T*>(m);
+  for (int64_t i = 0; i < n_steps; ++i) {
+    for (auto& gp : ctx->groups) {
+      Group& G = *gp;
+      T* mg = mb + G.off;
+      Epilogue e;
+      e.mode = FM_RKK;
+      e.out = G.k[0].p;
+      MMX_TRY(eval_group<T>(ctx, G, mg, Combine{}, e, 0, dt, nullptr, dt, nullptr));
+      for (int st = 1; st < 4; ++st) {
+        Combine cb;
+        cb.ncoef = 1;
+        cb.coef[0] = st == 3 ? 1.0 : 0.5;
+        cb.kidx[0] = st - 1;
+        cb.mout = G.ms.p;
+        e.out = G.k[st].p;
+        MMX_TRY(eval_group<T>(ctx, G, mg, cb, e, 0, dt, nullptr, dt, nullptr));
+      }
+      Combine fc;
+      fc.ncoef = 4;
+      const double w[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+      for (int j = 0; j < 4; ++j) {
+        fc.coef[j] = w[j];
+        fc.kidx[j] = j;
+      }
+      fc.normalise = 1;
+      fc.mout = mg;
+      MMX_TRY(launch_xfwd<T>(ctx, G, mg, fc, false, nullptr, dt, nullptr));
+    }
+  }
+  return MMX_OK;
+}
+
+// max over all replicas and cells of |dm/dt| (synchronous)
+template <typename T>
+mmx_status max_torque(mmx_ctx* ctx, const T* mb, double* out) {
+  constexpr int nb = 256;
+  HIP_TRY(ctx->maxbuf.ensure((nb + 1) * sizeof(double)));
+  for (auto& gp : ctx->groups) MMX_TRY(ensure_rk_buffers<T>(*gp));
+  double mx = 0;
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    Epilogue e;
+    e.mode = FM_TORQUE;
+    e.out = G.k[6].p;
+    MMX_TRY(eval_group<T>(ctx, G, mb + G.off, Combine{}, e, 0, 1.0, nullptr, 1.0, nullptr));
+    k_norm_max<T><<<nb, 256, 0, ctx->stream>>>(G.k[6].as<T>(), (size_t)G.N, G.R,
+                                                 ctx->maxbuf.as<double>());
+    k_max_fold<<<1, 256, 0, ctx->stream>>>(ctx->maxbuf.as<double>(), nb);
+    HIP_TRY(hipGetLastError());
+    double g = 0;
+    HIP_TRY(hipMemcpyAsync(&g, ctx->maxbuf.as<double>() + nb, sizeof(double),
+                           hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    mx = std::max(mx, g);
+  }
+  *out = mx;
+  return MMX_OK;
+}
+
+// Damping-only relaxation: RK45 on the damping-only dynamics in chunks of
+// 10 ps of simulated time (each chunk starting from the controller's last
+// unclipped proposal) until max |dm/dt| <= torque_tol or t reaches t_max.
+template <typename T>
+mmx_status relax_impl(mmx_ctx* ctx, void* m, double torque_tol, double t_max, double tol,
+                      mmx_rk_stats* stats, double* tq_out) {
+  constexpr double kChunk = 1e-11;
+  struct NoPrec {
+    mmx_ctx* c;
+    int prev;
+    ~NoPrec() { c->noprec = prev; }
+  } guard{ctx, ctx->noprec};
+  ctx->noprec = 1;
+  const T* mb = reinterpret_cast<const T*>(m);
+  double t = 0, dt = 1e-14, tq = 0;
+  int64_t acc = 0, rej = 0;
+  MMX_TRY(max_torque<T>(ctx, mb, &tq));
+  mmx_rk_stats st{};
+  while (tq > torque_tol && t < t_max) {
+    const double t1 = std::min(t + kChunk, t_max);
+    double prop = dt;
+    MMX_TRY(rk45_impl<T>(ctx, m, t, t1, tol, dt, nullptr, 0, nullptr, 0, &st, &prop));
+    t = st.t;
+    dt = prop;
+    acc += st.accepted;
+    rej += st.rejected;
+    MMX_TRY(max_torque<T>(ctx, mb, &tq));
+  }
+  if (stats) {
+    stats->t = t;
+    stats->dt = dt;
+    stats->err = st.err;
+    stats->accepted = acc;
+    stats->rejected = rej;
+  }
+  if (tq_out) *tq_out = tq;
   return MMX_OK;
 }
 
@@ -1674,6 +1789,33 @@ mmx_status mmx_heun(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t 
   if (!m) return fail(MMX_EINVAL, "null array");
   return ctx->prec == MMX_F64 ? heun_impl<double>(ctx, m, dt, n_steps, step0, t_switch)
                               : heun_impl<float>(ctx, m, dt, n_steps, step0, t_switch);
+}
+
+mmx_status mmx_rk4(mmx_ctx* ctx, void* m, double dt, int64_t n_steps) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  if (!m) return fail(MMX_EINVAL, "null array");
+  return ctx->prec == MMX_F64 ? rk4_impl<double>(ctx, m, dt, n_steps)
+                              : rk4_impl<float>(ctx, m, dt, n_steps);
+}
+
+mmx_status mmx_set_precession(mmx_ctx* ctx, int32_t on) {
+  MMX_TRY(check_ctx(ctx));
+  ctx->noprec = on ? 0 : 1;
+  return MMX_OK;
+}
+
+mmx_status mmx_relax(mmx_ctx* ctx, void* m, double torque_tol, double t_max, double tol,
+                     mmx_rk_stats* stats, double* max_torque_out) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  if (!m) return fail(MMX_EINVAL, "null array");
+  if (!(torque_tol >= 0) || !(t_max > 0) || !(tol > 0))
+    return fail(MMX_EINVAL, "torque_tol >= 0, t_max > 0 and tol > 0 required");
+  if (ctx->terms & MMX_THERMAL) return fail(MMX_EUNSUP, "thermal field in the relaxer");
+  return ctx->prec == MMX_F64
+             ? relax_impl<double>(ctx, m, torque_tol, t_max, tol, stats, max_torque_out)
+             : relax_impl<float>(ctx, m, torque_tol, t_max, tol, stats, max_torque_out);
 }
 
 mmx_status mmx_depondt(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,

@@ -129,6 +129,7 @@ __global__ void k_rk_controller(RkState* st, const double* replay, double* dts, 
     if (st->replay_idx >= st->n_replay) st->done = 1;
     return;
   }
+  st->dt_prop = next;
   st->final_flag = (st->t + next >= st->t_end) ? 1 : 0;
   if (st->final_flag) next = st->t_end - st->t;
   st->dt = next;
@@ -210,6 +211,43 @@ __global__ void k_fill_u64(unsigned long long* p, size_t n, unsigned long long v
 __global__ void k_fill_f64(double* p, size_t n, double v) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// max over cells of |v| for vectors stored component-major per replica
+// (n cells per replica, R replicas): per-workgroup maxima, then one workgroup
+// folds them (part: gridDim.x doubles).
+template <typename T>
+__global__ void k_norm_max(const T* v, size_t n, int R, double* part) {
+  __shared__ double red[256];
+  double mx = 0;
+  const size_t total = n * (size_t)R;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const size_t r = i / n, c = i - r * n;
+    const T* b = v + r * 3 * n + c;
+    const double x = (double)b[0], y = (double)b[n], z = (double)b[2 * n];
+    mx = fmax(mx, sqrt(x * x + y * y + z * z));
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_max_fold(double* part, int n) {
+  __shared__ double red[256];
+  double mx = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) mx = fmax(mx, part[i]);
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[n] = red[0];
 }
 
 // step counter of captured graphs: set before a replay, advanced inside it
