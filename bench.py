@@ -446,6 +446,46 @@ def bench_stt(args):
                          "P_sw": [round(float(x), 4) for x in psw]}}
 
 
+def bench_throughput(args):
+    """Milliseconds per field evaluation (FP32, T = 0, exchange + demag +
+    Zeeman) on single grids with the cell counts of the paper's throughput
+    table (10 K 2-D, 65 K / 540 K / 2.5 M 3-D; the grids are stand-ins with
+    about those counts and 5-smooth padded sizes), advanced by fixed-step RK4
+    (four evaluations per step)."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import random_unit
+    grids = [("2d_10k", (128, 80, 1), (4e-9, 4e-9, 3e-9)),
+             ("3d_65k", (64, 64, 16), (4e-9, 4e-9, 4e-9)),
+             ("3d_540k", (128, 128, 32), (4e-9, 4e-9, 4e-9)),
+             ("3d_2.5m", (256, 256, 40), (4e-9, 4e-9, 4e-9))]
+    out = {}
+    for name, n, cell in grids:
+        ctx = mmx.mmx_create([mmx.make_group(n, cell, replicas=1)], mmx.MMX_F32)
+        mmx.mmx_set_stream(ctx, torch.cuda.current_stream().cuda_stream)
+        mmx.mmx_set_material(ctx, 0, Ms=8e5, A=1.3e-11, alpha=0.02, Ku=0.0, u=(0, 0, 1), D=0.0)
+        mmx.mmx_set_field(ctx, 0, (0.0, 0.0, 0.01))
+        mmx.mmx_set_terms(ctx, mmx.MMX_EXCH | mmx.MMX_DEMAG | mmx.MMX_ZEEMAN)
+        mmx.mmx_build_demag(ctx)
+        mmx.mmx_autotune(ctx)
+        m = torch.tensor(random_unit(n, seed=5, replicas=1), dtype=torch.float32,
+                         device="cuda:0").contiguous()
+        mmx.mmx_rk4(ctx, m, 1e-14, 5)
+        torch.cuda.synchronize()
+        steps = 200 if n[0] * n[1] * n[2] < 1e6 else 50
+        t0 = time.perf_counter()
+        mmx.mmx_rk4(ctx, m, 1e-14, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        mmx.mmx_destroy(ctx)
+        out[name] = {"grid": list(n), "cells": n[0] * n[1] * n[2],
+                     "ms_per_field_eval": el / (4 * steps) * 1e3, "steps": steps}
+    return {"metric": "ms per field evaluation, single grids (RK4, FP32, T = 0)",
+            "value": out["3d_2.5m"]["ms_per_field_eval"], "unit": "ms", "n_gpus": 1,
+            "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": "field_eval_throughput_rk4"}, "grids": out}
+
+
 def setup(R, prec, seeds, n=(64, 64, 1)):
     import torch
     import paper_2608_15253_amd as mmx
@@ -506,7 +546,8 @@ def main():
                     help="write the HBM traffic table from two rocprofv3 --pmc runs")
     ap.add_argument("--traffic-cmd", default="", help="command line recorded in the summary")
     ap.add_argument("--workload", default="switching",
-                    choices=["switching", "uneven", "closure", "skyrmion512", "depondt", "stt"],
+                    choices=["switching", "uneven", "closure", "skyrmion512", "depondt", "stt",
+                             "throughput"],
                     help="switching: the benchmark line; the others measure the other "
                          "workload configurations (one JSON line each)")
     ap.add_argument("--t-end", type=float, default=None,
@@ -524,7 +565,8 @@ def main():
     if args.workload != "switching":
         print(json.dumps({"uneven": bench_uneven, "closure": bench_closure,
                           "skyrmion512": bench_skyrmion512,
-                          "depondt": bench_depondt, "stt": bench_stt}[args.workload](args)))
+                          "depondt": bench_depondt, "stt": bench_stt,
+                          "throughput": bench_throughput}[args.workload](args)))
         return
     import torch
     import paper_2608_15253_amd as mmx
