@@ -271,7 +271,9 @@ mmx_status mmx_topological_charge(mmx_ctx* ctx, const void* m, void* Q);
  * and column scratch fit the device's LDS per workgroup; mmx_heun returns
  * MMX_EUNSUP otherwise).  MMX_PATH_AUTO (default): fused where it fits, staged
  * elsewhere.  Both paths compute the same arithmetic per transform line and
- * per cell. */
+ * per cell.  Under AUTO and FUSED, single-cell groups without the demag term
+ * (macrospins) advance every replica for all steps in one thread's registers
+ * (mmx_heun and mmx_depondt; results equal the staged path to round-off). */
 enum { MMX_PATH_AUTO = 0, MMX_PATH_STAGED = 1, MMX_PATH_FUSED = 2 };
 mmx_status mmx_set_path(mmx_ctx* ctx, int32_t path);
 
