@@ -13,6 +13,17 @@ for a batch of replicas sharing one geometry and material.
   ghost is m_edge +/- D_a d_a m.  Along z, and everywhere when D = 0, the ghost
   is m_edge (Neumann).  Exchange and DMI share the ghosts (reading).  An axis
   with a single cell contributes no derivative (reading).
+* Bulk DMI (Methods lists it among the field terms; form not printed;
+  reading): energy density Db m . (curl m), field H = -(2 Db / mu0 Ms) curl m
+  with central differences; its free boundary condition (from the variation
+  of A |grad m|^2 + Db m . curl m) is d_a m = (Db / 2A) e_a x m on every open
+  axis, added to the interfacial one in the shared ghosts.
+* Cubic anisotropy (Methods; reading): energy density Kc1 (m1^2 m2^2 +
+  m2^2 m3^2 + m3^2 m1^2) + Kc2 m1^2 m2^2 m3^2 with m_i = m . c_i, c3 = c1 x c2,
+  field H = -(1 / mu0 Ms) dE/dm.
+* RKKY interlayer exchange (Methods; reading): surface energy density
+  -sigma m(z0) . m(z1) between cell layers z0 and z1, field on either layer
+  (sigma / (mu0 Ms d_z)) m(other layer).
 * Uniaxial anisotropy H = (2 Ku / mu0 Ms)(m . u) u; Zeeman H = B / mu0.
 * Thermal (Brown) field H = sigma eta with
   sigma = sqrt(2 alpha kB T / (mu0^2 Ms V gamma0 dt)) (Results, "A
@@ -36,16 +47,29 @@ def _comp(m, c):
     return m[..., c, :, :, :]
 
 
-def _edge_derivative(mc, axis, D, A):
-    """Boundary-condition derivative d_axis m at an open edge (3, ...)."""
+def _edge_derivative(mc, axis, D, A, Db=0.0):
+    """Boundary-condition derivative d_axis m at an open edge (3, ...):
+    interfacial (D/2A)(z x e_a) x m on x and y, bulk (Db/2A) e_a x m on
+    every axis."""
     k = D / (2.0 * A) if A != 0 else 0.0
+    kb = Db / (2.0 * A) if A != 0 else 0.0
     mx, my, mz = _comp(mc, 0), _comp(mc, 1), _comp(mc, 2)
     zero = np.zeros_like(mx)
     if axis == 0:
-        return k * np.stack([mz, zero, -mx], axis=-4)
-    if axis == 1:
-        return k * np.stack([zero, mz, -my], axis=-4)
-    return np.zeros_like(mc)
+        out = k * np.stack([mz, zero, -mx], axis=-4)
+    elif axis == 1:
+        out = k * np.stack([zero, mz, -my], axis=-4)
+    else:
+        out = np.zeros_like(mc)
+    if kb != 0.0:
+        if axis == 0:    # x x m
+            ex = np.stack([zero, -mz, my], axis=-4)
+        elif axis == 1:  # y x m
+            ex = np.stack([mz, zero, -mx], axis=-4)
+        else:            # z x m
+            ex = np.stack([-my, mx, zero], axis=-4)
+        out = out + kb * ex
+    return out
 
 
 def neighbours(m, grid, mat, axis):
@@ -63,12 +87,12 @@ def neighbours(m, grid, mat, axis):
     first[m.ndim + ax] = slice(0, 1)
     last[m.ndim + ax] = slice(n - 1, n)
     first, last = tuple(first), tuple(last)
-    use_dmi = mat.D != 0.0 and axis in (0, 1)
+    use_dmi = (mat.D != 0.0 and axis in (0, 1)) or mat.Db != 0.0
     m_first = m[first]
     m_last = m[last]
     if use_dmi:
-        mm[first] = m_first - h * _edge_derivative(m_first, axis, mat.D, mat.A)
-        mp[last] = m_last + h * _edge_derivative(m_last, axis, mat.D, mat.A)
+        mm[first] = m_first - h * _edge_derivative(m_first, axis, mat.D, mat.A, mat.Db)
+        mp[last] = m_last + h * _edge_derivative(m_last, axis, mat.D, mat.A, mat.Db)
     else:
         mm[first] = m_first
         mp[last] = m_last
@@ -99,6 +123,71 @@ def dmi_field(m, grid, mat):
         # d_x m_z -> H_x ; d_y m_z -> H_y ; -d_x m_x - d_y m_y -> H_z
         H[..., axis, :, :, :] += pref * _comp(d, 2)
         H[..., 2, :, :, :] -= pref * _comp(d, axis)
+    return H
+
+
+def bulk_dmi_field(m, grid, mat):
+    """-(2 Db / mu0 Ms) curl m, central differences with the shared ghosts."""
+    H = np.zeros_like(m)
+    if mat.Db == 0.0:
+        return H
+    pref = -2.0 * mat.Db / (MU0 * mat.Ms)
+    for axis in range(3):
+        if grid.n[axis] == 1:
+            continue
+        mm, mp = neighbours(m, grid, mat, axis)
+        d = (mp - mm) / (2.0 * grid.cell[axis])  # d_axis m
+        # curl_c = sum over (axis, j) of eps_{c axis j} d_axis m_j
+        for c in range(3):
+            for j in range(3):
+                e = _levi_civita(c, axis, j)
+                if e:
+                    H[..., c, :, :, :] += pref * e * _comp(d, j)
+    return H
+
+
+def _levi_civita(i, j, k):
+    return (i - j) * (j - k) * (k - i) // 2
+
+
+def _cubic_axes(mat):
+    c1 = np.asarray(mat.c1, float)
+    c1 = c1 / np.linalg.norm(c1)
+    c2 = np.asarray(mat.c2, float)
+    c2 = c2 - (c2 @ c1) * c1
+    c2 = c2 / np.linalg.norm(c2)
+    return c1, c2, np.cross(c1, c2)
+
+
+def cubic_field(m, mat):
+    """-(1 / mu0 Ms) d/dm of Kc1 (m1^2 m2^2 + m2^2 m3^2 + m3^2 m1^2) +
+    Kc2 m1^2 m2^2 m3^2."""
+    if mat.Kc1 == 0.0 and mat.Kc2 == 0.0:
+        return np.zeros_like(m)
+    ax = _cubic_axes(mat)
+    mi = [sum(a[c] * _comp(m, c) for c in range(3)) for a in ax]
+    g = [2 * mat.Kc1 * mi[i] * (mi[(i + 1) % 3] ** 2 + mi[(i + 2) % 3] ** 2) +
+         2 * mat.Kc2 * mi[i] * mi[(i + 1) % 3] ** 2 * mi[(i + 2) % 3] ** 2 for i in range(3)]
+    pref = -1.0 / (MU0 * mat.Ms)
+    return pref * np.stack([sum(g[i] * ax[i][c] for i in range(3)) for c in range(3)], axis=-4)
+
+
+def cubic_energy_density(m, mat):
+    ax = _cubic_axes(mat)
+    mi = [sum(a[c] * _comp(m, c) for c in range(3)) for a in ax]
+    return (mat.Kc1 * (mi[0] ** 2 * mi[1] ** 2 + mi[1] ** 2 * mi[2] ** 2 + mi[2] ** 2 * mi[0] ** 2)
+            + mat.Kc2 * mi[0] ** 2 * mi[1] ** 2 * mi[2] ** 2)
+
+
+def rkky_field(m, grid, mat):
+    """(sigma / (mu0 Ms d_z)) m(other layer) on layers z0 and z1."""
+    H = np.zeros_like(m)
+    if mat.rkky == 0.0:
+        return H
+    z0, z1 = mat.rkky_z
+    pref = mat.rkky / (MU0 * mat.Ms * grid.cell[2])
+    H[..., z0, :, :] += pref * m[..., z1, :, :]
+    H[..., z1, :, :] += pref * m[..., z0, :, :]
     return H
 
 
@@ -144,6 +233,9 @@ def terms(m, grid, mat):
     """Dict of the deterministic field terms at state m."""
     out = {"exchange": exchange_field(m, grid, mat),
            "dmi": dmi_field(m, grid, mat),
+           "dmi_bulk": bulk_dmi_field(m, grid, mat),
+           "cubic": cubic_field(m, mat),
+           "rkky": rkky_field(m, grid, mat),
            "demag": (_demag.demag_field(m, grid, mat.Ms) if mat.demag
                      else np.zeros_like(m)),
            "anisotropy": anisotropy_field(m, mat),
@@ -155,6 +247,7 @@ def effective_field(m, grid, mat, H_thermal=None):
     """H_eff = demag + exchange + DMI + anisotropy + Zeeman (+ thermal)."""
     t = terms(m, grid, mat)
     H = t["exchange"] + t["dmi"] + t["demag"] + t["anisotropy"] + t["zeeman"]
+    H = H + t["dmi_bulk"] + t["cubic"] + t["rkky"]
     if H_thermal is not None:
         H = H + H_thermal
     return H

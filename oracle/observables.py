@@ -6,6 +6,8 @@ printing their discretisation.  Readings:
 
 * Energy (J): E = V sum_i [ -(mu0 Ms / 2) m_i . (H_ex + H_dmi + H_demag + H_anis)_i
   - mu0 Ms m_i . H_zeeman ]; the anisotropy part equals -Ku V sum (m . u)^2.
+  Bulk DMI and RKKY (bilinear) enter like the first group; the cubic
+  anisotropy (quartic) as V sum of its energy density.
   The thermal field is excluded.
 * Topological charge: Q = (1/4 pi) sum_i m_i . (d_x m x d_y m)_i dx dy with
   central differences, periodic wrap on periodic axes, and the cell itself as the
@@ -20,14 +22,21 @@ import numpy as np
 from .constants import MU0
 from . import fields as _fields
 
-ENERGY_TERMS = ("exchange", "dmi", "demag", "anisotropy", "zeeman")
+ENERGY_TERMS = ("exchange", "dmi", "demag", "anisotropy", "zeeman", "dmi_bulk", "cubic", "rkky")
 
 
 def energies(m, grid, mat):
+    """Energy per term; the quadratic terms as -(mu0 Ms V / 2) sum m . H, the
+    Zeeman term as -mu0 Ms V sum m . H, the cubic anisotropy (quartic) from
+    its energy density."""
     t = _fields.terms(m, grid, mat)
     V = grid.volume
     out = {}
     for name in ENERGY_TERMS:
+        if name == "cubic":
+            out[name] = V * float(np.sum(_fields.cubic_energy_density(m, mat))) \
+                if (mat.Kc1 or mat.Kc2) else 0.0
+            continue
         dot = float(np.sum(m * t[name]))
         if name == "zeeman":
             out[name] = -MU0 * mat.Ms * V * dot

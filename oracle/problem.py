@@ -60,6 +60,17 @@ class Material:
     # False: damping-only dynamics (the precession term of the LLG equation
     # dropped), the relaxation dynamics
     precess: bool = True
+    # cubic anisotropy (J/m^3) along axes c1, c2, c3 = c1 x c2
+    Kc1: float = 0.0
+    Kc2: float = 0.0
+    c1: tuple = (1.0, 0.0, 0.0)
+    c2: tuple = (0.0, 1.0, 0.0)
+    # bulk DMI (J/m^2)
+    Db: float = 0.0
+    # RKKY interlayer exchange: surface energy density (J/m^2) coupling
+    # cell layers z0 and z1
+    rkky: float = 0.0
+    rkky_z: tuple = (0, 1)
 
     @property
     def stt(self) -> bool:
