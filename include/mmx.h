@@ -61,7 +61,10 @@ enum {
   MMX_DEMAG = 16,          /* Newell-tensor FFT demagnetisation                */
   MMX_THERMAL = 32,        /* Brown thermal field (Philox4x32-10 noise)        */
   MMX_STT = 64,            /* Slonczewski spin-transfer torque (mmx_set_stt)   */
-  MMX_ALL_TERMS = 127
+  MMX_DMI_BULK = 128,      /* bulk DMI (mmx_set_material_ext)                  */
+  MMX_ANIS_CUBIC = 256,    /* cubic anisotropy (mmx_set_material_ext)          */
+  MMX_RKKY = 512,          /* RKKY interlayer exchange (mmx_set_material_ext)  */
+  MMX_ALL_TERMS = 1023
 };
 
 /* One geometry advanced for `replicas` independent replicas. */
@@ -87,6 +90,16 @@ typedef struct {
   double t, dt, err;                    /* time, next step size, last error   */
   int64_t accepted, rejected;           /* step counts                        */
 } mmx_rk_stats;
+
+/* Further field terms of a group (Methods, "Physics and discretization":
+ * bulk DMI, cubic anisotropy, RKKY interlayer exchange).  SI units. */
+typedef struct {
+  double Kc1, Kc2;       /* cubic anisotropy constants, J/m^3                 */
+  double c1[3], c2[3];   /* cubic axes (c2 made orthogonal to c1; c3 = c1 x c2) */
+  double Db;             /* bulk DMI, J/m^2                                   */
+  double rkky;           /* RKKY surface energy density sigma, J/m^2          */
+  int32_t rkky_z[2];     /* the two coupled cell layers (distinct, < n_z)      */
+} mmx_material_ext;
 
 /* Creates a context for `n_groups` geometries.  Checks that device 0 of the
  * current HIP device set is gfx950 and that every axis length can be
@@ -129,6 +142,24 @@ mmx_status mmx_set_thermal(mmx_ctx* ctx, int32_t group, const double* T_per_repl
  * (Px/2+1)(Py/2+1)(Pz/2+1) block per component and rounded to the context
  * precision.  Requires the material to be set.  Synchronous. */
 mmx_status mmx_build_demag(mmx_ctx* ctx);
+
+/* Further field terms of group `group` (enabled by MMX_DMI_BULK,
+ * MMX_ANIS_CUBIC, MMX_RKKY in the term mask):
+ *   bulk DMI: energy density Db m.(curl m), H = -(2 Db / mu0 Ms) curl m with
+ *     central differences; open edges add (Db/2A) e_a x m to the free-edge
+ *     derivative of the shared exchange/DMI ghosts on every axis (from the
+ *     material's Db, whatever the mask);
+ *   cubic anisotropy: energy density Kc1 (m1^2 m2^2 + m2^2 m3^2 + m3^2 m1^2)
+ *     + Kc2 m1^2 m2^2 m3^2, m_i = m.c_i, H = -(1/mu0 Ms) dE/dm;
+ *   RKKY: surface energy density -sigma m(z0).m(z1) between cell layers
+ *     z0 = rkky_z[0], z1 = rkky_z[1]: H = sigma / (mu0 Ms dz) m(other layer).
+ * mmx_energy reports bulk DMI in the DMI slot, cubic anisotropy in the
+ * anisotropy slot (from its energy density) and RKKY in the exchange slot.
+ * These terms run on the field kernels of the staged path (the register row
+ * kernels and the replica-resident path do not take them).  MMX_EINVAL for a
+ * null pointer, Db != 0 with A = 0, zero or parallel cubic axes, or RKKY
+ * layers that are equal or out of range. */
+mmx_status mmx_set_material_ext(mmx_ctx* ctx, int32_t group, const mmx_material_ext* ext);
 
 /* Slonczewski spin-transfer torque of group `group` (Methods, "Physics and
  * discretization": spin torques added per integrator stage; Results, the

@@ -31,7 +31,10 @@ STATUS = {0: "MMX_OK", -1: "MMX_EINVAL", -2: "MMX_ESHAPE", -3: "MMX_EHIP",
 MMX_EXCH, MMX_DMI_INTERFACIAL, MMX_ANIS_UNIAXIAL = 1, 2, 4
 MMX_ZEEMAN, MMX_DEMAG, MMX_THERMAL = 8, 16, 32
 MMX_STT = 64
-MMX_ALL_TERMS = 127
+MMX_DMI_BULK = 128
+MMX_ANIS_CUBIC = 256
+MMX_RKKY = 512
+MMX_ALL_TERMS = 1023
 DEFAULT_TERMS = MMX_EXCH | MMX_DMI_INTERFACIAL | MMX_ANIS_UNIAXIAL | MMX_ZEEMAN | MMX_DEMAG
 
 
@@ -44,6 +47,13 @@ class mmx_group(ctypes.Structure):
 class mmx_material(ctypes.Structure):
     _fields_ = [("Ms", ctypes.c_double), ("A", ctypes.c_double), ("alpha", ctypes.c_double),
                 ("Ku", ctypes.c_double), ("u", ctypes.c_double * 3), ("D", ctypes.c_double)]
+
+
+class mmx_material_ext(ctypes.Structure):
+    _fields_ = [("Kc1", ctypes.c_double), ("Kc2", ctypes.c_double),
+                ("c1", ctypes.c_double * 3), ("c2", ctypes.c_double * 3),
+                ("Db", ctypes.c_double), ("rkky", ctypes.c_double),
+                ("rkky_z", ctypes.c_int32 * 2)]
 
 
 class mmx_rk_stats(ctypes.Structure):
@@ -87,6 +97,7 @@ _SIGS = {
     "mmx_set_stt": [_P, ctypes.c_int32, _P, _P, ctypes.c_double, ctypes.c_double,
                     ctypes.c_double],
     "mmx_rk4": [_P, _P, ctypes.c_double, ctypes.c_int64],
+    "mmx_set_material_ext": [_P, ctypes.c_int32, _P],
     "mmx_set_precession": [_P, ctypes.c_int32],
     "mmx_relax": [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P],
     "mmx_depondt_refill": [_P, _P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P,
@@ -222,6 +233,14 @@ def mmx_set_stt(ctx, group, J, p=(0.0, 0.0, 1.0), P=0.0, Lambda=1.0, eps_prime=0
     _check("mmx_set_stt", _lib.mmx_set_stt(ctx, int(group),
                                            Ja.ctypes.data_as(ctypes.c_void_p), pa, float(P),
                                            float(Lambda), float(eps_prime)))
+
+
+def mmx_set_material_ext(ctx, group, Kc1=0.0, Kc2=0.0, c1=(1.0, 0.0, 0.0), c2=(0.0, 1.0, 0.0),
+                         Db=0.0, rkky=0.0, rkky_z=(0, 1)) -> None:
+    e = mmx_material_ext(float(Kc1), float(Kc2), (ctypes.c_double * 3)(*map(float, c1)),
+                         (ctypes.c_double * 3)(*map(float, c2)), float(Db), float(rkky),
+                         (ctypes.c_int32 * 2)(*map(int, rkky_z)))
+    _check("mmx_set_material_ext", _lib.mmx_set_material_ext(ctx, int(group), ctypes.byref(e)))
 
 
 def mmx_rk4(ctx, m, dt, n_steps) -> None:

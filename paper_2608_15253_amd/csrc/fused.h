@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(kFusedBlock) k_heun_fused(HeunFusedArgs<T> a) 
           T mc[3];
           ld3(src + rb, (unsigned)f.N, (unsigned)cell, mc);
           T Hex[3], Hdm[3], Han[3], Hz[3];
-          local_terms(f, src + rb, (unsigned)cell, x, y, 0, mc, f.kbc, Hex, Hdm, Han, Hz);
+          local_terms<T, false>(f, src + rb, (unsigned)cell, x, y, 0, mc, f.kbc, Hex, Hdm, Han, Hz);
           T Hdd[3] = {0, 0, 0};
           if (demag) {
 #pragma unroll

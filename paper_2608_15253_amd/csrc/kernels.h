@@ -25,7 +25,8 @@
 namespace mmx {
 
 enum : unsigned {
-  T_EXCH = 1, T_DMI = 2, T_ANIS = 4, T_ZEEMAN = 8, T_DEMAG = 16, T_THERMAL = 32, T_STT = 64
+  T_EXCH = 1, T_DMI = 2, T_ANIS = 4, T_ZEEMAN = 8, T_DEMAG = 16, T_THERMAL = 32, T_STT = 64,
+  T_DMI_BULK = 128, T_CUBIC = 256, T_RKKY = 512
 };
 
 enum FieldMode { FM_FIELD = 0, FM_TORQUE, FM_HEUN1, FM_HEUN2, FM_RKK, FM_RK7, FM_ENERGY };
@@ -360,6 +361,12 @@ struct FArgs {
   T ih2[3];   // 1/(2d) (DMI)
   T hd[3];    // cell size (ghosts)
   T cex, cdmi, kbc, can, u[3], hz[3], gpm, alpha;
+  // bulk DMI: field -(2 Db / mu0 Ms) curl m (cbulk), ghost factor Db / 2A (kbb);
+  // cubic anisotropy 2 Kc1 / mu0 Ms, 2 Kc2 / mu0 Ms along the rows of cax;
+  // RKKY: sigma / (mu0 Ms dz) between cell layers rkz0 and rkz1
+  T cbulk, kbb, kc1h, kc2h, kc1, kc2, cax[3][3], crkky;
+  double ecub;  // -2 / (mu0 Ms): turns the cubic energy density into the -m.H/2 sum
+  int rkz0, rkz1;
   unsigned terms;
   const double* Trep;
   const uint64_t* seeds;
@@ -413,7 +420,30 @@ __device__ inline void ld3(const T* __restrict__ mr, unsigned N, unsigned cell, 
 // with periodic wrap or free-edge ghosts m_edge -/+ D_a (D/2A)(z x n) x m at
 // open x/y edges (Neumann along z), uniaxial anisotropy and Zeeman field of
 // the cell at (x, y, z) with magnetisation mc; neighbours read from m.
+// Cubic anisotropy field (added to Han) and energy density at mc.
 template <typename T>
+__device__ inline void cubic_terms(const FArgs<T>& a, const T mc[3], T Hc[3], T& dens) {
+  T mi[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    mi[i] = mc[0] * a.cax[i][0] + mc[1] * a.cax[i][1] + mc[2] * a.cax[i][2];
+  const T s0 = mi[0] * mi[0], s1 = mi[1] * mi[1], s2 = mi[2] * mi[2];
+  const T g[3] = {a.kc1h * mi[0] * (s1 + s2) + a.kc2h * mi[0] * s1 * s2,
+                  a.kc1h * mi[1] * (s0 + s2) + a.kc2h * mi[1] * s0 * s2,
+                  a.kc1h * mi[2] * (s0 + s1) + a.kc2h * mi[2] * s0 * s1};
+#pragma unroll
+  for (int c = 0; c < 3; ++c) Hc[c] = -(g[0] * a.cax[0][c] + g[1] * a.cax[1][c] + g[2] * a.cax[2][c]);
+  dens = a.kc1 * (s0 * s1 + s1 * s2 + s2 * s0) + a.kc2 * s0 * s1 * s2;
+}
+
+// Exchange (six-point Laplacian), interfacial DMI (central differences), both
+// with periodic wrap or free-edge ghosts m_edge -/+ D_a g at open edges, g =
+// (D/2A)(z x n) x m (x and y) + (Db/2A) e_a x m (every axis; Neumann when both
+// vanish), uniaxial anisotropy and Zeeman field of the cell at (x, y, z) with
+// magnetisation mc; neighbours read from m.  EXT adds bulk DMI (into Hdm),
+// cubic anisotropy (into Han) and RKKY (into Hex); kernels that never see
+// those terms instantiate it without.
+template <typename T, bool EXT = true>
 __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, unsigned cell,
                                    int x, int y, int z, const T mc[3], T kbc, T Hex[3],
                                    T Hdm[3], T Han[3], T Hz[3]) {
@@ -422,22 +452,35 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, 
   const int coord[3] = {x, y, z};
   const unsigned stride[3] = {1u, (unsigned)a.nx, (unsigned)(a.nx * a.ny)};
   const unsigned N = (unsigned)a.N;
+  const bool bulk = EXT && (a.terms & T_DMI_BULK);
+  const T kbb = EXT ? a.kbb : T(0);
+  T curl[3] = {0, 0, 0};
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
     if (a.nax[ax] == 1) continue;
     const int n = a.nax[ax];
     T mm[3], mp[3];
-    // edge-condition derivative (D/2A)(z x n) x m, applied on x and y only
+    // ghost offset D_a x (edge-condition derivative): (D/2A)(z x n) x m on
+    // x and y, plus (Db/2A) e_ax x m
     T ev[3] = {0, 0, 0};
     if (ax == 0) { ev[0] = mc[2]; ev[2] = -mc[0]; }
     if (ax == 1) { ev[1] = mc[2]; ev[2] = -mc[1]; }
     const T g = (ax < 2) ? a.hd[ax] * kbc : T(0);
+    T gv[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) gv[c] = g * ev[c];
+    if (EXT && kbb != T(0)) {
+      const T gb = a.hd[ax] * kbb;
+      if (ax == 0) { gv[1] -= gb * mc[2]; gv[2] += gb * mc[1]; }
+      if (ax == 1) { gv[0] += gb * mc[2]; gv[2] -= gb * mc[0]; }
+      if (ax == 2) { gv[0] -= gb * mc[1]; gv[1] += gb * mc[0]; }
+    }
     if (coord[ax] > 0) ld3(mr, N, cell - stride[ax], mm);
     else if (a.pbc[ax]) ld3(mr, N, cell + (unsigned)(n - 1) * stride[ax], mm);
-    else { for (int c = 0; c < 3; ++c) mm[c] = mc[c] - g * ev[c]; }
+    else { for (int c = 0; c < 3; ++c) mm[c] = mc[c] - gv[c]; }
     if (coord[ax] < n - 1) ld3(mr, N, cell + stride[ax], mp);
     else if (a.pbc[ax]) ld3(mr, N, cell - (unsigned)(n - 1) * stride[ax], mp);
-    else { for (int c = 0; c < 3; ++c) mp[c] = mc[c] + g * ev[c]; }
+    else { for (int c = 0; c < 3; ++c) mp[c] = mc[c] + gv[c]; }
     if (a.terms & T_EXCH) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) Hex[c] += a.cex * a.idd2[ax] * (mm[c] + mp[c] - T(2) * mc[c]);
@@ -448,11 +491,36 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, 
       Hdm[ax] += a.cdmi * d_z;
       Hdm[2] -= a.cdmi * d_ax;
     }
+    if (bulk) {
+      T d[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) d[c] = (mp[c] - mm[c]) * a.ih2[ax];
+      if (ax == 0) { curl[1] -= d[2]; curl[2] += d[1]; }
+      if (ax == 1) { curl[0] += d[2]; curl[2] -= d[0]; }
+      if (ax == 2) { curl[0] -= d[1]; curl[1] += d[0]; }
+    }
+  }
+  if (bulk) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Hdm[c] += a.cbulk * curl[c];
   }
   if (a.terms & T_ANIS) {
     const T mu = mc[0] * a.u[0] + mc[1] * a.u[1] + mc[2] * a.u[2];
 #pragma unroll
     for (int c = 0; c < 3; ++c) Han[c] = a.can * mu * a.u[c];
+  }
+  if (EXT && (a.terms & T_CUBIC)) {
+    T Hc[3], dens;
+    cubic_terms(a, mc, Hc, dens);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Han[c] += Hc[c];
+  }
+  if (EXT && (a.terms & T_RKKY) && (z == a.rkz0 || z == a.rkz1)) {
+    const int zp = (z == a.rkz0) ? a.rkz1 : a.rkz0;
+    T mo[3];
+    ld3(mr, N, (unsigned)((int)cell + (zp - z) * (int)stride[2]), mo);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) Hex[c] += a.crkky * mo[c];
   }
   if (a.terms & T_ZEEMAN) { Hz[0] = a.hz[0]; Hz[1] = a.hz[1]; Hz[2] = a.hz[2]; }
 }
@@ -722,6 +790,12 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       acc[1] += (double)(mc[0] * Hdm[0] + mc[1] * Hdm[1] + mc[2] * Hdm[2]);
       acc[2] += (double)(mc[0] * Hdd[0] + mc[1] * Hdd[1] + mc[2] * Hdd[2]);
       acc[3] += (double)(mc[0] * Han[0] + mc[1] * Han[1] + mc[2] * Han[2]);
+      if (a.terms & T_CUBIC) {
+        // the quartic cubic term enters by its energy density, not -m.H/2
+        T Hc[3], dens;
+        cubic_terms(a, mc, Hc, dens);
+        acc[3] += a.ecub * (double)dens - (double)(mc[0] * Hc[0] + mc[1] * Hc[1] + mc[2] * Hc[2]);
+      }
       acc[4] += (double)(mc[0] * Hz[0] + mc[1] * Hz[1] + mc[2] * Hz[2]);
       continue;
     }

@@ -141,6 +141,7 @@ struct Group {
   DevBuf tw_x, wpost, tw_y, tw_z, Nt, S, ms, m7, k[7], Trep, seeds, partial, E;
   DevBuf tgen, tstart, tflag, S_init;  // retire/refill trials
   DevBuf Jrep;  // spin-transfer current density per replica (A/m^2)
+  mmx_material_ext ext{};  // bulk DMI, cubic anisotropy, RKKY
   double stt_p[3] = {0, 0, 1}, stt_P = 0, stt_lambda = 1, stt_eps2 = 0;
   int nblk = 1;       // k_fields workgroups per replica
   int nblk_last = 1;  // workgroups per replica of the last field-kernel launch
@@ -432,6 +433,22 @@ struct Epilogue {
   int fwd = 0;  // Heun modes: also write the half spectrum of the new state
 };
 
+// orthonormal cubic axes from c1 and c2 (c2 orthogonalised against c1)
+bool cubic_axes(const mmx_material_ext& e, double c1[3], double c2[3], double c3[3]) {
+  double n1 = std::sqrt(e.c1[0] * e.c1[0] + e.c1[1] * e.c1[1] + e.c1[2] * e.c1[2]);
+  if (!(n1 > 0)) { c1[0] = 1; c1[1] = 0; c1[2] = 0; n1 = 1; }
+  else for (int c = 0; c < 3; ++c) c1[c] = e.c1[c] / n1;
+  const double d = e.c2[0] * c1[0] + e.c2[1] * c1[1] + e.c2[2] * c1[2];
+  for (int c = 0; c < 3; ++c) c2[c] = e.c2[c] - d * c1[c];
+  const double n2 = std::sqrt(c2[0] * c2[0] + c2[1] * c2[1] + c2[2] * c2[2]);
+  if (!(n2 > 1e-12)) return false;
+  for (int c = 0; c < 3; ++c) c2[c] /= n2;
+  c3[0] = c1[1] * c2[2] - c1[2] * c2[1];
+  c3[1] = c1[2] * c2[0] - c1[0] * c2[2];
+  c3[2] = c1[0] * c2[1] - c1[1] * c2[0];
+  return true;
+}
+
 template <typename T>
 FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   FArgs<T> a{};
@@ -461,7 +478,29 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   unsigned t = terms;
   if (G.mat.Ku == 0) t &= ~T_ANIS;
   if (G.mat.D == 0) t &= ~T_DMI;
+  if (G.ext.Db == 0) t &= ~T_DMI_BULK;
+  if (G.ext.Kc1 == 0 && G.ext.Kc2 == 0) t &= ~T_CUBIC;
+  if (G.ext.rkky == 0 || G.nz < 2) t &= ~T_RKKY;
   a.terms = t;
+  a.cbulk = (T)(-2.0 * G.ext.Db / mu0Ms);
+  a.kbb = (T)(G.mat.A != 0 ? G.ext.Db / (2.0 * G.mat.A) : 0.0);
+  a.kc1h = (T)(2.0 * G.ext.Kc1 / mu0Ms);
+  a.kc2h = (T)(2.0 * G.ext.Kc2 / mu0Ms);
+  a.kc1 = (T)G.ext.Kc1;
+  a.kc2 = (T)G.ext.Kc2;
+  a.ecub = -2.0 / mu0Ms;
+  {
+    double c1[3], c2[3], c3[3];
+    cubic_axes(G.ext, c1, c2, c3);
+    for (int c = 0; c < 3; ++c) {
+      a.cax[0][c] = (T)c1[c];
+      a.cax[1][c] = (T)c2[c];
+      a.cax[2][c] = (T)c3[c];
+    }
+  }
+  a.crkky = (T)(G.ext.rkky / (mu0Ms * G.g.cell[2]));
+  a.rkz0 = G.ext.rkky_z[0];
+  a.rkz1 = G.ext.rkky_z[1];
   const double V = G.g.cell[0] * G.g.cell[1] * G.g.cell[2];
   a.Trep = G.Trep.as<double>();
   a.seeds = G.seeds.as<uint64_t>();
@@ -502,6 +541,9 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
     if (!(mode == FM_HEUN1 || mode == FM_HEUN2 || mode == -1) || !(a.terms & T_DEMAG)) return false;
     if (mode != -1 && !a.fwd) return false;
     if (G.xone || a.hext || a.hd_out) return false;
+    // the register row kernels take neither the further field terms nor the
+    // bulk-DMI edge ghosts
+    if ((a.terms & (T_DMI_BULK | T_CUBIC | T_RKKY)) || a.kbb != 0) return false;
     hipStream_t s = ctx->stream;
     // variants: [stage][rotation][spin-transfer]
     using RowKernel = void (*)(FArgs<float>);
@@ -1121,9 +1163,12 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       const FusedTiles ft = fused_tiles<T>(ctx, G);
       if (ctx->path == MMX_PATH_FUSED && !ft.ok)
         return fail(MMX_EUNSUP, "group does not fit the replica-resident path");
-      const bool stt = (ctx->terms & MMX_STT) && G.Jrep.p && G.stt_P != 0;
+      const bool stt = ((ctx->terms & MMX_STT) && G.Jrep.p && G.stt_P != 0) ||
+                       G.ext.Db != 0 || ((ctx->terms & MMX_ANIS_CUBIC) && (G.ext.Kc1 != 0 || G.ext.Kc2 != 0)) ||
+                       ((ctx->terms & MMX_RKKY) && G.ext.rkky != 0);
       if (stt && ctx->path == MMX_PATH_FUSED)
-        return fail(MMX_EUNSUP, "the spin-transfer torque runs on the staged path only");
+        return fail(MMX_EUNSUP, "the spin-transfer torque and further field terms run on the "
+                                "staged path only");
       const bool use_fused = !rot && !refill && !stt && ft.ok &&
                              (ctx->path == MMX_PATH_FUSED ||
                               (ctx->path == MMX_PATH_AUTO && G.fused_faster));
@@ -1704,6 +1749,30 @@ mmx_status mmx_set_material(mmx_ctx* ctx, int32_t group, const mmx_material* mat
   G.mat = *mat;
   G.mat_set = 1;
   G.demag_built = 0;
+  return MMX_OK;
+}
+
+mmx_status mmx_set_material_ext(mmx_ctx* ctx, int32_t group, const mmx_material_ext* ext) {
+  MMX_TRY(check_group_idx(ctx, group));
+  if (!ext) return fail(MMX_EINVAL, "ext is null");
+  Group& G = *ctx->groups[group];
+  if (ext->Db != 0 && G.mat.A == 0) return fail(MMX_EINVAL, "bulk DMI needs A > 0 (edge condition)");
+  if (ext->Kc1 != 0 || ext->Kc2 != 0) {
+    double c1[3], c2[3], c3[3];
+    const double n1 = std::sqrt(ext->c1[0] * ext->c1[0] + ext->c1[1] * ext->c1[1] +
+                                ext->c1[2] * ext->c1[2]);
+    if (!(n1 > 0) || !cubic_axes(*ext, c1, c2, c3))
+      return fail(MMX_EINVAL, "cubic axes must be nonzero and not parallel");
+  }
+  if (ext->rkky != 0) {
+    const int z0 = ext->rkky_z[0], z1 = ext->rkky_z[1];
+    if (z0 == z1 || z0 < 0 || z1 < 0 || z0 >= G.nz || z1 >= G.nz)
+      return fail(MMX_EINVAL, "RKKY layers must be distinct and inside the grid");
+  }
+  if (!std::isfinite(ext->Kc1) || !std::isfinite(ext->Kc2) || !std::isfinite(ext->Db) ||
+      !std::isfinite(ext->rkky))
+    return fail(MMX_EINVAL, "non-finite parameter");
+  G.ext = *ext;
   return MMX_OK;
 }
 

@@ -225,7 +225,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
       T mc[3];
       ld3(mr, N, cell, mc);
       T Hex[3], Hdm[3], Han[3], Hz[3];
-      local_terms(a, mr, cell, x, y, z, mc, a.kbc, Hex, Hdm, Han, Hz);
+      local_terms<T, false>(a, mr, cell, x, y, z, mc, a.kbc, Hex, Hdm, Han, Hz);
       T H[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + Hs[c * 2 * hx + x];
