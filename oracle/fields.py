@@ -4,6 +4,10 @@ All fields are in A/m; ``m`` has shape (3, nz, ny, nx), or (R, 3, nz, ny, nx)
 for a batch of replicas sharing one geometry and material.
 
 * Exchange: six-point Laplacian, H = (2A / mu0 Ms) sum_a (m_{i+a} + m_{i-a} - 2 m_i) / D_a^2.
+  With a per-cell stiffness (Methods lists per-cell materials; reading of the
+  interface): H_i = (2 / mu0 Ms) sum_j A_ij (m_j - m_i) / D_a^2 with the
+  harmonic mean A_ij = 2 A_i A_j / (A_i + A_j) (0 if both vanish); a ghost
+  neighbour takes A_i.  The edge conditions use the edge cell's A_i.
 * Interfacial DMI: energy density D [m_z div m - (m . grad) m_z] (Rohart-Thiaville
   sign as in mumax3), field H = (2D / mu0 Ms)(d_x m_z, d_y m_z, -d_x m_x - d_y m_y)
   with central differences (m_{i+1} - m_{i-1}) / (2 D_a).
@@ -50,9 +54,11 @@ def _comp(m, c):
 def _edge_derivative(mc, axis, D, A, Db=0.0):
     """Boundary-condition derivative d_axis m at an open edge (3, ...):
     interfacial (D/2A)(z x e_a) x m on x and y, bulk (Db/2A) e_a x m on
-    every axis."""
-    k = D / (2.0 * A) if A != 0 else 0.0
-    kb = Db / (2.0 * A) if A != 0 else 0.0
+    every axis; A may be an array of the edge cells' values."""
+    A = np.asarray(A, dtype=np.float64)
+    safe = np.where(A != 0, A, 1.0)
+    k = np.where(A != 0, D / (2.0 * safe), 0.0)
+    kb = np.where(A != 0, Db / (2.0 * safe), 0.0)
     mx, my, mz = _comp(mc, 0), _comp(mc, 1), _comp(mc, 2)
     zero = np.zeros_like(mx)
     if axis == 0:
@@ -61,7 +67,7 @@ def _edge_derivative(mc, axis, D, A, Db=0.0):
         out = k * np.stack([zero, mz, -my], axis=-4)
     else:
         out = np.zeros_like(mc)
-    if kb != 0.0:
+    if np.any(kb != 0.0):
         if axis == 0:    # x x m
             ex = np.stack([zero, -mz, my], axis=-4)
         elif axis == 1:  # y x m
@@ -91,22 +97,58 @@ def neighbours(m, grid, mat, axis):
     m_first = m[first]
     m_last = m[last]
     if use_dmi:
-        mm[first] = m_first - h * _edge_derivative(m_first, axis, mat.D, mat.A, mat.Db)
-        mp[last] = m_last + h * _edge_derivative(m_last, axis, mat.D, mat.A, mat.Db)
+        if mat.A_cells is not None:
+            Ac = np.asarray(mat.A_cells, dtype=np.float64)
+            a_first, a_last = Ac[first[-3:]], Ac[last[-3:]]
+        else:
+            a_first = a_last = mat.A
+        mm[first] = m_first - h * _edge_derivative(m_first, axis, mat.D, a_first, mat.Db)
+        mp[last] = m_last + h * _edge_derivative(m_last, axis, mat.D, a_last, mat.Db)
     else:
         mm[first] = m_first
         mp[last] = m_last
     return mm, mp
 
 
+def _harmonic(a, b):
+    s = a + b
+    return np.where(s > 0, 2.0 * a * b / np.where(s > 0, s, 1.0), 0.0)
+
+
+def _neighbour_A(Ac, grid, axis):
+    """(A at i-1, A at i+1) along ``axis``: periodic wrap, or the cell's own
+    value where the neighbour is a ghost."""
+    ax = _NP_AXIS[axis]
+    am, ap = np.roll(Ac, 1, axis=ax), np.roll(Ac, -1, axis=ax)
+    if not grid.pbc[axis]:
+        n = grid.n[axis]
+        first = [slice(None)] * 3
+        last = [slice(None)] * 3
+        first[3 + ax] = slice(0, 1)
+        last[3 + ax] = slice(n - 1, n)
+        am[tuple(first)] = Ac[tuple(first)]
+        ap[tuple(last)] = Ac[tuple(last)]
+    return am, ap
+
+
 def exchange_field(m, grid, mat):
-    pref = 2.0 * mat.A / (MU0 * mat.Ms)
     H = np.zeros_like(m)
+    if mat.A_cells is None:
+        pref = 2.0 * mat.A / (MU0 * mat.Ms)
+        for axis in range(3):
+            if grid.n[axis] == 1:
+                continue
+            mm, mp = neighbours(m, grid, mat, axis)
+            H += pref * (mm + mp - 2.0 * m) / grid.cell[axis] ** 2
+        return H
+    Ac = np.asarray(mat.A_cells, dtype=np.float64)
     for axis in range(3):
         if grid.n[axis] == 1:
             continue
         mm, mp = neighbours(m, grid, mat, axis)
-        H += pref * (mm + mp - 2.0 * m) / grid.cell[axis] ** 2
+        am, ap = _neighbour_A(Ac, grid, axis)
+        wm, wp = _harmonic(Ac, am), _harmonic(Ac, ap)
+        H += 2.0 / (MU0 * mat.Ms) * (wm * (mm - m) + wp * (mp - m)) / grid.cell[axis] ** 2
     return H
 
 

@@ -71,6 +71,10 @@ class Material:
     # cell layers z0 and z1
     rkky: float = 0.0
     rkky_z: tuple = (0, 1)
+    # per-cell exchange stiffness (array (nz, ny, nx), J/m) or None: replaces A
+    # in the exchange term (harmonic mean per neighbour pair) and in the edge
+    # conditions (the edge cell's value)
+    A_cells: object = None
 
     @property
     def stt(self) -> bool:

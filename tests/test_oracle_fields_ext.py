@@ -2,8 +2,10 @@
 discretization": bulk DMI, cubic anisotropy, RKKY interlayer exchange): the
 field is the energy gradient on periodic grids with every term on, the exact
 discrete field and energy of a bulk-DMI helix (handedness), the bulk-DMI free
-edge condition, cubic easy axes and the [111] energy, and the RKKY energy of
-parallel and antiparallel layers."""
+edge condition, cubic easy axes and the [111] energy, the RKKY energy of
+parallel and antiparallel layers, and a per-cell exchange stiffness (uniform
+values reduce to the scalar, the two-cell harmonic-mean coupling, the energy
+gradient with a zero-stiffness cell)."""
 import math
 
 import numpy as np
@@ -109,3 +111,44 @@ def test_rkky_parallel_and_antiparallel_layers():
     H = fl.rkky_field(m, grid, mat)
     assert np.allclose(H[:, 1], sigma / (MU0 * mat.Ms * grid.cell[2]) * m[:, 2])
     assert not np.any(H[:, 0]) and not np.any(H[:, 3])
+
+
+def test_per_cell_exchange_reduces_to_uniform_and_two_cell_closed_form():
+    import dataclasses
+    grid = Grid((5, 4, 3), (2e-9, 3e-9, 1e-9))
+    mat = Material(Ms=6e5, A=1.1e-11, D=2e-3, Db=1e-3, demag=False)
+    m = random_unit(grid.n, seed=29)
+    ref = fl.effective_field(m, grid, mat)
+    same = dataclasses.replace(mat, A_cells=np.full((3, 4, 5), 1.1e-11))
+    assert np.abs(fl.effective_field(m, grid, same) - ref).max() <= 1e-15 * np.abs(ref).max()
+    # two cells along x with A1, A2: harmonic-mean coupling
+    g2 = Grid((2, 1, 1), (2e-9, 2e-9, 2e-9))
+    A1, A2 = 1e-11, 3e-11
+    m2 = random_unit(g2.n, seed=30)
+    two = Material(Ms=8e5, A=0.0, A_cells=np.array([[[A1, A2]]]), demag=False)
+    H = fl.exchange_field(m2, g2, two)
+    w = 2 * A1 * A2 / (A1 + A2)
+    ref0 = 2 * w / (MU0 * two.Ms) * (m2[:, 0, 0, 1] - m2[:, 0, 0, 0]) / g2.cell[0] ** 2
+    assert np.allclose(H[:, 0, 0, 0], ref0, rtol=1e-14)
+    assert np.allclose(H[:, 0, 0, 1], -ref0, rtol=1e-14)
+
+
+def test_per_cell_exchange_is_energy_gradient():
+    import dataclasses
+    grid = Grid((4, 3, 3), (3e-9, 2e-9, 2e-9), pbc=(1, 1, 1), images=(1, 1, 1))
+    rng = np.random.default_rng(31)
+    Ac = rng.uniform(0.2e-11, 2e-11, (3, 3, 4))
+    Ac[1, 1, 2] = 0.0  # a non-magnetic-like link: zero coupling to this cell
+    mat = Material(Ms=6e5, A=1e-11, A_cells=Ac, D=1e-3, Db=5e-4, Ku=2e5, demag=False)
+    m = random_unit(grid.n, seed=32)
+    H = fl.effective_field(m, grid, mat)
+    pref = 1.0 / (MU0 * mat.Ms * grid.volume)
+    flat = m.reshape(-1)
+    for idx in rng.choice(flat.size, 16, replace=False):
+        h = 1e-3
+        mp = flat.copy(); mp[idx] += h
+        mm = flat.copy(); mm[idx] -= h
+        Ep = observables.energies(mp.reshape(m.shape), grid, mat)["total"]
+        Em = observables.energies(mm.reshape(m.shape), grid, mat)["total"]
+        assert -(Ep - Em) / (2 * h) * pref == pytest.approx(H.reshape(-1)[idx], rel=1e-6,
+                                                            abs=1e-6 * np.abs(H).max())
