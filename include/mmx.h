@@ -161,6 +161,17 @@ mmx_status mmx_build_demag(mmx_ctx* ctx);
  * layers that are equal or out of range. */
 mmx_status mmx_set_material_ext(mmx_ctx* ctx, int32_t group, const mmx_material_ext* ext);
 
+/* Per-cell exchange stiffness of group `group` (Methods, per-cell materials):
+ * A (host double[N], J/m, x-fastest like one component of m; copied) replaces
+ * the material's A in the exchange term, with the pair coupling given by the
+ * harmonic mean 2 A_i A_j / (A_i + A_j) (0 if both vanish), H_i = (2 / mu0 Ms)
+ * sum_j A_ij (m_j - m_i) / d^2, a ghost neighbour taking A_i; the edge
+ * conditions use D / 2A_i and Db / 2A_i (0 where A_i = 0).  A = null goes
+ * back to the uniform A.  Field kernels of the staged path only (like
+ * mmx_set_material_ext).  Synchronous.  MMX_EINVAL for a negative or
+ * non-finite value. */
+mmx_status mmx_set_exchange_cells(mmx_ctx* ctx, int32_t group, const double* A);
+
 /* Slonczewski spin-transfer torque of group `group` (Methods, "Physics and
  * discretization": spin torques added per integrator stage; Results, the
  * replica-batched STT switching sweep with a current density per replica).

@@ -98,6 +98,7 @@ _SIGS = {
                     ctypes.c_double],
     "mmx_rk4": [_P, _P, ctypes.c_double, ctypes.c_int64],
     "mmx_set_material_ext": [_P, ctypes.c_int32, _P],
+    "mmx_set_exchange_cells": [_P, ctypes.c_int32, _P],
     "mmx_set_precession": [_P, ctypes.c_int32],
     "mmx_relax": [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P],
     "mmx_depondt_refill": [_P, _P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P,
@@ -241,6 +242,16 @@ def mmx_set_material_ext(ctx, group, Kc1=0.0, Kc2=0.0, c1=(1.0, 0.0, 0.0), c2=(0
                          (ctypes.c_double * 3)(*map(float, c2)), float(Db), float(rkky),
                          (ctypes.c_int32 * 2)(*map(int, rkky_z)))
     _check("mmx_set_material_ext", _lib.mmx_set_material_ext(ctx, int(group), ctypes.byref(e)))
+
+
+def mmx_set_exchange_cells(ctx, group, A) -> None:
+    """A: per-cell stiffness array (nz, ny, nx) or None."""
+    if A is None:
+        _check("mmx_set_exchange_cells", _lib.mmx_set_exchange_cells(ctx, int(group), None))
+        return
+    Aa = np.ascontiguousarray(np.asarray(A, dtype=np.float64).ravel())
+    _check("mmx_set_exchange_cells", _lib.mmx_set_exchange_cells(
+        ctx, int(group), Aa.ctypes.data_as(ctypes.c_void_p)))
 
 
 def mmx_rk4(ctx, m, dt, n_steps) -> None:

@@ -367,6 +367,10 @@ struct FArgs {
   T cbulk, kbb, kc1h, kc2h, kc1, kc2, cax[3][3], crkky;
   double ecub;  // -2 / (mu0 Ms): turns the cubic energy density into the -m.H/2 sum
   int rkz0, rkz1;
+  // per-cell exchange stiffness (null: uniform A): pair coupling by the
+  // harmonic mean, field prefactor 2 / mu0 Ms, edge factors D/2 and Db/2 over A_i
+  const T* Acell;
+  T exs, dhalf, dbhalf;
   unsigned terms;
   const double* Trep;
   const uint64_t* seeds;
@@ -453,7 +457,14 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, 
   const unsigned stride[3] = {1u, (unsigned)a.nx, (unsigned)(a.nx * a.ny)};
   const unsigned N = (unsigned)a.N;
   const bool bulk = EXT && (a.terms & T_DMI_BULK);
-  const T kbb = EXT ? a.kbb : T(0);
+  const T* __restrict__ Ac = EXT ? a.Acell : nullptr;
+  T kbb = EXT ? a.kbb : T(0);
+  T Ai = 0;
+  if (Ac) {  // the cell's own stiffness sets its edge conditions
+    Ai = Ac[cell];
+    kbc = Ai > T(0) ? a.dhalf / Ai : T(0);
+    kbb = Ai > T(0) ? a.dbhalf / Ai : T(0);
+  }
   T curl[3] = {0, 0, 0};
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
@@ -475,15 +486,27 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, 
       if (ax == 1) { gv[0] += gb * mc[2]; gv[2] -= gb * mc[0]; }
       if (ax == 2) { gv[0] -= gb * mc[1]; gv[1] += gb * mc[0]; }
     }
-    if (coord[ax] > 0) ld3(mr, N, cell - stride[ax], mm);
-    else if (a.pbc[ax]) ld3(mr, N, cell + (unsigned)(n - 1) * stride[ax], mm);
+    // neighbour cells (jm, jp); a ghost keeps the cell's own index
+    unsigned jm = cell, jp = cell;
+    if (coord[ax] > 0) { jm = cell - stride[ax]; ld3(mr, N, jm, mm); }
+    else if (a.pbc[ax]) { jm = cell + (unsigned)(n - 1) * stride[ax]; ld3(mr, N, jm, mm); }
     else { for (int c = 0; c < 3; ++c) mm[c] = mc[c] - gv[c]; }
-    if (coord[ax] < n - 1) ld3(mr, N, cell + stride[ax], mp);
-    else if (a.pbc[ax]) ld3(mr, N, cell - (unsigned)(n - 1) * stride[ax], mp);
+    if (coord[ax] < n - 1) { jp = cell + stride[ax]; ld3(mr, N, jp, mp); }
+    else if (a.pbc[ax]) { jp = cell - (unsigned)(n - 1) * stride[ax]; ld3(mr, N, jp, mp); }
     else { for (int c = 0; c < 3; ++c) mp[c] = mc[c] + gv[c]; }
     if (a.terms & T_EXCH) {
+      if (EXT && Ac) {
+        // harmonic mean of the pair's stiffness (a ghost takes the cell's own)
+        const T Am = Ac[jm], Ap = Ac[jp];
+        const T wm = (Ai + Am > T(0)) ? T(2) * Ai * Am / (Ai + Am) : T(0);
+        const T wp = (Ai + Ap > T(0)) ? T(2) * Ai * Ap / (Ai + Ap) : T(0);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) Hex[c] += a.cex * a.idd2[ax] * (mm[c] + mp[c] - T(2) * mc[c]);
+        for (int c = 0; c < 3; ++c)
+          Hex[c] += a.exs * a.idd2[ax] * (wm * (mm[c] - mc[c]) + wp * (mp[c] - mc[c]));
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Hex[c] += a.cex * a.idd2[ax] * (mm[c] + mp[c] - T(2) * mc[c]);
+      }
     }
     if ((a.terms & T_DMI) && ax < 2) {
       const T d_ax = (mp[ax] - mm[ax]) * a.ih2[ax];

@@ -142,6 +142,7 @@ struct Group {
   DevBuf tgen, tstart, tflag, S_init;  // retire/refill trials
   DevBuf Jrep;  // spin-transfer current density per replica (A/m^2)
   mmx_material_ext ext{};  // bulk DMI, cubic anisotropy, RKKY
+  DevBuf Acell;            // per-cell exchange stiffness (T[N]) or empty
   double stt_p[3] = {0, 0, 1}, stt_P = 0, stt_lambda = 1, stt_eps2 = 0;
   int nblk = 1;       // k_fields workgroups per replica
   int nblk_last = 1;  // workgroups per replica of the last field-kernel launch
@@ -501,6 +502,10 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   a.crkky = (T)(G.ext.rkky / (mu0Ms * G.g.cell[2]));
   a.rkz0 = G.ext.rkky_z[0];
   a.rkz1 = G.ext.rkky_z[1];
+  a.Acell = G.Acell.p ? G.Acell.as<T>() : nullptr;
+  a.exs = (T)(2.0 / mu0Ms);
+  a.dhalf = (T)(0.5 * G.mat.D);
+  a.dbhalf = (T)(0.5 * G.ext.Db);
   const double V = G.g.cell[0] * G.g.cell[1] * G.g.cell[2];
   a.Trep = G.Trep.as<double>();
   a.seeds = G.seeds.as<uint64_t>();
@@ -543,7 +548,7 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
     if (G.xone || a.hext || a.hd_out) return false;
     // the register row kernels take neither the further field terms nor the
     // bulk-DMI edge ghosts
-    if ((a.terms & (T_DMI_BULK | T_CUBIC | T_RKKY)) || a.kbb != 0) return false;
+    if ((a.terms & (T_DMI_BULK | T_CUBIC | T_RKKY)) || a.kbb != 0 || a.Acell) return false;
     hipStream_t s = ctx->stream;
     // variants: [stage][rotation][spin-transfer]
     using RowKernel = void (*)(FArgs<float>);
@@ -1165,7 +1170,7 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
         return fail(MMX_EUNSUP, "group does not fit the replica-resident path");
       const bool stt = ((ctx->terms & MMX_STT) && G.Jrep.p && G.stt_P != 0) ||
                        G.ext.Db != 0 || ((ctx->terms & MMX_ANIS_CUBIC) && (G.ext.Kc1 != 0 || G.ext.Kc2 != 0)) ||
-                       ((ctx->terms & MMX_RKKY) && G.ext.rkky != 0);
+                       ((ctx->terms & MMX_RKKY) && G.ext.rkky != 0) || G.Acell.p;
       if (stt && ctx->path == MMX_PATH_FUSED)
         return fail(MMX_EUNSUP, "the spin-transfer torque and further field terms run on the "
                                 "staged path only");
@@ -1773,6 +1778,28 @@ mmx_status mmx_set_material_ext(mmx_ctx* ctx, int32_t group, const mmx_material_
       !std::isfinite(ext->rkky))
     return fail(MMX_EINVAL, "non-finite parameter");
   G.ext = *ext;
+  return MMX_OK;
+}
+
+mmx_status mmx_set_exchange_cells(mmx_ctx* ctx, int32_t group, const double* A) {
+  MMX_TRY(check_group_idx(ctx, group));
+  Group& G = *ctx->groups[group];
+  if (!A) {
+    HIP_TRY(G.Acell.alloc(0));
+    return MMX_OK;
+  }
+  for (int i = 0; i < G.N; ++i)
+    if (!(A[i] >= 0) || !std::isfinite(A[i]))
+      return fail(MMX_EINVAL, "per-cell stiffness must be finite and >= 0");
+  const size_t es = esize(ctx);
+  std::vector<unsigned char> buf((size_t)G.N * es);
+  for (int i = 0; i < G.N; ++i) {
+    if (es == 8) reinterpret_cast<double*>(buf.data())[i] = A[i];
+    else reinterpret_cast<float*>(buf.data())[i] = (float)A[i];
+  }
+  HIP_TRY(G.Acell.ensure(buf.size()));
+  HIP_TRY(hipMemcpyAsync(G.Acell.p, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
   return MMX_OK;
 }
 

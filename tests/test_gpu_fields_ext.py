@@ -119,3 +119,45 @@ def test_rk45_block_with_rkky_fp64():
     rep = oit.rk45_run(m0[0], case.grid, _mat(case, -3e-4, (0, 3)), 0.0, t_end, tol, dt_replay=dts)
     assert st.t == t_end
     assert np.abs(got[0] - rep.m).max() <= 1e-12
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_per_cell_exchange_fields_and_steps(prec):
+    """Per-cell stiffness (two regions and a zero-stiffness cell) with
+    interfacial and bulk DMI edges: fields, energies and Heun steps."""
+    import paper_2608_15253_amd as mmx
+    R = 2
+    case = Case((12, 10, 3), (3e-9, 3e-9, 2e-9), R=R, Ms=6e5, A=1.3e-11, D=1.5e-3, alpha=0.2,
+                Ku=2e5, B=(0, 0, 0.05), T=200.0, seeds=list(replica_seeds(54, R)),
+                terms=("exchange", "dmi", "anisotropy", "zeeman", "demag", "thermal"))
+    Ac = np.full((3, 10, 12), 1.3e-11)
+    Ac[:, :, 6:] = 0.4e-11
+    Ac[1, 4, 3] = 0.0
+    ext = dict(EXT, Kc1=0.0, Kc2=0.0)
+    m0 = _round(random_unit(case.n, seed=55, replicas=R), prec)
+    ctx = open_ctx(case, prec)
+    try:
+        _setup(ctx, case, ext=ext)
+        mmx.mmx_set_exchange_cells(ctx, 0, Ac)
+        full = case.mask() | mmx.MMX_DMI_BULK | mmx.MMX_ANIS_CUBIC | mmx.MMX_RKKY
+        mmx.mmx_set_terms(ctx, full & ~mmx.MMX_THERMAL)  # fields without the noise
+        H = dev(np.zeros_like(m0), prec)
+        mmx.mmx_field(ctx, dev(m0, prec), H)
+        E = dev(np.zeros((R, 6)), 2)
+        mmx.mmx_energy(ctx, dev(m0, prec), E)
+        mmx.mmx_set_terms(ctx, full)
+        md = dev(m0, prec)
+        mmx.mmx_heun(ctx, md, 1e-14, 10, 0)
+        got, gE, gm = host(H), host(E), host(md)
+    finally:
+        mmx.mmx_destroy(ctx)
+    mat = dataclasses.replace(_mat(case, ext=ext), A_cells=Ac)
+    nothermal = dataclasses.replace(mat, T=0.0)
+    for r in range(R):
+        ref = ofl.effective_field(m0[r], case.grid, nothermal)
+        assert np.abs(got[r] - ref).max() <= (1e-11 if prec == 2 else 4e-6) * np.abs(ref).max()
+        e = oob.energies(m0[r], case.grid, nothermal)
+        assert abs(gE[r][0] - (e["exchange"] + e["rkky"])) <= \
+            (1e-12 if prec == 2 else 2e-6) * max(abs(v) for v in e.values())
+    ref_m = oit.heun_run(m0, case.grid, mat, 1e-14, 10, seed=np.array(case.seeds))
+    assert np.abs(gm - ref_m).max() <= (1e-12 if prec == 2 else 1e-5)
