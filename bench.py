@@ -486,6 +486,44 @@ def bench_throughput(args):
             "config": {"workload": "field_eval_throughput_rk4"}, "grids": out}
 
 
+def bench_fields_ext(args):
+    """The switching film (1024 replicas of 64x64x1, thermal Heun) with the
+    further field terms on: cubic anisotropy (Kc1 = 2e4 J/m^3 along x, y, z),
+    bulk DMI (Db = 1e-3 J/m^2) and a per-cell exchange stiffness (two halves,
+    1.3e-11 and 0.9e-11 J/m); these run on the field kernels, so the line
+    shows what the general path costs next to the register row kernels."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import replica_seeds, uniform
+    R, dt = args.replicas, 1e-14
+    ctx = setup(R, mmx.MMX_F32, replica_seeds(3, R))
+    mmx.mmx_set_material_ext(ctx, 0, Kc1=2e4, Db=1e-3)
+    A = np.full((1, 64, 64), 1.3e-11)
+    A[:, :, 32:] = 0.9e-11
+    mmx.mmx_set_exchange_cells(ctx, 0, A)
+    mmx.mmx_set_terms(ctx, mmx.MMX_EXCH | mmx.MMX_ANIS_UNIAXIAL | mmx.MMX_ZEEMAN | mmx.MMX_DEMAG |
+                      mmx.MMX_THERMAL | mmx.MMX_ANIS_CUBIC | mmx.MMX_DMI_BULK)
+    m = torch.tensor(uniform((64, 64, 1), replicas=R), dtype=torch.float32,
+                     device="cuda:0").contiguous()
+    mmx.mmx_heun(ctx, m, dt, args.warmup, 0, None)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mmx.mmx_heun(ctx, m, dt, args.steps, args.warmup, None)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    mmx.mmx_profile_enable(ctx, 1)
+    mmx.mmx_heun(ctx, m, dt, args.prof_steps, args.warmup + args.steps, None)
+    prof = mmx.mmx_profile_get(ctx)
+    mmx.mmx_profile_enable(ctx, 0)
+    mmx.mmx_destroy(ctx)
+    return {"metric": "LLG cell-steps/s, switching film with cubic anisotropy, bulk DMI and "
+                      "per-cell exchange", "value": R * 4096 * args.steps / el,
+            "unit": "cell-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": el / args.steps * 1e3, "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic", "config": {"workload": "thermal_switching_64x64x1_R1024_ext"},
+            "kernels": {k: {"avg_us": v[0] / v[1] * 1e3, "launches": v[1]} for k, v in prof.items()}}
+
+
 def setup(R, prec, seeds, n=(64, 64, 1)):
     import torch
     import paper_2608_15253_amd as mmx
@@ -547,7 +585,7 @@ def main():
     ap.add_argument("--traffic-cmd", default="", help="command line recorded in the summary")
     ap.add_argument("--workload", default="switching",
                     choices=["switching", "uneven", "closure", "skyrmion512", "depondt", "stt",
-                             "throughput"],
+                             "throughput", "fields_ext"],
                     help="switching: the benchmark line; the others measure the other "
                          "workload configurations (one JSON line each)")
     ap.add_argument("--t-end", type=float, default=None,
@@ -566,7 +604,8 @@ def main():
         print(json.dumps({"uneven": bench_uneven, "closure": bench_closure,
                           "skyrmion512": bench_skyrmion512,
                           "depondt": bench_depondt, "stt": bench_stt,
-                          "throughput": bench_throughput}[args.workload](args)))
+                          "throughput": bench_throughput,
+                          "fields_ext": bench_fields_ext}[args.workload](args)))
         return
     import torch
     import paper_2608_15253_amd as mmx

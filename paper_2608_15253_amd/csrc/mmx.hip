@@ -210,6 +210,8 @@ struct ProfScope {
     a = p->ev();
     (void)hipEventRecord(a, s);
   }
+  // the launch did not happen here (another scope records it)
+  void cancel() { id = -1; }
   ~ProfScope() {
     if (id < 0) return;
     hipEvent_t b = p->ev();
@@ -595,6 +597,7 @@ mmx_status launch_fields(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
       HIP_TRY(hipGetLastError());
       return MMX_OK;
     }
+    ps.cancel();
   }
   G.nblk_last = G.nblk;
   dim3 grid((G.ny + G.L - 1) / G.L, G.nz, G.R);
