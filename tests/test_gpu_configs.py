@@ -16,7 +16,7 @@ from oracle import Grid, Material
 from oracle import fields as ofl
 from oracle import integrators as oit
 from oracle import observables as oob
-from workloads import landau_seed, neel_skyrmions, random_unit, uniform
+from workloads import landau_seed, neel_skyrmions, random_unit, replica_seeds, uniform
 from workloads import relax_film_fp64, skyrmion_film_fp32
 
 from _mmx_case import Case, dev, host, open_ctx
@@ -190,3 +190,68 @@ def test_block_relaxation_3d_against_oracle(prec):
             assert np.abs(got[0] - own.m).max() <= 1e-5
     rep = oit.rk45_run(m0[0], case.grid, case.material(), 0.0, t_end, tol, dt_replay=dts)
     assert np.abs(got[0] - rep.m).max() <= (1e-12 if prec == 2 else 1e-5)
+
+
+def test_thermal_switching_full_batch_sampled_replicas():
+    """The benchmark's configuration (1024 replicas of the 64x64x1 film,
+    FP32, autotuned tiles, 100 Heun steps through the captured-graph path):
+    sampled replicas against the oracle run one by one (FP32 bar)."""
+    import paper_2608_15253_amd as mmx
+    from workloads import thermal_switching_batch
+    w = thermal_switching_batch(1024)
+    R = w.replicas
+    seeds = replica_seeds(w.extra["seed_base"], R)
+    case = Case(w.n, w.cell, R=R, Ms=w.Ms, A=w.A, alpha=w.alpha, Ku=w.Ku, B=w.B, T=w.T,
+                seeds=list(seeds), terms=("exchange", "anisotropy", "zeeman", "demag", "thermal"))
+    m0 = uniform(w.n, (0, 0, 1), replicas=R)
+    dt, steps = w.extra["dt"], 100
+    ctx = open_ctx(case, 1)
+    try:
+        mmx.mmx_autotune(ctx)
+        md = dev(m0, 1)
+        mmx.mmx_heun(ctx, md, dt, steps, 0)
+        got = host(md)
+    finally:
+        mmx.mmx_destroy(ctx)
+    mat = case.material()
+    for r in (0, 511, 1023):
+        ref = oit.heun_run(m0[r], case.grid, mat, dt, steps, seed=int(seeds[r]))
+        err = np.abs(got[r] - ref).max()
+        print(f"[case] switching batch replica {r}: max |dm| {err:.2e}, "
+              f"moved {np.abs(ref - m0[r]).max():.2e}")
+        assert err <= 1e-5
+
+
+def test_uneven_groups_full_size_sampled_replicas():
+    """The uneven-groups configuration at full size (256 replicas each of
+    32x32x1, 128x32x1, 96x96x2 and 256x64x1 in one context, FP32, autotuned,
+    70 Heun steps through the graph path): one sampled replica per group
+    against the oracle."""
+    import paper_2608_15253_amd as mmx
+    from workloads import uneven_groups
+    ws = uneven_groups(256)
+    cases = []
+    for w in ws:
+        seeds = replica_seeds(w.extra["seed_base"], w.replicas)
+        cases.append(Case(w.n, w.cell, R=w.replicas, Ms=w.Ms, A=w.A, alpha=w.alpha, Ku=w.Ku,
+                          D=w.D, B=w.B, T=w.T, seeds=list(seeds),
+                          terms=("exchange", "dmi", "anisotropy", "zeeman", "demag", "thermal")))
+    m0 = [uniform(c.n, (0, 0, 1), replicas=c.R) for c in cases]
+    dt, steps = ws[0].extra["dt"], 70
+    ctx = open_ctx(cases[0], 1, groups=cases)
+    try:
+        mmx.mmx_autotune(ctx)
+        md = dev(np.concatenate([m.ravel() for m in m0]), 1)
+        mmx.mmx_heun(ctx, md, dt, steps, 0)
+        flat = host(md)
+    finally:
+        mmx.mmx_destroy(ctx)
+    off = 0
+    for c, m in zip(cases, m0):
+        got = flat[off:off + m.size].reshape(m.shape)
+        off += m.size
+        r = c.R // 2
+        ref = oit.heun_run(m[r], c.grid, c.material(), dt, steps, seed=int(c.seeds[r]))
+        err = np.abs(got[r] - ref).max()
+        print(f"[case] uneven group {c.n}: replica {r} max |dm| {err:.2e}")
+        assert err <= 1e-5
