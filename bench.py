@@ -51,12 +51,14 @@ def algorithmic_bytes(kernel: str, R: int, nx: int, ny: int, w: int) -> float | 
     spec = 3 * ny * (nx + 1) * 2 * w      # half spectrum of one replica
     state = 3 * N * w                      # one magnetisation-sized array
     # the Heun epilogues also write the half spectrum of the state they
-    # produce (the x transform of the next evaluation)
+    # produce (the x transform of the next evaluation); the predictor reads
+    # m and writes the predictor state, the corrector reads the predictor and
+    # m and writes m (no stored slope)
     per = {
         "k_xfwd": state + spec,
         "k_yconv": 2 * spec,
-        "k_fields_heun1": spec + state + 2 * state + spec,
-        "k_fields_heun2": spec + 3 * state + state + spec,
+        "k_fields_heun1": spec + state + state + spec,
+        "k_fields_heun2": spec + 2 * state + state + spec,
     }
     if kernel not in per:
         return None

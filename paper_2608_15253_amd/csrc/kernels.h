@@ -655,10 +655,12 @@ __device__ inline void add_cross(const T m[3], const T t[3], T o[3]) {
   o[2] += m[0] * t[1] - m[1] * t[0];
 }
 
-// Heun-stage epilogues shared by the field kernels.  Predictor: k1 <- slope,
-// m~ = m + dt k (Heun) or k1 <- Omega, m~ = rotation of m by dt Omega.
-// Corrector from the saved state mo and k1: normalised m + dt/2 (k1 + k)
-// (Heun) or the rotation of mo by dt/2 (Omega_1 + Omega_2), not normalised.
+// Heun-stage epilogues shared by the field kernels.  Predictor: m~ = m + dt k
+// (Heun; the slope is not kept) or k1 <- Omega, m~ = rotation of m by
+// dt Omega.  Corrector at m~ (mc) from the saved state mo: Heun's
+// m + dt/2 (k1 + k) written as (mo + m~)/2 + dt/2 k (m~ = mo + dt k1, so no
+// slope has to be stored), normalised; or the rotation of mo by
+// dt/2 (Omega_1 + Omega_2), not normalised.
 // tau: spin-transfer torque at (mc), entering Omega as mc x tau
 template <typename T>
 __device__ inline void heun_predict(const FArgs<T>& a, bool rot, const T mc[3], const T H[3],
@@ -693,7 +695,7 @@ __device__ inline void heun_correct(const FArgs<T>& a, bool rot, const T mc[3], 
   } else {
     T u[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) u[c] = mo[c] + T(0.5) * dt * (k1v[c] + k[c]);
+    for (int c = 0; c < 3; ++c) u[c] = T(0.5) * (mo[c] + mc[c]) + T(0.5) * dt * k[c];
     const T inv = T(1) / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) mn[c] = u[c] * inv;
@@ -848,14 +850,15 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       heun_predict(a, a.rot != 0, mc, H, k, tau, dt, k1v, mn);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        k1_r[c * N + cell] = k1v[c];
+        if (a.rot) k1_r[c * N + cell] = k1v[c];
         mout_r[c * N + cell] = mn[c];
         if (fwd) F[(c * L + l) * 2 * hx + x] = mn[c];
       }
     } else if (MODE == FM_HEUN2) {
       T mo[3], k1v[3];
       ld3(a.m0 + rb, N, cell, mo);
-      ld3(k1_r, N, cell, k1v);
+      if (a.rot) ld3(k1_r, N, cell, k1v);
+      else k1v[0] = k1v[1] = k1v[2] = T(0);
       T mn[3];
       heun_correct(a, a.rot != 0, mc, H, k, tau, mo, k1v, dt, mn);
 #pragma unroll

