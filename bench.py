@@ -417,6 +417,20 @@ def bench_stt(args):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     psw = (tsw.view(npts, per) > 0).double().mean(dim=1).cpu().numpy()
+    # retire/refill over the same steps: every switched trial restarts, so
+    # each slot reports its number of finished trials
+    cap = 16
+    times = torch.empty(R * cap, dtype=torch.float64, device="cuda:0")
+    counts = torch.zeros(R, dtype=torch.int32, device="cuda:0")
+    mr = torch.zeros((R, 3), dtype=torch.float32, device="cuda:0")
+    mr[:, 2] = 1.0
+    m_init = mr.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mmx.mmx_depondt_refill(ctx, mr, m_init, dt, steps, times, cap, counts)
+    torch.cuda.synchronize()
+    el_r = time.perf_counter() - t0
+    trials = counts.view(npts, per).double().mean(dim=1).cpu().numpy()
     mmx.mmx_destroy(ctx)
     # per-trial loop: 32 single-replica contexts, one call per step each
     trials, tsteps = 32, 200
@@ -445,7 +459,9 @@ def bench_stt(args):
                           "trials": trials, "steps": tsteps},
             "speedup_vs_per_trial": (R * steps / el) / (trials * tsteps / el_t),
             "p_switch": {"J_over_Jc0": [round(float(x), 4) for x in ratios],
-                         "P_sw": [round(float(x), 4) for x in psw]}}
+                         "P_sw": [round(float(x), 4) for x in psw]},
+            "refill": {"value": R * steps / el_r, "unit": "replica-steps/s", "seconds": el_r,
+                       "mean_finished_trials_per_slot": [round(float(x), 3) for x in trials]}}
 
 
 def bench_throughput(args):

@@ -234,8 +234,10 @@ mmx_status mmx_depondt(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64
  * at the next step from its row of m_init (device, D1, not modified) with
  * trial g + 1, whose thermal noise uses counter word 3 = g + 1 and step
  * numbers counted from the trial's start (trial 0 is the noise of
- * mmx_depondt).  Each call starts a fresh set of trials.  MMX_EINVAL for
- * null m, m_init or counts, cap < 0, or null times with cap > 0. */
+ * mmx_depondt).  Each call starts a fresh set of trials.  Single-cell groups
+ * without demag keep the bookkeeping in the replica's thread (as mmx_depondt
+ * does under MMX_PATH_AUTO).  MMX_EINVAL for null m, m_init or counts,
+ * cap < 0, or null times with cap > 0. */
 mmx_status mmx_depondt_refill(mmx_ctx* ctx, void* m, const void* m_init, double dt,
                               int64_t n_steps, uint64_t step0, void* times, int32_t cap,
                               void* counts);

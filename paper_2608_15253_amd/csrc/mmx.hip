@@ -1122,7 +1122,7 @@ struct SchemeScope {
 // registers of one thread (k_macrospin), in launches of at most 8192 steps.
 template <typename T>
 mmx_status heun_macrospin(mmx_ctx* ctx, Group& G, T* mg, double dt, int64_t n_steps,
-                          uint64_t step0, double* tsw, int rot) {
+                          uint64_t step0, double* tsw, int rot, const MacroRefill<T>& mr) {
   FArgs<T> a = field_args<T>(ctx, G, ctx->terms);
   a.dth = dt;
   a.dt_th = dt;
@@ -1132,13 +1132,35 @@ mmx_status heun_macrospin(mmx_ctx* ctx, Group& G, T* mg, double dt, int64_t n_st
     ProfScope ps(ctx->prof, "k_macrospin", ctx->stream);
     if (rot)
       k_macrospin<T, true><<<grid, 256, 0, ctx->stream>>>(a, mg, dt, n, step0 + (uint64_t)done,
-                                                          tsw, G.R);
+                                                          tsw, G.R, mr);
     else
       k_macrospin<T, false><<<grid, 256, 0, ctx->stream>>>(a, mg, dt, n, step0 + (uint64_t)done,
-                                                           tsw, G.R);
+                                                           tsw, G.R, mr);
     HIP_TRY(hipGetLastError());
     done += n;
   }
+  return MMX_OK;
+}
+
+// Trial bookkeeping of a retire/refill call: every replica of the group starts
+// trial 0 at step step0; counts zeroed, times set to -1.
+template <typename T>
+mmx_status refill_begin(mmx_ctx* ctx, Group& G, const RefillArgs& rf, int roff, uint64_t step0) {
+  hipStream_t s = ctx->stream;
+  HIP_TRY(G.tgen.ensure((size_t)G.R * sizeof(int)));
+  HIP_TRY(G.tflag.ensure((size_t)G.R * sizeof(int)));
+  HIP_TRY(G.tstart.ensure((size_t)G.R * sizeof(unsigned long long)));
+  const unsigned nb = (unsigned)((G.R + 255) / 256);
+  k_fill_i32<<<nb, 256, 0, s>>>(G.tgen.as<int>(), G.R, 0);
+  k_fill_i32<<<nb, 256, 0, s>>>(G.tflag.as<int>(), G.R, 0);
+  k_fill_i32<<<nb, 256, 0, s>>>(rf.counts + roff, G.R, 0);
+  k_fill_u64<<<nb, 256, 0, s>>>(G.tstart.as<unsigned long long>(), G.R,
+                                (unsigned long long)step0);
+  const size_t nt = (size_t)G.R * rf.cap;
+  if (nt)
+    k_fill_f64<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(rf.times + (size_t)roff * rf.cap, nt,
+                                                            -1.0);
+  HIP_TRY(hipGetLastError());
   return MMX_OK;
 }
 
@@ -1162,9 +1184,19 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
     int roff = 0;
     for (size_t gi = 0; gi < ctx->groups.size(); ++gi) {
       Group& G = *ctx->groups[gi];
-      if (G.N == 1 && !(ctx->terms & MMX_DEMAG) && !refill && ctx->path != MMX_PATH_STAGED) {
+      if (G.N == 1 && !(ctx->terms & MMX_DEMAG) && ctx->path != MMX_PATH_STAGED) {
+        MacroRefill<T> mr{};
+        if (refill) {
+          MMX_TRY(refill_begin<T>(ctx, G, *rf, roff, step0));
+          mr.m_init = reinterpret_cast<const T*>(rf->m_init) + G.off;
+          mr.tgen = G.tgen.as<int>();
+          mr.tstart = G.tstart.as<unsigned long long>();
+          mr.counts = rf->counts + roff;
+          mr.times = rf->times + (size_t)roff * rf->cap;
+          mr.cap = rf->cap;
+        }
         MMX_TRY(heun_macrospin<T>(ctx, G, mb + G.off, dt, n_steps, step0,
-                                  tsw_d ? tsw_d + roff : nullptr, rot));
+                                  tsw_d ? tsw_d + roff : nullptr, rot, mr));
         roff += G.R;
         continue;
       }
@@ -1277,20 +1309,7 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
     for (int gi : staged) {
       Group& G = *ctx->groups[gi];
       const int roff = roffs[gi];
-      HIP_TRY(G.tgen.ensure((size_t)G.R * sizeof(int)));
-      HIP_TRY(G.tflag.ensure((size_t)G.R * sizeof(int)));
-      HIP_TRY(G.tstart.ensure((size_t)G.R * sizeof(unsigned long long)));
-      const unsigned nb = (unsigned)((G.R + 255) / 256);
-      k_fill_i32<<<nb, 256, 0, s>>>(G.tgen.as<int>(), G.R, 0);
-      k_fill_i32<<<nb, 256, 0, s>>>(G.tflag.as<int>(), G.R, 0);
-      k_fill_i32<<<nb, 256, 0, s>>>(rf->counts + roff, G.R, 0);
-      k_fill_u64<<<nb, 256, 0, s>>>(G.tstart.as<unsigned long long>(), G.R,
-                                    (unsigned long long)step0);
-      const size_t nt = (size_t)G.R * rf->cap;
-      if (nt)
-        k_fill_f64<<<(unsigned)((nt + 255) / 256), 256, 0, s>>>(
-            rf->times + (size_t)roff * rf->cap, nt, -1.0);
-      HIP_TRY(hipGetLastError());
+      MMX_TRY(refill_begin<T>(ctx, G, *rf, roff, step0));
       if (n_steps > 0 && (ctx->terms & MMX_DEMAG)) {
         HIP_TRY(G.S_init.ensure(G.S.bytes));
         MMX_TRY(spectrum_of(G, reinterpret_cast<const T*>(rf->m_init) + G.off));

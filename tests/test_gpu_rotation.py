@@ -184,3 +184,41 @@ def test_refill_fp32_zero_temperature_repeats_the_switching_time():
     assert np.array_equal(got_c, [3, 3])
     assert np.all(got_t[:, :3] == s_star * dt) and np.all(got_t[:, 3:] == -1)
     assert np.array_equal(got_m, five)
+
+
+def test_refill_single_cell_resident_path_fp64():
+    """Retire/refill on single-cell replicas runs in one thread per replica;
+    its trial lengths and counts equal the oracle's (sampled slots) and the
+    staged field-kernel path's."""
+    import paper_2608_15253_amd as mmx
+    import torch
+    R, cap, nsteps, dt = 64, 6, 3000, 1e-13
+    case = Case((1, 1, 1), (4e-9, 4e-9, 4e-9), R=R, A=0.0, alpha=0.2, Ku=2e5, B=(0, 0, -1.0),
+                T=300.0, seeds=list(replica_seeds(33, R)), terms=("anisotropy", "zeeman", "thermal"))
+    th = 0.3
+    m_init = uniform(case.n, (math.sin(th), 0.0, math.cos(th)), replicas=R)
+    out = {}
+    for path in (mmx.MMX_PATH_AUTO, mmx.MMX_PATH_STAGED):
+        ctx = open_ctx(case, 2)
+        try:
+            mmx.mmx_set_path(ctx, path)
+            md = dev(m_init, 2)
+            times = dev(np.zeros(R * cap), 2)
+            counts = torch.zeros(R, dtype=torch.int32, device="cuda:0")
+            mmx.mmx_depondt_refill(ctx, md, dev(m_init, 2), dt, nsteps, times, cap, counts)
+            out[path] = (host(md), host(times).reshape(R, cap), counts.cpu().numpy())
+        finally:
+            mmx.mmx_destroy(ctx)
+    a, b = out[mmx.MMX_PATH_AUTO], out[mmx.MMX_PATH_STAGED]
+    assert np.array_equal(a[2], b[2]) and np.array_equal(a[1], b[1])
+    assert np.abs(a[0] - b[0]).max() <= 1e-12
+    assert a[2].min() >= 2
+    for r in (0, 37):
+        times_r, done, m_r, _, _, margins = orot.refill_slot(m_init[r], case.grid, case.material(),
+                                                              dt, nsteps, case.seeds[r], cap)
+        assert min(abs(x) for x in margins) > 1e-9
+        assert a[2][r] == done
+        ref_t = np.full(cap, -1.0)
+        ref_t[:len(times_r)] = times_r
+        assert np.array_equal(a[1][r], ref_t)
+        assert np.abs(a[0][r] - m_r).max() <= 1e-12
