@@ -231,7 +231,27 @@ struct YArgs {
   FftPlan pf, pi;
   int ny, Py, Kx, W, Ty, Sy, nz, Pz, Tz, z;
   const int* done;
+  // switching check of the previous Heun step, folded into the register
+  // column kernel (sw_tsw null: none): the workgroup of column tile 0 of
+  // each replica sums that replica's corrector partial sums of m_z
+  const double* sw_part;
+  double* sw_tsw;
+  const int* sw_nblk;  // the corrector's workgroups per replica (device)
+  int sw_N;
+  double sw_dt;
+  unsigned long long sw_step;
+  const unsigned long long* sw_stepdev;
 };
+
+// Replica r's switching time: the first t after which the mean m_z (from
+// the corrector's per-workgroup partial sums, summed in a fixed order) is
+// negative.
+__device__ inline void switch_check(const double* part, double* tsw, int nblk, int N, int r,
+                                    double t) {
+  double s = 0;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)r * nblk + b];
+  if (tsw[r] < 0 && s / N < 0) tsw[r] = t;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
@@ -405,6 +425,7 @@ struct FArgs {
   // Slonczewski spin-transfer torque: b_J = stt_c J[r] (A/m), fixed-layer unit
   // vector, polarisation, Lambda^2 and the field-like coefficient eps'
   int noprec;         // damping-only dynamics: the precession term is dropped
+  int* nblk_out;      // Heun corrector: receives its workgroups per replica (partial-sum stride)
   const double* Jrep;
   double stt_c;
   T sttp[3], stt_P, stt_L2, stt_e2;
@@ -917,6 +938,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
         }
       } else {
         for (int v = 0; v < nv; ++v) a.partial[((size_t)r * nblk + blk) * nv + v] = red[v * kBlock];
+        if (MODE == FM_HEUN2 && a.nblk_out && blk == 0 && r == 0) *a.nblk_out = (int)nblk;
       }
     }
   }

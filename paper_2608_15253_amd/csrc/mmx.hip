@@ -143,6 +143,7 @@ struct Group {
   DevBuf Jrep;  // spin-transfer current density per replica (A/m^2)
   mmx_material_ext ext{};  // bulk DMI, cubic anisotropy, RKKY
   DevBuf Acell;            // per-cell exchange stiffness (T[N]) or empty
+  DevBuf nblk_dev;         // int: the last corrector's workgroups per replica
   double stt_p[3] = {0, 0, 1}, stt_P = 0, stt_lambda = 1, stt_eps2 = 0;
   int nblk = 1;       // k_fields workgroups per replica
   int nblk_last = 1;  // workgroups per replica of the last field-kernel launch
@@ -528,6 +529,7 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
     a.terms &= ~(unsigned)T_STT;
   }
   a.noprec = ctx->noprec;
+  a.nblk_out = G.nblk_dev.p ? G.nblk_dev.as<int>() : nullptr;
   a.rot = ctx->rot;
   if (ctx->refill) {
     a.tgen = G.tgen.as<int>();
@@ -678,12 +680,30 @@ mmx_status launch_xfwd(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb
   return MMX_OK;
 }
 
+// Switching check of the previous Heun step, done by the register column
+// kernel of the next step's first field evaluation.
+struct SwitchFold {
+  const double* part = nullptr;
+  double* tsw = nullptr;
+  const int* nblk = nullptr;  // device: written by the corrector
+  int N = 1;
+  double dt = 0;
+  unsigned long long step = 0;
+  const unsigned long long* stepdev = nullptr;
+};
+
+// whether launch_yconv_reg takes the 2-D column pass of group G
+template <typename T>
+bool yconv_reg_applies(const Group& G) {
+  return std::is_same<T, float>::value && !G.is3d && (G.Py == 64 || G.Py == 128 || G.Py == 256);
+}
+
 // m: group-local base pointer of the state used for fields.
 template <typename T>
 mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb, const Epilogue& ep,
                       uint64_t step, double dt_th, const double* dtdev, double dth,
                       const int* done, uint32_t terms_override = 0xFFFFFFFFu,
-                      bool spec_ready = false) {
+                      bool spec_ready = false, const SwitchFold* sw = nullptr) {
   uint32_t terms = (terms_override == 0xFFFFFFFFu) ? ctx->terms : terms_override;
   const bool demag = (terms & MMX_DEMAG) != 0;
   if (demag && !G.demag_built) return fail(MMX_ESTATE, "mmx_build_demag has not been called");
@@ -710,8 +730,18 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
       y.tw = G.tw_y.as<cpx<T>>();
       y.pf = G.plan_yf;
       y.pi = G.plan_yi;
+      if (sw) {
+        y.sw_part = sw->part;
+        y.sw_tsw = sw->tsw;
+        y.sw_nblk = sw->nblk;
+        y.sw_N = sw->N;
+        y.sw_dt = sw->dt;
+        y.sw_step = sw->step;
+        y.sw_stepdev = sw->stepdev;
+      }
       ProfScope ps(ctx->prof, "k_yconv", s);
       if (!launch_yconv_reg<T>(G, y, s)) {
+        if (sw) return fail(MMX_ESTATE, "switching check folded into a column kernel without it");
         dim3 grid((G.Kx + G.Wy - 1) / G.Wy, 1, G.R);
         k_yconv<T><<<grid, kBlock, (2 * (size_t)3 * G.Wy * G.Py + G.Py) * cpxb<T>(), s>>>(y);
       }
@@ -1230,6 +1260,22 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       roff += gp->R;
     }
   }
+  // groups whose switching check is folded into the next step's column
+  // kernel: their partial sums start neutral (positive) so that the first
+  // step's check changes nothing; one reduction follows the last step
+  std::vector<char> folds(ctx->groups.size(), 0);
+  if (tsw_d && !refill && (ctx->terms & MMX_DEMAG) && n_steps > 0) {
+    for (int gi : staged) {
+      Group& G = *ctx->groups[gi];
+      if (!yconv_reg_applies<T>(G)) continue;
+      folds[gi] = 1;
+      HIP_TRY(G.nblk_dev.ensure(sizeof(int)));
+      const size_t np = G.partial.bytes / sizeof(double);
+      k_fill_f64<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(G.partial.as<double>(), np, 1.0);
+      k_fill_i32<<<1, 64, 0, s>>>(G.nblk_dev.as<int>(), 1, 1);
+      HIP_TRY(hipGetLastError());
+    }
+  }
   // one Heun step of every staged group on ctx->stream; with ctx->cur_stepdev
   // set the step index comes from device memory and is advanced in-stream
   auto one_step = [&](uint64_t step) -> mmx_status {
@@ -1246,8 +1292,21 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       e1.k1 = G.k[0].p;
       e1.mout = G.ms.p;
       e1.fwd = 1;
+      // the previous step's switching check rides on this step's first
+      // column kernel (the partial sums are those of the last corrector)
+      SwitchFold sf;
+      const bool fold = tsw_d && !refill && folds[gi];
+      if (fold) {
+        sf.part = G.partial.as<double>();
+        sf.tsw = tsw_d + roff;
+        sf.nblk = G.nblk_dev.as<int>();
+        sf.N = G.N;
+        sf.dt = dt;
+        sf.step = (unsigned long long)step;
+        sf.stepdev = ctx->cur_stepdev;
+      }
       MMX_TRY(eval_group<T>(ctx, G, mg, Combine{}, e1, step, dt, nullptr, dt, nullptr,
-                            0xFFFFFFFFu, true));
+                            0xFFFFFFFFu, true, fold ? &sf : nullptr));
       Epilogue e2;
       e2.mode = FM_HEUN2;
       e2.k1 = G.k[0].p;
@@ -1274,7 +1333,7 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
             ns ? G.S.as<cpx<T>>() : nullptr, ns ? G.S_init.as<cpx<T>>() : nullptr, ns);
         HIP_TRY(hipGetLastError());
       }
-      if (tsw_d) {
+      if (tsw_d && !folds[gi]) {
         ProfScope ps(ctx->prof, "k_switch_reduce", st);
         k_switch_reduce<<<(G.R + 63) / 64, 64, 0, st>>>(G.partial.as<double>(), G.nblk_last, G.R,
                                                          G.N, tsw_d + roff, (double)(step + 1) * dt,
@@ -1366,6 +1425,16 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
     HIP_TRY(hipStreamWaitEvent(user, ctx->ev_cap, 0));
   }
   for (int64_t i = done_steps; i < n_steps; ++i) MMX_TRY(one_step(step0 + (uint64_t)i));
+  for (int gi : staged) {  // the last step's switching check
+    if (!folds[gi]) continue;
+    Group& G = *ctx->groups[gi];
+    ProfScope ps(ctx->prof, "k_switch_reduce", s);
+    k_switch_reduce<<<(G.R + 63) / 64, 64, 0, s>>>(G.partial.as<double>(), G.nblk_last, G.R, G.N,
+                                                   tsw_d + roffs[gi],
+                                                   (double)(step0 + (uint64_t)n_steps) * dt,
+                                                   nullptr, dt);
+    HIP_TRY(hipGetLastError());
+  }
   return MMX_OK;
 }
 

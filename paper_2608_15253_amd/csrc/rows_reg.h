@@ -292,6 +292,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
       const size_t blk = (size_t)by * gridDim.x + bx;
       const size_t nblk = (size_t)gridDim.x * gridDim.y;
       a.partial[(size_t)r * nblk + blk] = red[0];
+      if (a.nblk_out && blk == 0 && r == 0) *a.nblk_out = (int)nblk;
     }
   }
 }

@@ -152,10 +152,7 @@ __global__ void k_switch_reduce(const double* partial, int nblk, int R, int N, d
                                 double t_after, const unsigned long long* stepdev, double dt) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
-  double s = 0;
-  for (int b = 0; b < nblk; ++b) s += partial[(size_t)r * nblk + b];
-  const double t = stepdev ? (double)(*stepdev + 1) * dt : t_after;
-  if (tsw[r] < 0 && s / N < 0) tsw[r] = t;
+  switch_check(partial, tsw, nblk, N, r, stepdev ? (double)(*stepdev + 1) * dt : t_after);
 }
 
 // Retire/refill bookkeeping after a step (one thread per replica): a replica

@@ -345,3 +345,34 @@ def test_heun_resume_is_bitwise(prec):
         mmx.mmx_destroy(ctx)
     assert np.array_equal(full, resumed)
     assert np.array_equal(tfull, tres)
+
+
+def test_folded_switching_check_equals_per_step_check():
+    """FP32 64 x 64 films (register column kernel): the switching check of
+    each step rides on the next step's column kernel, with one reduction
+    after the last step; one call of 200 steps (captured graph replays)
+    equals 200 calls of one step each, states and switching times bit for
+    bit."""
+    import paper_2608_15253_amd as mmx
+    R = 4
+    case = Case((64, 64, 1), (4e-9, 4e-9, 4e-9), R=R, alpha=0.5, Ku=1e5, B=(0, 0, -1.5),
+                T=300.0, seeds=list(replica_seeds(61, R)),
+                terms=("exchange", "anisotropy", "zeeman", "demag", "thermal"))
+    m0 = _round(uniform(case.n, (0.05, 0.0, 1.0), replicas=R), 1)
+    n = 320  # the films switch after about 255 steps
+    ctx = open_ctx(case, 1)
+    try:
+        md = dev(m0, 1)
+        ts = dev(-np.ones(R), 2)
+        mmx.mmx_heun(ctx, md, 1e-13, n, 0, ts)
+        one, tone = host(md), host(ts)
+        md = dev(m0, 1)
+        ts = dev(-np.ones(R), 2)
+        for k in range(n):
+            mmx.mmx_heun(ctx, md, 1e-13, 1, k, ts)
+        split, tsplit = host(md), host(ts)
+    finally:
+        mmx.mmx_destroy(ctx)
+    print(f"switching times {tone}")
+    assert np.all(tone > 0) and np.all(tone < n * 1e-13)
+    assert np.array_equal(one, split) and np.array_equal(tone, tsplit)
