@@ -9,7 +9,7 @@
 //   k_yconv  (2-D) y transform (pruned: rows >= ny are zero), product with the
 //            parity-compressed real symmetric tensor spectrum, inverse y
 //            transform, rows >= ny dropped;
-//   k_yfwd / k_zconv / k_yinv  (3-D) the same split over y and z;
+//   k_ypass / k_zconv(_reg) / k_ypass  (3-D) the same split over y and z;
 //   k_fields complex-to-real inverse x transform (outputs x < nx only) fused
 //            with exchange, interfacial DMI, uniaxial anisotropy, Zeeman and
 //            Brown thermal fields, the LLG torque and the integrator epilogue
@@ -301,26 +301,28 @@ __global__ void __launch_bounds__(kBlock) k_ypass(YArgs<T> a) {
   if (a.done && *a.done) return;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int W = a.W, Py = a.Py, nl = 3 * W;
-  cpx<T>* Bf = A + nl * Py;
-  const cpx<T>* tw = stage_table(Bf + nl * Py, a.tw, Py);
-  const int r = blockIdx.z, z = blockIdx.y, kx0 = blockIdx.x * W;
-  const size_t rbase = (size_t)r * 3;
+  const int W = a.W, Py = a.Py;
+  cpx<T>* Bf = A + W * Py;
+  const cpx<T>* tw = stage_table(Bf + W * Py, a.tw, Py);
+  const int kx0 = blockIdx.x * W;
+  // one (component, z) plane of one replica: no product couples the
+  // components here, so a workgroup takes W columns of a single one (wider
+  // tiles, longer contiguous runs along kx)
+  cpx<T>* __restrict__ P =
+      a.S + ((size_t)blockIdx.z * 3 * a.nz + blockIdx.y) * a.Sy * a.Kx + kx0;
   const int nin = INV ? Py : a.ny;
-  for (int t = threadIdx.x; t < nl * Py; t += blockDim.x) {
-    const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, Py), c = udiv(rest, Py);
+  for (int t = threadIdx.x; t < W * Py; t += blockDim.x) {
+    const int w = umod(t, W), y = udiv(t, W);
     cpx<T> v = {0, 0};
-    if (y < nin && kx0 + w < a.Kx)
-      v = a.S[(((rbase + c) * a.nz + z) * a.Sy + y) * a.Kx + kx0 + w];
-    A[(c * W + w) * Py + y] = v;
+    if (y < nin && kx0 + w < a.Kx) v = P[(size_t)y * a.Kx + w];
+    A[w * Py + y] = v;
   }
   __syncthreads();
-  const cpx<T>* Y = lds_fft<T, INV>(A, Bf, nl, INV ? a.pi : a.pf, tw);
+  const cpx<T>* Y = lds_fft<T, INV>(A, Bf, W, INV ? a.pi : a.pf, tw);
   const int nout = INV ? a.ny : Py;
-  for (int t = threadIdx.x; t < nl * nout; t += blockDim.x) {
-    const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, nout), c = udiv(rest, nout);
-    if (kx0 + w < a.Kx)
-      a.S[(((rbase + c) * a.nz + z) * a.Sy + y) * a.Kx + kx0 + w] = Y[(c * W + w) * Py + y];
+  for (int t = threadIdx.x; t < W * nout; t += blockDim.x) {
+    const int w = umod(t, W), y = udiv(t, W);
+    if (kx0 + w < a.Kx) P[(size_t)y * a.Kx + w] = Y[w * Py + y];
   }
 }
 
@@ -367,6 +369,74 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
     if (kx0 + w < a.Kx)
       a.S[(((rbase + c) * a.nz + z) * a.Sy + ky) * a.Kx + kx0 + w] = Y[(c * W + w) * Pz + z];
   }
+}
+
+// 3-D grids of few layers (nz <= NZ): one thread per (ky, kx) pillar holds
+// its nz planes of all three components in registers and takes the z
+// transform as a direct sum over the nz planes that carry data (the padding
+// planes are zero), the full tensor product per kz, and the inverse z
+// transform as a direct sum evaluated only on the nz planes kept.  Threads
+// run along the contiguous (ky, kx) plane, so every access is a coalesced
+// stream; the LDS kernel above moves a few hundred values per workgroup
+// through several synchronised passes instead.
+template <typename T, int NZ>
+__global__ void __launch_bounds__(kBlock) k_zconv_reg(YArgs<T> a) {
+  if (a.done && *a.done) return;
+  const int nz = a.nz, Pz = a.Pz, Kx = a.Kx;
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= a.Py * Kx) return;
+  const int ky = j / Kx, kx = j - ky * Kx;
+  const size_t pstride = (size_t)a.Sy * Kx;
+  cpx<T>* __restrict__ base = a.S + (size_t)blockIdx.y * 3 * nz * pstride + j;
+  cpx<T> x[3][NZ], y[3][NZ];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) {
+      x[c][z] = (z < nz) ? base[(size_t)(c * nz + z) * pstride] : cpx<T>{0, 0};
+      y[c][z] = {0, 0};
+    }
+  const bool ylo = 2 * ky <= a.Py;
+  const int ty = ylo ? ky : a.Py - ky;
+  const T sy = ylo ? T(1) : T(-1);
+  const cpx<T>* __restrict__ tw = a.tw;  // exp(-2 pi i k / Pz), k < Pz
+  for (int kz = 0; kz < Pz; ++kz) {
+    cpx<T> X[3] = {x[0][0], x[1][0], x[2][0]};
+    int e = 0;  // kz z mod Pz
+#pragma unroll
+    for (int z = 1; z < NZ; ++z) {
+      e += kz;
+      if (e >= Pz) e -= Pz;
+      if (z < nz) {
+        const cpx<T> w = tw[e];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) X[c] = cadd(X[c], cmul(x[c][z], w));
+      }
+    }
+    const bool zlo = 2 * kz <= Pz;
+    const int tz = zlo ? kz : Pz - kz;
+    const T sz = zlo ? T(1) : T(-1);
+    tensor_apply(a.Nt, ((size_t)tz * a.Ty + ty) * Kx + kx, sy, sz, sy * sz, true, X[0], X[1],
+                 X[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[c][0] = cadd(y[c][0], X[c]);
+    e = 0;
+#pragma unroll
+    for (int z = 1; z < NZ; ++z) {
+      e += kz;
+      if (e >= Pz) e -= Pz;
+      if (z < nz) {
+        const cpx<T> w = tw[e];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) y[c][z] = cadd(y[c][z], cmulc(X[c], w));
+      }
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < NZ; ++z)
+      if (z < nz) base[(size_t)(c * nz + z) * pstride] = y[c][z];
 }
 
 // ---------------------------------------------------------------------------

@@ -271,6 +271,14 @@ mmx_status ensure_graph_stream(mmx_ctx* ctx);
 template <typename T>
 size_t cpxb() { return sizeof(cpx<T>); }
 
+// LDS of a y workgroup of W spectrum columns of length Py: all three
+// components in 2-D (the tensor product needs them together), one component
+// per workgroup for the 3-D y passes
+template <typename T>
+size_t lds_ycols(bool is3d, int W, int Py) {
+  return (2 * (is3d ? 1 : 3) * (size_t)W * Py + Py) * cpxb<T>();
+}
+
 mmx_status check_group(const mmx_group& g) {
   for (int a = 0; a < 3; ++a) {
     if (g.n[a] < 1) return fail(MMX_ESHAPE, "group: n must be >= 1");
@@ -311,7 +319,8 @@ mmx_status setup_group(mmx_ctx* ctx, Group& G) {
     return fail(MMX_EUNSUP, "z length not 2^a 3^b 5^c");
   G.L = std::max(1, std::min(G.ny, kBlock / std::max(1, G.nx)));
   const size_t budget = 48 * 1024;
-  G.Wy = (int)std::max<size_t>(1, std::min<size_t>(16, budget / (6 * (size_t)G.Py * cpxb<T>())));
+  G.Wy = (int)std::max<size_t>(
+      1, std::min<size_t>(16, budget / ((G.is3d ? 2 : 6) * (size_t)G.Py * cpxb<T>())));
   G.Wy = std::min(G.Wy, G.Kx);
   G.Wz = (int)std::max<size_t>(1, std::min<size_t>(16, budget / (6 * (size_t)G.Pz * cpxb<T>())));
   G.Wz = std::min(G.Wz, G.Kx);
@@ -321,7 +330,7 @@ mmx_status setup_group(mmx_ctx* ctx, Group& G) {
       (2 * 3 * (size_t)G.Pz + G.Pz) * cpxb<T>() > 64 * 1024)
     return fail(MMX_EUNSUP, "grid too long along one axis for this precision");
   while (G.L > 1 && (2 * 3 * (size_t)G.L * G.hx + 2 * G.hx + 1) * cpxb<T>() > 64 * 1024) G.L /= 2;
-  while (G.Wy > 1 && (2 * 3 * (size_t)G.Wy * G.Py + G.Py) * cpxb<T>() > 64 * 1024) G.Wy /= 2;
+  while (G.Wy > 1 && lds_ycols<T>(G.is3d, G.Wy, G.Py) > 64 * 1024) G.Wy /= 2;
   while (G.Wz > 1 && (2 * 3 * (size_t)G.Wz * G.Pz + G.Pz) * cpxb<T>() > 64 * 1024) G.Wz /= 2;
   G.nblk = ((G.ny + G.L - 1) / G.L) * G.nz;
   // twiddles
@@ -565,7 +574,9 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
       }
       G.nblk_last = gx * G.nz;
       const RowKernel kern = k[mode == FM_HEUN1 ? 0 : 1][a.rot ? 1 : 0][(a.terms & T_STT) ? 1 : 0];
-      kern<<<grid, 64, 0, s>>>(a);
+      // each of the wave's rows stages its field: 3 components of nx reals
+      const size_t lds = (size_t)rpw * 3 * G.nx * sizeof(float);
+      kern<<<grid, 64, lds, s>>>(a);
       return true;
     };
 #define MMX_ROWS_V(N1, N2, M) \
@@ -698,6 +709,10 @@ bool yconv_reg_applies(const Group& G) {
   return std::is_same<T, float>::value && !G.is3d && (G.Py == 64 || G.Py == 128 || G.Py == 256);
 }
 
+// whether the z pass of the 3-D group G runs in registers (few layers); the
+// z tile Wz then plays no part
+inline bool zconv_reg_applies(const Group& G) { return G.is3d && G.nz <= 8; }
+
 // m: group-local base pointer of the state used for fields.
 template <typename T>
 mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb, const Epilogue& ep,
@@ -751,8 +766,8 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
       y.tw = G.tw_y.as<cpx<T>>();
       y.pf = G.plan_yf;
       y.pi = G.plan_yi;
-      dim3 gy((G.Kx + G.Wy - 1) / G.Wy, G.nz, G.R);
-      const size_t ldy = (2 * (size_t)3 * G.Wy * G.Py + G.Py) * cpxb<T>();
+      dim3 gy((G.Kx + G.Wy - 1) / G.Wy, 3 * G.nz, G.R);
+      const size_t ldy = lds_ycols<T>(true, G.Wy, G.Py);
       {
         ProfScope ps(ctx->prof, "k_ypass_fwd", s);
         k_ypass<T, false><<<gy, kBlock, ldy, s>>>(y);
@@ -763,9 +778,21 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
       zz.tw = G.tw_z.as<cpx<T>>();
       zz.pf = G.plan_zf;
       zz.pi = G.plan_zi;
-      dim3 gz((G.Kx + G.Wz - 1) / G.Wz, G.Py, G.R);
-      ProfScope psz(ctx->prof, "k_zconv", s);
-      k_zconv<T><<<gz, kBlock, (2 * (size_t)3 * G.Wz * G.Pz + G.Pz) * cpxb<T>(), s>>>(zz);
+      {
+        ProfScope psz(ctx->prof, "k_zconv", s);
+        if (zconv_reg_applies(G)) {
+          dim3 gz((G.Py * G.Kx + kBlock - 1) / kBlock, G.R);
+          if (G.nz <= 2)
+            k_zconv_reg<T, 2><<<gz, kBlock, 0, s>>>(zz);
+          else if (G.nz <= 4)
+            k_zconv_reg<T, 4><<<gz, kBlock, 0, s>>>(zz);
+          else
+            k_zconv_reg<T, 8><<<gz, kBlock, 0, s>>>(zz);
+        } else {
+          dim3 gz((G.Kx + G.Wz - 1) / G.Wz, G.Py, G.R);
+          k_zconv<T><<<gz, kBlock, (2 * (size_t)3 * G.Wz * G.Pz + G.Pz) * cpxb<T>(), s>>>(zz);
+        }
+      }
       HIP_TRY(hipGetLastError());
       {
         ProfScope ps(ctx->prof, "k_ypass_inv", s);
@@ -1633,7 +1660,7 @@ template <typename T>
 mmx_status apply_tiles(Group& G, int L, int Wy, int Wz) {
   if (L < 1 || L > G.ny || Wy < 1 || Wy > G.Kx || Wz < 1 || Wz > G.Kx)
     return fail(MMX_EINVAL, "tile sizes out of range");
-  if (lds_x<T>(G, L) > kMaxDynLds || lds_col<T>(Wy, G.Py) > kMaxDynLds ||
+  if (lds_x<T>(G, L) > kMaxDynLds || lds_ycols<T>(G.is3d, Wy, G.Py) > kMaxDynLds ||
       lds_col<T>(Wz, G.Pz) > kMaxDynLds)
     return fail(MMX_EINVAL, "tile sizes exceed the LDS budget");
   G.L = L;
@@ -1690,13 +1717,13 @@ mmx_status autotune_impl(mmx_ctx* ctx) {
     }
     bt = 1e30f;
     for (int W : cand) {
-      if (W > G.Kx || lds_col<T>(W, G.Py) > kMaxDynLds) continue;
+      if (W > G.Kx || lds_ycols<T>(G.is3d, W, G.Py) > kMaxDynLds) continue;
       MMX_TRY(apply_tiles<T>(G, bestL, W, bestWz));
       float t;
       MMX_TRY(time_eval<T>(ctx, G, t));
       if (t < bt) { bt = t; bestW = W; }
     }
-    if (G.is3d) {
+    if (G.is3d && !zconv_reg_applies(G)) {
       bt = 1e30f;
       for (int W : cand) {
         if (W > G.Kx || lds_col<T>(W, G.Pz) > kMaxDynLds) continue;

@@ -56,21 +56,16 @@ __device__ inline void line_transform(cpx<T> (&v)[N2], cpx<T>* E, int q,
 // Real-to-complex split S[kx] = E + conj(W^kx) O of a row whose half-length
 // transform X sits in the lanes as v[c][d] = X[q + N1 d]: lane q stores
 // kx = q + N1 d and (lane 0) kx = hx; the partner X[hx - kx] comes through
-// LDS.  Followed by no barrier: E is reused only after the next one.
+// LDS, one component at a time (hx slots of E).  Followed by no barrier: E
+// is reused only after the next one.
 template <typename T, int N1, int N2>
 __device__ inline void rows_store_spectrum(const cpx<T> (&v)[3][N2], cpx<T>* E, int q, bool live,
                                            cpx<T>* __restrict__ Srow, size_t cstride,
                                            const cpx<T>* __restrict__ wpost) {
   constexpr int hx = N1 * N2;
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int d = 0; d < N2; ++d) E[c * hx + q + N1 * d] = v[c][d];
-  __syncthreads();
-  if (!live) return;
-  auto split = [&](int c, int kx) -> cpx<T> {
-    const cpx<T> Zk = E[c * hx + (kx == hx ? 0 : kx)];
-    cpx<T> Zc = E[c * hx + (kx == 0 ? 0 : hx - kx)];
+  auto split = [&](int kx) -> cpx<T> {
+    const cpx<T> Zk = E[kx == hx ? 0 : kx];
+    cpx<T> Zc = E[kx == 0 ? 0 : hx - kx];
     Zc.im = -Zc.im;
     const cpx<T> Ev = {T(0.5) * (Zk.re + Zc.re), T(0.5) * (Zk.im + Zc.im)};
     const cpx<T> O = {T(0.5) * (Zk.re - Zc.re), T(0.5) * (Zk.im - Zc.im)};
@@ -81,15 +76,21 @@ __device__ inline void rows_store_spectrum(const cpx<T> (&v)[3][N2], cpx<T>* E, 
   // cover 2 N1 consecutive columns), lane 0 also the last column kx = hx
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    if (c > 0) __syncthreads();  // the previous component's reads are done
 #pragma unroll
-    for (int d = 0; d < N2 / 2; ++d) {
-      const int kx = 2 * q + 2 * N1 * d;
-      const cpx<T> s0 = split(c, kx), s1 = split(c, kx + 1);
-      cpx<T>* dst = Srow + c * cstride + kx;
-      dst[0] = s0;
-      dst[1] = s1;
+    for (int d = 0; d < N2; ++d) E[q + N1 * d] = v[c][d];
+    __syncthreads();
+    if (live) {
+#pragma unroll
+      for (int d = 0; d < N2 / 2; ++d) {
+        const int kx = 2 * q + 2 * N1 * d;
+        const cpx<T> s0 = split(kx), s1 = split(kx + 1);
+        cpx<T>* dst = Srow + c * cstride + kx;
+        dst[0] = s0;
+        dst[1] = s1;
+      }
+      if (q == 0) Srow[c * cstride + hx] = split(hx);
     }
-    if (q == 0) Srow[c * cstride + hx] = split(c, hx);
   }
 }
 
@@ -101,7 +102,7 @@ template <typename T, int N1, int N2>
 __global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
   static_assert(N2 % N1 == 0 && 64 % N1 == 0, "row split");
   constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = N2 / N1;
-  constexpr int RS = 3 * hx;
+  constexpr int RS = hx + N1;  // transpose slots N1 (N2 + 1); split slots hx
   __shared__ cpx<T> Es[RPW * RS];
   const int lane = threadIdx.x, row = lane / N1, q = lane - row * N1;
   int bx, by, bz;
@@ -146,9 +147,12 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   static_assert(MODE == FM_HEUN1 || MODE == FM_HEUN2, "Heun stages only");
   static_assert(N2 % N1 == 0 && 64 % N1 == 0, "row split");
   constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = N2 / N1;
-  constexpr int RS = 3 * hx;  // LDS per row (complex): the row's field, 3 components
-  static_assert(RS >= N1 * (N2 + 1), "transpose slots fit the row's LDS");
-  __shared__ cpx<T> Es[RPW * RS];
+  // LDS per row (complex, dynamic): the row's field, 3 components of nx
+  // reals (nx = hx for an open x axis, 2 hx periodic); this covers the
+  // transpose slots N1 (N2 + 1) and the split slots hx
+  const int nx = a.nx, RS = 3 * nx / 2;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* Es = reinterpret_cast<cpx<T>*>(smem_raw);
   __shared__ double red[64];
   const int lane = threadIdx.x, row = lane / N1, q = lane - row * N1;
   int bx, by, bz;
@@ -156,7 +160,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   const int r = bz, z = by, y = bx * RPW + row;
   const bool live = y < a.ny;
   cpx<T>* E = Es + row * RS;
-  T* Hs = reinterpret_cast<T*>(E);  // real view [c][x], 2 hx per component
+  T* Hs = reinterpret_cast<T*>(E);  // real view [c][x], x < nx
   const size_t rb = (size_t)r * 3 * a.N;
   const unsigned N = (unsigned)a.N;
   const int Kx = a.Kx;
@@ -195,13 +199,16 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
 #pragma unroll
   for (int c = 0; c < 3; ++c) line_transform<T, N1, N2, true>(v[c], E, q, tw);
   // lane q holds z[q + N1 d] = H_demag at cells x = 2 (q + N1 d) + {0, 1};
-  // stage the row's field in LDS
+  // stage the row's field in LDS (cells x < nx; nx is even)
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int d = 0; d < N2; ++d) {
-      Hs[c * 2 * hx + 2 * (q + N1 * d)] = v[c][d].re;
-      Hs[c * 2 * hx + 2 * (q + N1 * d) + 1] = v[c][d].im;
+      const int x = 2 * (q + N1 * d);
+      if (x < nx) {
+        Hs[c * nx + x] = v[c][d].re;
+        Hs[c * nx + x + 1] = v[c][d].im;
+      }
     }
   __syncthreads();
   const T dt = (T)a.dth;
@@ -220,15 +227,16 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   for (int j = 0; j < 2 * N2; ++j) {
     const int x = q + N1 * j;
     T mn_out[3] = {0, 0, 0};
-    if (live && x < a.nx) {
-      const unsigned cell = (unsigned)x + (unsigned)a.nx * (unsigned)(y + a.ny * z);
+    if (x >= nx) break;  // x grows with j
+    if (live) {
+      const unsigned cell = (unsigned)x + (unsigned)nx * (unsigned)(y + a.ny * z);
       T mc[3];
       ld3(mr, N, cell, mc);
       T Hex[3], Hdm[3], Han[3], Hz[3];
       local_terms<T, false>(a, mr, cell, x, y, z, mc, a.kbc, Hex, Hdm, Han, Hz);
       T H[3];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + Hs[c * 2 * hx + x];
+      for (int c = 0; c < 3; ++c) H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + Hs[c * nx + x];
       if (sigma != T(0)) {
         T eta[3];
         uint32_t gen;
@@ -259,13 +267,14 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
         acc += (double)mn_out[2];
       }
     }
-    // the new state is the forward transform's input (zero beyond the last
-    // cell); it replaces the field value of the same cell
+    // the new state is the forward transform's input; it replaces the field
+    // value of the same cell
 #pragma unroll
-    for (int c = 0; c < 3; ++c) Hs[c * 2 * hx + x] = mn_out[c];
+    for (int c = 0; c < 3; ++c) Hs[c * nx + x] = mn_out[c];
   }
   __syncthreads();
   // 2. forward x transform of the new state, inputs at k = q + N1 s + N2 b
+  //    (zero beyond the last cell)
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -273,7 +282,8 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
 #pragma unroll
       for (int b = 0; b < N1; ++b) {
         const int k = q + N1 * s + N2 * b;
-        v[c][s * N1 + b] = {Hs[c * 2 * hx + 2 * k], Hs[c * 2 * hx + 2 * k + 1]};
+        v[c][s * N1 + b] = (2 * k < nx) ? cpx<T>{Hs[c * nx + 2 * k], Hs[c * nx + 2 * k + 1]}
+                                        : cpx<T>{0, 0};
       }
   __syncthreads();
 #pragma unroll
