@@ -574,8 +574,7 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
       }
       G.nblk_last = gx * G.nz;
       const RowKernel kern = k[mode == FM_HEUN1 ? 0 : 1][a.rot ? 1 : 0][(a.terms & T_STT) ? 1 : 0];
-      // each of the wave's rows stages its field: 3 components of nx reals
-      const size_t lds = (size_t)rpw * 3 * G.nx * sizeof(float);
+      const size_t lds = (size_t)rpw * rows_lds_stride(G.nx) * sizeof(cpx<float>);
       kern<<<grid, 64, lds, s>>>(a);
       return true;
     };

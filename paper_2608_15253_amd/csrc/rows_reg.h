@@ -142,15 +142,21 @@ __global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
   rows_store_spectrum<T, N1, N2>(v, E, q, live, Srow, cstride, wpl);
 }
 
+// LDS row stride of k_rows_reg (complex slots): at least the row's field (3
+// components of nx reals; nx = hx for an open x axis, 2 hx periodic), which
+// covers the transpose slots N1 (N2 + 1) and the split slots hx, rounded to
+// 8 mod 16 slots so that the 8-byte accesses of two neighbouring rows fall
+// into complementary halves of the LDS banks
+__host__ __device__ constexpr int rows_lds_stride(int nx) {
+  return ((3 * nx / 2 + 7) & ~15) + 8;
+}
+
 template <typename T, int N1, int N2, int MODE, bool ROT, bool STT>
 __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   static_assert(MODE == FM_HEUN1 || MODE == FM_HEUN2, "Heun stages only");
   static_assert(N2 % N1 == 0 && 64 % N1 == 0, "row split");
   constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = N2 / N1;
-  // LDS per row (complex, dynamic): the row's field, 3 components of nx
-  // reals (nx = hx for an open x axis, 2 hx periodic); this covers the
-  // transpose slots N1 (N2 + 1) and the split slots hx
-  const int nx = a.nx, RS = 3 * nx / 2;
+  const int nx = a.nx, RS = rows_lds_stride(nx);  // LDS per row (dynamic)
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* Es = reinterpret_cast<cpx<T>*>(smem_raw);
   __shared__ double red[64];
