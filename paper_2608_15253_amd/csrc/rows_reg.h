@@ -181,29 +181,41 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   __syncthreads();
   const cpx<T>* tw = twl;  // exp(-2 pi i k / hx), k < hx
   // 1. inverse x transform of the demag spectrum: inputs Z[k] at k = q + N1 s
-  //    + N2 b (complex-to-real combination of S[k] and S[hx - k])
+  //    + N2 b (complex-to-real combination of S[k] and S[hx - k]).  Each
+  //    spectrum row is read once, in coalesced order (columns q + N1 i, lane
+  //    0 also hx; all loads issued up front), and staged in LDS, where each
+  //    lane picks its pairs
+  cpx<T> sv[3][N2], slast[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int i = 0; i < N2; ++i)
+      sv[c][i] = live ? Srow[c * cstride + q + N1 * i] : cpx<T>{0, 0};
+    slast[c] = (live && q == 0) ? Srow[c * cstride + hx] : cpx<T>{0, 0};
+  }
   cpx<T> v[3][N2];
 #pragma unroll
-  for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int i = 0; i < N2; ++i) E[q + N1 * i] = sv[c][i];
+    if (q == 0) E[hx] = slast[c];
+    __syncthreads();
 #pragma unroll
     for (int s = 0; s < S2; ++s)
 #pragma unroll
       for (int b = 0; b < N1; ++b) {
         const int k = q + N1 * s + N2 * b;
-        cpx<T> Zv = {0, 0};
-        if (live) {
-          const cpx<T> Xk = Srow[c * cstride + k];
-          cpx<T> Xc = Srow[c * cstride + (hx - k)];
-          Xc.im = -Xc.im;
-          const cpx<T> Ev = cadd(Xk, Xc);
-          const cpx<T> D = csub(Xk, Xc);
-          const cpx<T> O = cmulc(D, wpl[k]);  // D * conj(W^k)
-          Zv = {Ev.re - O.im, Ev.im + O.re};
-        }
-        v[c][s * N1 + b] = Zv;
+        const cpx<T> Xk = E[k];
+        cpx<T> Xc = E[hx - k];
+        Xc.im = -Xc.im;
+        const cpx<T> Ev = cadd(Xk, Xc);
+        const cpx<T> D = csub(Xk, Xc);
+        const cpx<T> O = cmulc(D, wpl[k]);  // D * conj(W^k)
+        v[c][s * N1 + b] = live ? cpx<T>{Ev.re - O.im, Ev.im + O.re} : cpx<T>{0, 0};
       }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) line_transform<T, N1, N2, true>(v[c], E, q, tw);
+    __syncthreads();
+    line_transform<T, N1, N2, true>(v[c], E, q, tw);
+  }
   // lane q holds z[q + N1 d] = H_demag at cells x = 2 (q + N1 d) + {0, 1};
   // stage the row's field in LDS (cells x < nx; nx is even)
 #pragma unroll
