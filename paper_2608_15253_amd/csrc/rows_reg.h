@@ -154,6 +154,7 @@ __host__ __device__ constexpr int rows_lds_stride(int nx) {
 template <typename T, int N1, int N2, int MODE, bool ROT, bool STT>
 __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   static_assert(MODE == FM_HEUN1 || MODE == FM_HEUN2, "Heun stages only");
+  static_assert(sizeof(T) == sizeof(float), "FP32 row kernels");
   static_assert(N2 % N1 == 0 && 64 % N1 == 0, "row split");
   constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = N2 / N1;
   const int nx = a.nx, RS = rows_lds_stride(nx);  // LDS per row (dynamic)
@@ -269,10 +270,9 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
       if (MODE == FM_HEUN1) {
         T k1v[3];
         heun_predict(a, ROT, mc, H, kv, tau, dt, k1v, mn_out);
+        if (ROT) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (ROT) k1_r[c * N + cell] = k1v[c];
-          mout_r[c * N + cell] = mn_out[c];
+          for (int c = 0; c < 3; ++c) k1_r[c * N + cell] = k1v[c];
         }
       } else {
         T mo[3], k1v[3];
@@ -280,8 +280,6 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
         if (ROT) ld3(k1_r, N, cell, k1v);
         else k1v[0] = k1v[1] = k1v[2] = T(0);
         heun_correct(a, ROT, mc, H, kv, tau, mo, k1v, dt, mn_out);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) mout_r[c * N + cell] = mn_out[c];
         acc += (double)mn_out[2];
       }
     }
@@ -291,6 +289,25 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
     for (int c = 0; c < 3; ++c) Hs[c * nx + x] = mn_out[c];
   }
   __syncthreads();
+  // the row's new state goes out from LDS in 16-byte pieces (the N1 lanes of
+  // a row write 16 N1 consecutive bytes per instruction), or cell by cell
+  // when the state of this replica group is not 16-byte aligned
+  if (live) {
+    const unsigned row0 = (unsigned)nx * (unsigned)(y + a.ny * z);
+    if ((((uintptr_t)mout_r) & 15) == 0 && (N & 3) == 0) {
+      const int nq = nx / 4;
+      for (int i = q; i < 3 * nq; i += N1) {
+        const int c = i / nq, x4 = 4 * (i - c * nq);
+        const T* h = Hs + c * nx + x4;
+        *reinterpret_cast<float4*>(mout_r + c * N + row0 + x4) = float4{h[0], h[1], h[2], h[3]};
+      }
+    } else {
+      for (int i = q; i < 3 * nx; i += N1) {
+        const int c = i / nx, x = i - c * nx;
+        mout_r[c * N + row0 + x] = Hs[c * nx + x];
+      }
+    }
+  }
   // 2. forward x transform of the new state, inputs at k = q + N1 s + N2 b
   //    (zero beyond the last cell)
 #pragma unroll
