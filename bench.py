@@ -430,7 +430,7 @@ def bench_stt(args):
     mmx.mmx_depondt_refill(ctx, mr, m_init, dt, steps, times, cap, counts)
     torch.cuda.synchronize()
     el_r = time.perf_counter() - t0
-    trials = counts.view(npts, per).double().mean(dim=1).cpu().numpy()
+    finished = counts.view(npts, per).double().mean(dim=1).cpu().numpy()
     mmx.mmx_destroy(ctx)
     # per-trial loop: 32 single-replica contexts, one call per step each
     trials, tsteps = 32, 200
@@ -461,7 +461,7 @@ def bench_stt(args):
             "p_switch": {"J_over_Jc0": [round(float(x), 4) for x in ratios],
                          "P_sw": [round(float(x), 4) for x in psw]},
             "refill": {"value": R * steps / el_r, "unit": "replica-steps/s", "seconds": el_r,
-                       "mean_finished_trials_per_slot": [round(float(x), 3) for x in trials]}}
+                       "mean_finished_trials_per_slot": [round(float(x), 3) for x in finished]}}
 
 
 def bench_throughput(args):
