@@ -132,7 +132,7 @@ struct Dft {
 template <typename T, bool INV, int R>
 __device__ inline void stockham_pass(const cpx<T>* __restrict__ src, cpx<T>* __restrict__ dst,
                                      int n, int Ns, int nlines, const cpx<T>* __restrict__ tw,
-                                     int tid, int nthr) {
+                                     int tid, int nthr, int ld) {
   const int nb = n / R;
   const int total = nb * nlines;
   const int twscale = n / (Ns * R);
@@ -142,8 +142,8 @@ __device__ inline void stockham_pass(const cpx<T>* __restrict__ src, cpx<T>* __r
   for (int t = tid; t < total; t += nthr) {
     const int line = p2 ? (t >> lnb) : t / nb;
     const int j = t - line * nb;
-    const cpx<T>* s = src + line * n;
-    cpx<T>* d = dst + line * n;
+    const cpx<T>* s = src + line * ld;
+    cpx<T>* d = dst + line * ld;
     const int jq = p2 ? (j >> lns) : j / Ns;
     const int jm = j - jq * Ns;
     cpx<T> v[R];
@@ -169,12 +169,14 @@ __device__ inline void stockham_pass(const cpx<T>* __restrict__ src, cpx<T>* __r
 }
 
 // Transforms nlines lines in `a` (scratch `b`), returns the buffer holding the
-// result.  `tw` is the table exp(-2 pi i k / n), k < n.  Must be called by the
-// whole workgroup; ends with a barrier.
+// result.  `tw` is the table exp(-2 pi i k / n), k < n.  Lines start every
+// `ld` slots (0: every n, contiguous).  Must be called by the whole
+// workgroup; ends with a barrier.
 template <typename T, bool INV>
 __device__ cpx<T>* lds_fft(cpx<T>* a, cpx<T>* b, int nlines, const FftPlan& p,
-                           const cpx<T>* __restrict__ tw) {
+                           const cpx<T>* __restrict__ tw, int ld = 0) {
   const int n = p.n;
+  if (ld == 0) ld = n;
   const int tid = threadIdx.x, nthr = blockDim.x;
   int Ns = 1;
   for (int ps = 0; ps < p.npass; ++ps) {
@@ -185,18 +187,18 @@ __device__ cpx<T>* lds_fft(cpx<T>* a, cpx<T>* b, int nlines, const FftPlan& p,
       for (int t = tid; t < total; t += nthr) {
         const int line = udiv(t, half);
         const int j = t - line * half;
-        const cpx<T> v = a[line * n + j];
-        b[line * n + 2 * j] = v;
-        b[line * n + 2 * j + 1] = v;
+        const cpx<T> v = a[line * ld + j];
+        b[line * ld + 2 * j] = v;
+        b[line * ld + 2 * j + 1] = v;
       }
     } else {
       switch (R) {
-        case 2: stockham_pass<T, INV, 2>(a, b, n, Ns, nlines, tw, tid, nthr); break;
-        case 3: stockham_pass<T, INV, 3>(a, b, n, Ns, nlines, tw, tid, nthr); break;
-        case 4: stockham_pass<T, INV, 4>(a, b, n, Ns, nlines, tw, tid, nthr); break;
-        case 5: stockham_pass<T, INV, 5>(a, b, n, Ns, nlines, tw, tid, nthr); break;
-        case 8: stockham_pass<T, INV, 8>(a, b, n, Ns, nlines, tw, tid, nthr); break;
-        default: stockham_pass<T, INV, 16>(a, b, n, Ns, nlines, tw, tid, nthr); break;
+        case 2: stockham_pass<T, INV, 2>(a, b, n, Ns, nlines, tw, tid, nthr, ld); break;
+        case 3: stockham_pass<T, INV, 3>(a, b, n, Ns, nlines, tw, tid, nthr, ld); break;
+        case 4: stockham_pass<T, INV, 4>(a, b, n, Ns, nlines, tw, tid, nthr, ld); break;
+        case 5: stockham_pass<T, INV, 5>(a, b, n, Ns, nlines, tw, tid, nthr, ld); break;
+        case 8: stockham_pass<T, INV, 8>(a, b, n, Ns, nlines, tw, tid, nthr, ld); break;
+        default: stockham_pass<T, INV, 16>(a, b, n, Ns, nlines, tw, tid, nthr, ld); break;
       }
     }
     __syncthreads();

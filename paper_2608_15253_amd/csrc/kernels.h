@@ -301,9 +301,11 @@ __global__ void __launch_bounds__(kBlock) k_ypass(YArgs<T> a) {
   if (a.done && *a.done) return;
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
-  const int W = a.W, Py = a.Py;
-  cpx<T>* Bf = A + W * Py;
-  const cpx<T>* tw = stage_table(Bf + W * Py, a.tw, Py);
+  // lines of Py + 1 slots: the lanes of one global access (consecutive kx,
+  // i.e. consecutive lines) then fall into different LDS banks
+  const int W = a.W, Py = a.Py, ld = Py + 1;
+  cpx<T>* Bf = A + W * ld;
+  const cpx<T>* tw = stage_table(Bf + W * ld, a.tw, Py);
   const int kx0 = blockIdx.x * W;
   // one (component, z) plane of one replica: no product couples the
   // components here, so a workgroup takes W columns of a single one (wider
@@ -315,14 +317,14 @@ __global__ void __launch_bounds__(kBlock) k_ypass(YArgs<T> a) {
     const int w = umod(t, W), y = udiv(t, W);
     cpx<T> v = {0, 0};
     if (y < nin && kx0 + w < a.Kx) v = P[(size_t)y * a.Kx + w];
-    A[w * Py + y] = v;
+    A[w * ld + y] = v;
   }
   __syncthreads();
-  const cpx<T>* Y = lds_fft<T, INV>(A, Bf, W, INV ? a.pi : a.pf, tw);
+  const cpx<T>* Y = lds_fft<T, INV>(A, Bf, W, INV ? a.pi : a.pf, tw, ld);
   const int nout = INV ? a.ny : Py;
   for (int t = threadIdx.x; t < W * nout; t += blockDim.x) {
     const int w = umod(t, W), y = udiv(t, W);
-    if (kx0 + w < a.Kx) P[(size_t)y * a.Kx + w] = Y[w * Py + y];
+    if (kx0 + w < a.Kx) P[(size_t)y * a.Kx + w] = Y[w * ld + y];
   }
 }
 

@@ -273,10 +273,11 @@ size_t cpxb() { return sizeof(cpx<T>); }
 
 // LDS of a y workgroup of W spectrum columns of length Py: all three
 // components in 2-D (the tensor product needs them together), one component
-// per workgroup for the 3-D y passes
+// per workgroup for the 3-D y passes (lines of Py + 1 slots)
 template <typename T>
 size_t lds_ycols(bool is3d, int W, int Py) {
-  return (2 * (is3d ? 1 : 3) * (size_t)W * Py + Py) * cpxb<T>();
+  if (is3d) return (2 * (size_t)W * (Py + 1) + Py) * cpxb<T>();
+  return (2 * 3 * (size_t)W * Py + Py) * cpxb<T>();
 }
 
 mmx_status check_group(const mmx_group& g) {
