@@ -9,7 +9,9 @@
 //   k_yconv  (2-D) y transform (pruned: rows >= ny are zero), product with the
 //            parity-compressed real symmetric tensor spectrum, inverse y
 //            transform, rows >= ny dropped;
-//   k_ypass / k_zconv(_reg) / k_ypass  (3-D) the same split over y and z;
+//   k_yzconv (3-D, few layers) y transforms, z transform with the full
+//            tensor product and inverse transforms in one pass;
+//   k_ypass / k_zconv(_reg) / k_ypass  (other 3-D) the same split over y and z;
 //   k_fields complex-to-real inverse x transform (outputs x < nx only) fused
 //            with exchange, interfacial DMI, uniaxial anisotropy, Zeeman and
 //            Brown thermal fields, the LLG torque and the integrator epilogue
@@ -231,6 +233,7 @@ struct YArgs {
   FftPlan pf, pi;
   int ny, Py, Kx, W, Ty, Sy, nz, Pz, Tz, z;
   const int* done;
+  const cpx<T>* twz;  // z twiddles exp(-2 pi i k / Pz) of the fused y-z pass
   // switching check of the previous Heun step, folded into the register
   // column kernel (sw_tsw null: none): the workgroup of column tile 0 of
   // each replica sums that replica's corrector partial sums of m_z
@@ -373,36 +376,35 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
   }
 }
 
-// 3-D grids of few layers (nz <= NZ): one thread per (ky, kx) pillar holds
-// its nz planes of all three components in registers and takes the z
-// transform as a direct sum over the nz planes that carry data (the padding
-// planes are zero), the full tensor product per kz, and the inverse z
-// transform as a direct sum evaluated only on the nz planes kept.  Threads
-// run along the contiguous (ky, kx) plane, so every access is a coalesced
-// stream; the LDS kernel above moves a few hundred values per workgroup
-// through several synchronised passes instead.
+// The z transform of one (ky, kx) pillar held as x[c][z] (planes z >= nz
+// are zero padding and not stored) as a direct sum over the nz planes, the
+// full tensor product per kz, and the inverse z transform as a direct sum
+// evaluated only on the nz planes kept (accumulated into y, zero on entry).
+// tw: exp(-2 pi i k / Pz), k < Pz.
 template <typename T, int NZ>
-__global__ void __launch_bounds__(kBlock) k_zconv_reg(YArgs<T> a) {
-  if (a.done && *a.done) return;
+__device__ inline void z_pillar(const YArgs<T>& a, const cpx<T>* __restrict__ tw, int ky, int kx,
+                                const cpx<T> (&x)[3][NZ], cpx<T> (&y)[3][NZ]) {
   const int nz = a.nz, Pz = a.Pz, Kx = a.Kx;
-  const int j = blockIdx.x * kBlock + threadIdx.x;
-  if (j >= a.Py * Kx) return;
-  const int ky = j / Kx, kx = j - ky * Kx;
-  const size_t pstride = (size_t)a.Sy * Kx;
-  cpx<T>* __restrict__ base = a.S + (size_t)blockIdx.y * 3 * nz * pstride + j;
-  cpx<T> x[3][NZ], y[3][NZ];
-#pragma unroll
-  for (int c = 0; c < 3; ++c)
-#pragma unroll
-    for (int z = 0; z < NZ; ++z) {
-      x[c][z] = (z < nz) ? base[(size_t)(c * nz + z) * pstride] : cpx<T>{0, 0};
-      y[c][z] = {0, 0};
-    }
   const bool ylo = 2 * ky <= a.Py;
   const int ty = ylo ? ky : a.Py - ky;
   const T sy = ylo ? T(1) : T(-1);
-  const cpx<T>* __restrict__ tw = a.tw;  // exp(-2 pi i k / Pz), k < Pz
-  for (int kz = 0; kz < Pz; ++kz) {
+  // Pz <= 2 NZ: with few layers the tensor entries of every kz are loaded
+  // before the first product, so their latencies overlap
+  constexpr int KZ = 2 * NZ;
+  constexpr bool kPre = NZ <= 4;
+  T pre[kPre ? KZ : 1][6];
+  if constexpr (kPre) {
+#pragma unroll
+    for (int kz = 0; kz < KZ; ++kz) {
+      if (kz < Pz) {
+        const int tz = (2 * kz <= Pz) ? kz : Pz - kz;
+        const T* __restrict__ n = a.Nt + (((size_t)tz * a.Ty + ty) * Kx + kx) * kTensorStride;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) pre[kz][i] = n[i];
+      }
+    }
+  }
+  auto step = [&](int kz, const T* __restrict__ n) {
     cpx<T> X[3] = {x[0][0], x[1][0], x[2][0]};
     int e = 0;  // kz z mod Pz
 #pragma unroll
@@ -415,11 +417,8 @@ __global__ void __launch_bounds__(kBlock) k_zconv_reg(YArgs<T> a) {
         for (int c = 0; c < 3; ++c) X[c] = cadd(X[c], cmul(x[c][z], w));
       }
     }
-    const bool zlo = 2 * kz <= Pz;
-    const int tz = zlo ? kz : Pz - kz;
-    const T sz = zlo ? T(1) : T(-1);
-    tensor_apply(a.Nt, ((size_t)tz * a.Ty + ty) * Kx + kx, sy, sz, sy * sz, true, X[0], X[1],
-                 X[2]);
+    const T sz = (2 * kz <= Pz) ? T(1) : T(-1);
+    tensor_apply(n, 0, sy, sz, sy * sz, true, X[0], X[1], X[2]);
 #pragma unroll
     for (int c = 0; c < 3; ++c) y[c][0] = cadd(y[c][0], X[c]);
     e = 0;
@@ -433,12 +432,104 @@ __global__ void __launch_bounds__(kBlock) k_zconv_reg(YArgs<T> a) {
         for (int c = 0; c < 3; ++c) y[c][z] = cadd(y[c][z], cmulc(X[c], w));
       }
     }
+  };
+  if constexpr (kPre) {
+#pragma unroll
+    for (int kz = 0; kz < KZ; ++kz)
+      if (kz < Pz) step(kz, pre[kz]);
+  } else {
+    for (int kz = 0; kz < Pz; ++kz) {
+      const int tz = (2 * kz <= Pz) ? kz : Pz - kz;
+      step(kz, a.Nt + (((size_t)tz * a.Ty + ty) * Kx + kx) * kTensorStride);
+    }
   }
+}
+
+// 3-D grids of few layers (nz <= NZ): one thread per (ky, kx) pillar holds
+// its nz planes of all three components in registers (z_pillar).  Threads
+// run along the contiguous (ky, kx) plane, so every access is a coalesced
+// stream; the LDS kernel above moves a few hundred values per workgroup
+// through several synchronised passes instead.
+template <typename T, int NZ>
+__global__ void __launch_bounds__(kBlock) k_zconv_reg(YArgs<T> a) {
+  if (a.done && *a.done) return;
+  const int nz = a.nz, Kx = a.Kx;
+  const int j = blockIdx.x * kBlock + threadIdx.x;
+  if (j >= a.Py * Kx) return;
+  const int ky = j / Kx, kx = j - ky * Kx;
+  const size_t pstride = (size_t)a.Sy * Kx;
+  cpx<T>* __restrict__ base = a.S + (size_t)blockIdx.y * 3 * nz * pstride + j;
+  cpx<T> x[3][NZ], y[3][NZ];
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int z = 0; z < NZ; ++z) {
+      x[c][z] = (z < nz) ? base[(size_t)(c * nz + z) * pstride] : cpx<T>{0, 0};
+      y[c][z] = {0, 0};
+    }
+  z_pillar<T, NZ>(a, a.tw, ky, kx, x, y);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int z = 0; z < NZ; ++z)
       if (z < nz) base[(size_t)(c * nz + z) * pstride] = y[c][z];
+}
+
+// 3-D grids of few layers, y and z in one pass: a workgroup holds W spectrum
+// columns of one replica, all nz planes of all three components (3 nz W
+// lines of Py + 1 slots in LDS); forward y transforms (rows >= ny are zero:
+// pruned), then per (ky, kx) pillar the z transform, tensor product and
+// inverse z transform in registers (z_pillar), then inverse y transforms
+// keeping the ny rows stored.  HBM carries each stored row once in and once
+// out, instead of the three passes of k_ypass / k_zconv_reg / k_ypass over
+// the Py padded rows.
+template <typename T, int NZ>
+__global__ void __launch_bounds__(kBlock) k_yzconv(YArgs<T> a) {
+  if (a.done && *a.done) return;
+  extern __shared__ unsigned char smem_raw[];
+  cpx<T>* A = reinterpret_cast<cpx<T>*>(smem_raw);
+  const int W = a.W, Py = a.Py, nz = a.nz, ny = a.ny, ld = Py + 1, nl = 3 * nz * W;
+  cpx<T>* Bf = A + nl * ld;
+  const cpx<T>* tw = stage_table(Bf + nl * ld, a.tw, Py);
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int kx0 = bx * W;
+  const size_t plane = (size_t)a.Sy * a.Kx;
+  cpx<T>* __restrict__ S = a.S + (size_t)bz * 3 * nz * plane + kx0;
+  // line (c nz + z) W + w holds column kx0 + w of plane z of component c
+  for (int t = threadIdx.x; t < nl * ny; t += blockDim.x) {
+    const int w = umod(t, W), rest = udiv(t, W), cz = rest / ny, y = rest - cz * ny;
+    cpx<T> v = {0, 0};
+    if (kx0 + w < a.Kx) v = S[cz * plane + (size_t)y * a.Kx + w];
+    A[(cz * W + w) * ld + y] = v;
+  }
+  __syncthreads();
+  cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, tw, ld);
+  cpx<T>* scratch = (X == A) ? Bf : A;
+  for (int t = threadIdx.x; t < W * Py; t += blockDim.x) {
+    const int w = umod(t, W), ky = udiv(t, W), kx = kx0 + w;
+    if (kx >= a.Kx) continue;
+    cpx<T> x[3][NZ], yv[3][NZ];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int z = 0; z < NZ; ++z) {
+        x[c][z] = (z < nz) ? X[((c * nz + z) * W + w) * ld + ky] : cpx<T>{0, 0};
+        yv[c][z] = {0, 0};
+      }
+    z_pillar<T, NZ>(a, a.twz, ky, kx, x, yv);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int z = 0; z < NZ; ++z)
+        if (z < nz) X[((c * nz + z) * W + w) * ld + ky] = yv[c][z];
+  }
+  __syncthreads();
+  const cpx<T>* Y = lds_fft<T, true>(X, scratch, nl, a.pi, tw, ld);
+  for (int t = threadIdx.x; t < nl * ny; t += blockDim.x) {
+    const int w = umod(t, W), rest = udiv(t, W), cz = rest / ny, y = rest - cz * ny;
+    if (kx0 + w < a.Kx) S[cz * plane + (size_t)y * a.Kx + w] = Y[(cz * W + w) * ld + y];
+  }
 }
 
 // ---------------------------------------------------------------------------

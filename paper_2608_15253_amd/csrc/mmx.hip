@@ -131,7 +131,8 @@ struct Group {
   int nx = 1, ny = 1, nz = 1, N = 1, R = 1;
   int Px = 1, Py = 1, Pz = 1, Kx = 1, hx = 1, Ty = 1, Tz = 1, Sy = 1;
   int xone = 0, is3d = 0;
-  int L = 1, Wy = 1, Wz = 1;
+  int L = 1, Wy = 1, Wz = 1;  // Wz: columns per workgroup of the fused y-z pass when it applies
+  size_t max_lds = 64 * 1024;  // dynamic LDS per workgroup on the device
   FftPlan plan_x{}, plan_xi{}, plan_yf{}, plan_yi{}, plan_zf{}, plan_zi{};
   mmx_material mat{};
   int mat_set = 0;
@@ -274,6 +275,43 @@ size_t cpxb() { return sizeof(cpx<T>); }
 // LDS of a y workgroup of W spectrum columns of length Py: all three
 // components in 2-D (the tensor product needs them together), one component
 // per workgroup for the 3-D y passes (lines of Py + 1 slots)
+// LDS of a fused y-z workgroup of W spectrum columns (3 nz W lines of Py + 1
+// slots, two buffers, the y twiddles)
+template <typename T>
+size_t lds_yz(const Group& G, int W) {
+  return (2 * 3 * (size_t)G.nz * W * (G.Py + 1) + G.Py) * cpxb<T>();
+}
+
+// whether the 3-D group G takes its y and z passes in one fused kernel (few
+// layers, and one column of the workgroup fits the device's LDS)
+template <typename T>
+bool yz_applies(const Group& G) {
+  return G.is3d && G.nz <= 8 && lds_yz<T>(G, 1) <= G.max_lds;
+}
+
+// the fused y-z kernels may take up to the device's LDS per workgroup
+// (beyond the default 64 KB); set once per process, to the device maximum,
+// so that groups with different tiles never undercut each other
+template <typename T>
+mmx_status yz_attr(const Group& G) {
+  const int b = (int)G.max_lds;
+  HIP_TRY(hipFuncSetAttribute((const void*)&k_yzconv<T, 2>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, b));
+  HIP_TRY(hipFuncSetAttribute((const void*)&k_yzconv<T, 4>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, b));
+  HIP_TRY(hipFuncSetAttribute((const void*)&k_yzconv<T, 8>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, b));
+  return MMX_OK;
+}
+
+// whether Wz columns fit one workgroup of the 3-D group's z (or fused y-z) pass
+template <typename T>
+bool wz_fits(const Group& G, int Wz) {
+  constexpr size_t kDefaultLds = 64 * 1024;
+  return yz_applies<T>(G) ? lds_yz<T>(G, Wz) <= G.max_lds
+                          : (2 * 3 * (size_t)Wz * G.Pz + G.Pz) * cpxb<T>() <= kDefaultLds;
+}
+
 template <typename T>
 size_t lds_ycols(bool is3d, int W, int Py) {
   if (is3d) return (2 * (size_t)W * (Py + 1) + Py) * cpxb<T>();
@@ -334,6 +372,13 @@ mmx_status setup_group(mmx_ctx* ctx, Group& G) {
   while (G.Wy > 1 && lds_ycols<T>(G.is3d, G.Wy, G.Py) > 64 * 1024) G.Wy /= 2;
   while (G.Wz > 1 && (2 * 3 * (size_t)G.Wz * G.Pz + G.Pz) * cpxb<T>() > 64 * 1024) G.Wz /= 2;
   G.nblk = ((G.ny + G.L - 1) / G.L) * G.nz;
+  G.max_lds = ctx->max_lds;
+  if (yz_applies<T>(G)) {  // widest column tile with four workgroups per CU
+    G.Wz = 1;
+    for (int W : {16, 8, 4, 2})
+      if (W <= G.Kx && lds_yz<T>(G, W) <= G.max_lds / 4) { G.Wz = W; break; }
+    MMX_TRY(yz_attr<T>(G));
+  }
   // twiddles
   auto up = [&](DevBuf& b, const void* src, size_t bytes) -> mmx_status {
     HIP_TRY(b.alloc(bytes));
@@ -709,9 +754,10 @@ bool yconv_reg_applies(const Group& G) {
   return std::is_same<T, float>::value && !G.is3d && (G.Py == 64 || G.Py == 128 || G.Py == 256);
 }
 
-// whether the z pass of the 3-D group G runs in registers (few layers); the
-// z tile Wz then plays no part
-inline bool zconv_reg_applies(const Group& G) { return G.is3d && G.nz <= 8; }
+// whether the separate z pass of the 3-D group G runs in registers (few
+// layers whose fused y-z workgroup does not fit the LDS)
+template <typename T>
+bool zconv_reg_applies(const Group& G) { return G.is3d && G.nz <= 8 && !yz_applies<T>(G); }
 
 // m: group-local base pointer of the state used for fields.
 template <typename T>
@@ -761,6 +807,22 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
         k_yconv<T><<<grid, kBlock, (2 * (size_t)3 * G.Wy * G.Py + G.Py) * cpxb<T>(), s>>>(y);
       }
       HIP_TRY(hipGetLastError());
+    } else if (yz_applies<T>(G)) {
+      y.W = G.Wz;
+      y.tw = G.tw_y.as<cpx<T>>();
+      y.twz = G.tw_z.as<cpx<T>>();
+      y.pf = G.plan_yf;
+      y.pi = G.plan_yi;
+      dim3 g((G.Kx + G.Wz - 1) / G.Wz, 1, G.R);
+      const size_t lds = lds_yz<T>(G, G.Wz);
+      ProfScope ps(ctx->prof, "k_yzconv", s);
+      if (G.nz <= 2)
+        k_yzconv<T, 2><<<g, kBlock, lds, s>>>(y);
+      else if (G.nz <= 4)
+        k_yzconv<T, 4><<<g, kBlock, lds, s>>>(y);
+      else
+        k_yzconv<T, 8><<<g, kBlock, lds, s>>>(y);
+      HIP_TRY(hipGetLastError());
     } else {
       y.W = G.Wy;
       y.tw = G.tw_y.as<cpx<T>>();
@@ -780,7 +842,7 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
       zz.pi = G.plan_zi;
       {
         ProfScope psz(ctx->prof, "k_zconv", s);
-        if (zconv_reg_applies(G)) {
+        if (zconv_reg_applies<T>(G)) {
           dim3 gz((G.Py * G.Kx + kBlock - 1) / kBlock, G.R);
           if (G.nz <= 2)
             k_zconv_reg<T, 2><<<gz, kBlock, 0, s>>>(zz);
@@ -1661,7 +1723,7 @@ mmx_status apply_tiles(Group& G, int L, int Wy, int Wz) {
   if (L < 1 || L > G.ny || Wy < 1 || Wy > G.Kx || Wz < 1 || Wz > G.Kx)
     return fail(MMX_EINVAL, "tile sizes out of range");
   if (lds_x<T>(G, L) > kMaxDynLds || lds_ycols<T>(G.is3d, Wy, G.Py) > kMaxDynLds ||
-      lds_col<T>(Wz, G.Pz) > kMaxDynLds)
+      !wz_fits<T>(G, Wz))
     return fail(MMX_EINVAL, "tile sizes exceed the LDS budget");
   G.L = L;
   G.Wy = Wy;
@@ -1717,16 +1779,17 @@ mmx_status autotune_impl(mmx_ctx* ctx) {
     }
     bt = 1e30f;
     for (int W : cand) {
+      if (yz_applies<T>(G)) break;  // the fused y-z pass takes no y tile
       if (W > G.Kx || lds_ycols<T>(G.is3d, W, G.Py) > kMaxDynLds) continue;
       MMX_TRY(apply_tiles<T>(G, bestL, W, bestWz));
       float t;
       MMX_TRY(time_eval<T>(ctx, G, t));
       if (t < bt) { bt = t; bestW = W; }
     }
-    if (G.is3d && !zconv_reg_applies(G)) {
+    if (G.is3d && !zconv_reg_applies<T>(G)) {
       bt = 1e30f;
       for (int W : cand) {
-        if (W > G.Kx || lds_col<T>(W, G.Pz) > kMaxDynLds) continue;
+        if (W > G.Kx || !wz_fits<T>(G, W)) continue;
         MMX_TRY(apply_tiles<T>(G, bestL, bestW, W));
         float t;
         MMX_TRY(time_eval<T>(ctx, G, t));

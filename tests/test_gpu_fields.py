@@ -33,12 +33,16 @@ CASES = {
     "block_pbcx_8x4x4": Case((8, 4, 4), (4e-9, 4e-9, 4e-9), pbc=(1, 0, 0), images=(3, 0, 0),
                              R=1),
     "film_96x24x2_radix3": Case((96, 24, 2), (4e-9, 4e-9, 4e-9), R=1, Ku=1e5),
-    # z pass in registers with nz = 5 of 8 (periodic z, Pz = 5) and nz = 8
-    # (open, Pz = 16); nz = 10 takes the LDS z kernel
+    # few-layer z passes (fused with y) with nz = 5 of 8 (periodic z, Pz = 5)
+    # and nz = 8 (open, Pz = 16); nz = 10 takes the LDS z kernel
     "block_pbcz_6x4x5": Case((6, 4, 5), (3e-9, 3e-9, 2e-9), pbc=(0, 0, 1), images=(0, 0, 2),
                              R=2, Ku=2e5, D=1e-3),
     "block_open_4x3x8": Case((4, 3, 8), (3e-9, 3e-9, 2e-9), R=1, Ku=1e5),
     "block_open_4x3x10": Case((4, 3, 10), (3e-9, 3e-9, 2e-9), R=1, Ku=1e5),
+    # FP64: one fused y-z column (6 nz (Py + 1) values) exceeds the LDS of a
+    # workgroup, so the separate y passes and the register z pass run; FP32
+    # fits and takes the fused pass
+    "block_tall_4x120x8": Case((4, 120, 8), (3e-9, 3e-9, 2e-9), R=1, Ku=1e5),
     "chain_30x1x1": Case((30, 1, 1), (5e-9, 5e-9, 5e-9), R=3, Ku=1e5),
     "macrospin": Case((1, 1, 1), (4e-9, 3e-9, 2e-9), R=4, Ku=6e5, B=(0, 0, 0.1)),
     "column_1x9x1": Case((1, 9, 1), (4e-9, 4e-9, 4e-9), R=1),
