@@ -301,15 +301,18 @@ mmx_status mmx_topological_charge(mmx_ctx* ctx, const void* m, void* Q);
 
 /* Tile sizes of group g: tiles[0] = grid rows per workgroup of the x
  * transform / local-field kernels, tiles[1] = spectrum columns per workgroup
- * of the y transform, tiles[2] = of the z transform.  Results are identical
- * for every valid choice; only speed changes.  mmx_set_tiles rejects sizes
- * outside [1, n_y] / [1, n_x/2 + 1] or beyond 64 KiB of LDS per workgroup
+ * of the y transform, tiles[2] = of the z transform, or, for 3-D groups of
+ * at most 8 layers, of the fused y-z pass (which then takes no y tile).
+ * Results are identical for every valid choice; only speed changes.
+ * mmx_set_tiles rejects sizes outside [1, n_y] / [1, n_x/2 + 1] or beyond the
+ * LDS of a workgroup (64 KiB; the fused y-z pass: the device's maximum)
  * (MMX_EINVAL) and synchronises the stream.  mmx_autotune times one field
  * evaluation of every group (after mmx_build_demag) for candidate sizes
  * 1, 2, 4, ..., 32 per tile, keeps the fastest, and synchronises; it
  * overwrites the library's stage buffers, not caller arrays. */
 /* Execution path of mmx_heun.  MMX_PATH_STAGED: every field evaluation is
- * three (2-D) or five (3-D) launches over all replicas, with the spectrum in
+ * three (2-D and few-layer 3-D) or five (other 3-D) launches over all
+ * replicas, with the spectrum in
  * HBM.  MMX_PATH_FUSED: one workgroup per replica runs whole Heun steps with
  * the replica's half spectrum resident in LDS (2-D films whose spectrum, row
  * and column scratch fit the device's LDS per workgroup; mmx_heun returns

@@ -1,7 +1,8 @@
 // Hot-path kernels of the effective-field + LLG step (device code).
 //
-// One field evaluation of a replica group is three launches (2-D films) or
-// five (3-D blocks), all over every replica of the group at once:
+// One field evaluation of a replica group is three launches (2-D films and
+// 3-D blocks of at most 8 layers) or five (other 3-D blocks), all over every
+// replica of the group at once:
 //   k_xfwd   stage combine (RK45: m + dt sum a_sj k_j; optional
 //            normalisation) fused with the real-to-complex x transform of the
 //            zero-padded magnetisation (two real cells packed per complex
