@@ -11,12 +11,15 @@
 // lane q takes the N1-point DFTs over b for a = q, q + N1, ... in registers,
 // multiplies by w^(+-a c), the values are transposed through LDS so that lane
 // c holds all a, and an N2-point DFT over a leaves lane c the outputs
-// c + N1 d.  The inverse transform's output (the demag field of the row) is
-// staged in LDS, the lanes take the row's cells in coalesced order (x = q +
-// N1 j) and overwrite each cell's field with its new state, which is then
-// read back in the input order of the forward transform; one more LDS
-// exchange pairs X[k] with X[hx - k] for the real-to-complex split.  A row
-// thus crosses LDS a fixed handful of times instead of once per radix pass.
+// c + N1 d.  Each spectrum row is read once in coalesced order and paired
+// (S[k] with S[hx - k]) through LDS for the complex-to-real combination.  The
+// inverse transform's output (the demag field of the row) is staged in LDS,
+// the lanes take the row's cells in coalesced order (x = q + N1 j) and
+// overwrite each cell's field with its new state, which then leaves for HBM
+// in 16-byte pieces and is read back in the input order of the forward
+// transform; one more LDS exchange pairs X[k] with X[hx - k] for the
+// real-to-complex split.  A row thus crosses LDS a fixed handful of times
+// instead of once per radix pass.
 // The cell arithmetic is the one of k_fields; only the butterfly order of
 // the transforms differs.
 #pragma once
