@@ -133,3 +133,38 @@ def test_full_size_network(use_mfma):
     g = unpack_grads(gg, p, 4)
     for k in gref:
         assert _rel(g[k], gref[k]) < tol_g, (k, _rel(g[k], gref[k]))
+
+
+def test_adam_three_steps_match_oracle():
+    """Three Adam steps (t = 1, 2, 3: bias corrections beyond the first step)
+    on the network's packed parameters with a varying gradient history, FP32
+    on the GPU against the FP64 oracle's update of the same values."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    H, W, C, M1, M2, L, Cp = SMALL
+    p = _params(C, M1, M2, L, Cp, 5)
+    f = mmx.mmx_fno_create(H, W, C, M1, M2, L, Cp, 1, False)
+    try:
+        mmx.mmx_fno_set_stream(f, torch.cuda.current_stream().cuda_stream)
+        n = mmx.mmx_fno_param_count(f)
+        flat = pack(p, L)
+        rng = np.random.default_rng(21)
+        gs = [rng.standard_normal(n).astype(np.float32).astype(np.float64) * s
+              for s in (1.0, 0.3, 2.0)]
+        gs[1][: n // 4] *= -1.0
+        prm = torch.tensor(flat, dtype=torch.float32, device="cuda:0")
+        mom = torch.zeros(2 * n, dtype=torch.float32, device="cuda:0")
+        ref = {"x": flat.copy()}
+        state = {}
+        for t, g in enumerate(gs, start=1):
+            gd = torch.tensor(g, dtype=torch.float32, device="cuda:0")
+            mmx.mmx_fno_adam(f, prm, gd, mom, 1e-3, t)
+            ref = ofno.adam(ref, {"x": g}, state, 1e-3, t)
+            torch.cuda.synchronize()
+            got = prm.double().cpu().numpy()
+            # FP32 state: parameter values of O(1) carry 6e-8 relative rounding
+            # (a wrong bias correction at t >= 2 shifts steps of size lr = 1e-3 by
+            # a sizeable fraction of lr)
+            assert np.abs(got - ref["x"]).max() <= 2e-6, t
+    finally:
+        mmx.mmx_fno_destroy(f)

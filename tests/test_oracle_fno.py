@@ -92,3 +92,39 @@ def test_adam_training_lowers_the_loss():
         g = fno.backward(params, cs, h, t, M1, M2)
         params = fno.adam(params, g, state, 1e-2, it)
     assert fno.loss(fno.forward(params, m, M1, M2), t) < 0.5 * first
+
+
+def _adam_by_hand(g_seq, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """Adam written out step by step for one scalar (Kingma & Ba 2015,
+    Algorithm 1): the moments as explicit weighted sums of the gradient
+    history, m_t = (1 - b1) sum_s b1^(t-s) g_s and v_t = (1 - b2) sum_s
+    b2^(t-s) g_s^2, bias-corrected by 1 - b^t, one update per step."""
+    x, out = 0.0, []
+    for t in range(1, len(g_seq) + 1):
+        mt = (1 - b1) * sum(b1 ** (t - s) * g_seq[s - 1] for s in range(1, t + 1))
+        vt = (1 - b2) * sum(b2 ** (t - s) * g_seq[s - 1] ** 2 for s in range(1, t + 1))
+        x -= lr * (mt / (1 - b1 ** t)) / (np.sqrt(vt / (1 - b2 ** t)) + eps)
+        out.append(x)
+    return out
+
+
+def test_adam_matches_step_by_step_expansion_for_three_steps():
+    """Steps t = 1, 2, 3 with a varying gradient history (a sign change and a
+    gradient near eps), on a real array and on the real and imaginary parts of
+    a complex array, which Adam updates independently."""
+    seqs = [[1.0, -2.0, 0.5], [3e-3, 3e-3, -1e-9], [-0.7, 0.0, 4.0], [2.0, 2.0, 2.0]]
+    lr = 0.05
+    expect = np.array([_adam_by_hand(s, lr) for s in seqs])      # (4, 3)
+    params = {"w": np.zeros(4), "c": np.zeros(2, complex)}
+    state = {}
+    for t in range(1, 4):
+        g = {"w": np.array([s[t - 1] for s in seqs]),
+             "c": np.array([seqs[0][t - 1] + 1j * seqs[1][t - 1],
+                            seqs[2][t - 1] + 1j * seqs[3][t - 1]])}
+        params = fno.adam(params, g, state, lr, t)
+        assert np.allclose(params["w"], expect[:, t - 1], rtol=1e-13, atol=1e-16)
+        c = params["c"]
+        got = np.array([c[0].real, c[0].imag, c[1].real, c[1].imag])
+        assert np.allclose(got, expect[:, t - 1], rtol=1e-13, atol=1e-16)
+    # a constant gradient is bias-corrected exactly: every step moves by lr g/(|g| + eps)
+    assert np.allclose(np.diff([0.0] + list(expect[3])), -lr * 2.0 / (2.0 + 1e-8), rtol=1e-13)
