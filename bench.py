@@ -8,11 +8,12 @@ of every replica (two full field evaluations: demag FFT convolution, exchange,
 anisotropy, Zeeman, thermal, LLG torque, predictor and corrector) plus the
 switching-time update.
 
-Reported (one JSON line): batched cell-steps/s (replicas x cells x steps / s),
-the per-trial loop rate on the same GPU (the same kernels on single-replica
-contexts, one call per trial per step), the parity gate max |dm| between the
-two, the roofline of the dominant kernel from HIP-event timings, and the FP64
-oracle timed on the host cores.
+Reported (one JSON line): batched cell-steps/s (replicas x cells x steps / s;
+median of five timed runs of exactly --steps steps, with the paper's two-run
+subtraction beside it), the per-trial loop rate on the same GPU (the same
+kernels on single-replica contexts, the trials run one after the other), the
+parity gate max |dm| between the two, the roofline of the dominant kernel from
+HIP-event timings, and the FP64 oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -432,18 +433,17 @@ def bench_stt(args):
     el_r = time.perf_counter() - t0
     finished = counts.view(npts, per).double().mean(dim=1).cpu().numpy()
     mmx.mmx_destroy(ctx)
-    # per-trial loop: 32 single-replica contexts, one call per step each
-    trials, tsteps = 32, 200
+    # per-trial loop: 32 single-replica contexts, each trial one whole run
+    trials, tsteps = 32, 2000
     tctx = [_stt_macrospin_ctx(J[r:r + 1], seeds[r:r + 1], mmx.MMX_F32) for r in range(trials)]
     tm = [torch.tensor([[0.0, 0.0, 1.0]], dtype=torch.float32, device="cuda:0")
           for _ in range(trials)]
     for r in range(trials):
-        mmx.mmx_depondt(tctx[r], tm[r].clone(), dt, 1, 0, None)
+        mmx.mmx_depondt(tctx[r], tm[r].clone(), dt, tsteps, 0, None)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(tsteps):
-        for r in range(trials):
-            mmx.mmx_depondt(tctx[r], tm[r], dt, 1, k, None)
+    for r in range(trials):  # whole trials, one after the other
+        mmx.mmx_depondt(tctx[r], tm[r], dt, tsteps, 0, None)
     torch.cuda.synchronize()
     el_t = time.perf_counter() - t0
     for c in tctx:
@@ -558,31 +558,63 @@ def setup(R, prec, seeds, n=(64, 64, 1)):
     return ctx
 
 
-def cpu_baseline(seconds: float = 12.0):
-    """The FP64 oracle (numpy, single thread) on a bounded sample of the same
-    workload: 16 replicas advanced by Heun steps for about ``seconds``."""
+def _cpu_worker(job):
+    """One host process of the CPU baseline: the FP64 oracle advancing its own
+    replicas of the benchmark film by Heun steps on one thread."""
+    first, R, steps = job
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)
     from oracle import Grid, Material
     from oracle import integrators as oit
     from workloads import replica_seeds, uniform
-    from threadpoolctl import threadpool_limits
-    threadpool_limits(1)  # the sample runs on one host core
-    R = 16
     grid = Grid((64, 64, 1), (4e-9, 4e-9, 4e-9))
     mat = Material(Ms=8.0e5, A=1.3e-11, alpha=0.02, Ku=5e5, B=(0, 0, -0.15), T=300.0)
-    seeds = replica_seeds(3, R)
+    seeds = replica_seeds(3, first + R)[first:]
     m = uniform(grid.n, replicas=R)
     m = oit.heun_run(m, grid, mat, 1e-14, 1, seed=seeds, step0=0)  # builds the kernel
     t0 = time.perf_counter()
-    m = oit.heun_run(m, grid, mat, 1e-14, 2, seed=seeds, step0=1)
-    per_step = (time.perf_counter() - t0) / 2
-    steps = max(2, int(seconds / per_step))
+    oit.heun_run(m, grid, mat, 1e-14, steps, seed=seeds, step0=1)
+    return R * grid.ncells * steps, time.perf_counter() - t0
+
+
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(seconds: float = 12.0):
+    """The FP64 oracle (numpy) on a bounded sample of the same workload, run
+    on the host cores: one single-threaded process per core (at most 16, the
+    host share of one GPU), each advancing 2 replicas of its own for about
+    ``seconds``.  Called before anything touches the GPU, so the worker
+    processes are plain forks of a process without a HIP runtime."""
+    import multiprocessing as mp
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    workers = max(1, min(16, avail))
+    per_proc = 2
+    # calibrate the step count on one process
+    _, el = _cpu_worker((0, per_proc, 2))
+    steps = max(2, int(seconds / (el / 2)))
+    jobs = [(w * per_proc, per_proc, steps) for w in range(workers)]
     t0 = time.perf_counter()
-    oit.heun_run(m, grid, mat, 1e-14, steps, seed=seeds, step0=3)
-    el = time.perf_counter() - t0
-    return {"value": R * grid.ncells * steps / el, "unit": "cell-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"FP64 numpy oracle, {R} replicas x 64x64x1 cells x {steps} Heun steps "
-                      f"({el:.1f} s, single thread)"}
+    with mp.get_context("fork").Pool(workers) as pool:
+        res = pool.map(_cpu_worker, jobs)
+    wall = time.perf_counter() - t0
+    work = sum(r[0] for r in res)
+    slowest = max(r[1] for r in res)
+    return {"value": work / slowest, "unit": "cell-steps/s", "cores": workers,
+            "kind": "oracle", "nproc": os.cpu_count(), "cpu_model": _cpu_model(),
+            "sample": f"FP64 numpy oracle, {workers} single-threaded processes x {per_proc} "
+                      f"replicas of 64x64x1 cells x {steps} Heun steps (slowest process "
+                      f"{slowest:.1f} s of timed stepping, {wall:.1f} s with start-up)"}
 
 
 def main():
@@ -625,6 +657,9 @@ def main():
                           "throughput": bench_throughput,
                           "fields_ext": bench_fields_ext}[args.workload](args)))
         return
+    # the CPU baseline runs first: its worker processes are forked before
+    # this process initialises the GPU
+    cpu = None if args.no_cpu else cpu_baseline()
     import torch
     import paper_2608_15253_amd as mmx
     from workloads import replica_seeds, uniform
@@ -644,18 +679,23 @@ def main():
     tsw = torch.full((R,), -1.0, dtype=torch.float64, device=dev)
 
     # ---- per-trial loop (same kernels, single-replica contexts) ------------
+    # the trials run one after the other, each a whole run of K_t steps on its
+    # own context (one call, replaying that context's captured graphs)
     K_t = args.trial_steps
     trials = min(args.trials, R)
     tctx = [setup(1, prec, seeds[r:r + 1]) for r in range(trials)]
     tm = [torch.tensor(m0[r:r + 1], dtype=tdt, device=dev).contiguous() for r in range(trials)]
     tts = [torch.full((1,), -1.0, dtype=torch.float64, device=dev) for _ in range(trials)]
-    for r in range(trials):  # warm-up launch paths
-        mmx.mmx_heun(tctx[r], tm[r].clone(), dt, 1, 0, None)
+    for r in range(trials):  # warm-up (captures each context's graphs for K_t steps)
+        mmx.mmx_heun(tctx[r], tm[r], dt, K_t, 0, tts[r])
+    torch.cuda.synchronize()
+    for r in range(trials):  # back to the initial state, same arrays
+        tm[r].copy_(torch.tensor(m0[r:r + 1], dtype=tdt, device=dev))
+        tts[r].fill_(-1.0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(K_t):
-        for r in range(trials):
-            mmx.mmx_heun(tctx[r], tm[r], dt, 1, k, tts[r])
+    for r in range(trials):
+        mmx.mmx_heun(tctx[r], tm[r], dt, K_t, 0, tts[r])
     torch.cuda.synchronize()
     t_trial = time.perf_counter() - t0
     trial_rate = trials * N * K_t / t_trial
@@ -667,21 +707,43 @@ def main():
     for c in tctx:
         mmx.mmx_destroy(c)
 
-    # ---- timed batched run --------------------------------------------------
+    # ---- timed batched runs ---------------------------------------------------
+    # Every call replays captured graphs of its step sequence (kept between
+    # calls); the warm-up calls use the timed lengths, so no capture happens
+    # inside a timed region.  `value` is the median of REPEATS timed runs of
+    # exactly K steps, each bracketed by device synchronisations; the paper's
+    # protocol (two-run subtraction [t(2K) - t(K)] / K, median and IQR of
+    # REPEATS pairs) is reported beside it.
+    REPEATS = 5
+    K = args.steps
     step = K_t
-    mmx.mmx_heun(ctx, m, dt, args.warmup, step, tsw)
-    step += args.warmup
+    for n in (K, 2 * K, max(0, args.warmup - 3 * K)):
+        if n:
+            mmx.mmx_heun(ctx, m, dt, n, step, tsw)
+            step += n
     torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    mmx.mmx_heun(ctx, m, dt, args.steps, step, tsw)
-    ev1.record()
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t0
-    step += args.steps
-    t_ev = ev0.elapsed_time(ev1) / 1e3
-    batched_rate = R * N * args.steps / t_wall
+
+    def timed(n):
+        nonlocal step
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mmx.mmx_heun(ctx, m, dt, n, step, tsw)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        step += n
+        return el
+
+    t_runs = [timed(K) for _ in range(REPEATS)]
+    pairs = []
+    for _ in range(REPEATS):
+        t1 = timed(K)
+        t2 = timed(2 * K)
+        pairs.append((t2 - t1) / K)
+    q = lambda v, f: float(np.quantile(np.array(v), f))
+    t_wall = q(t_runs, 0.5)
+    ms_runs = [t / K * 1e3 for t in t_runs]
+    ms_pairs = [p * 1e3 for p in pairs]
+    batched_rate = R * N * K / t_wall
 
     # ---- per-kernel HIP-event timings over the same step sequence ----------
     mmx.mmx_profile_enable(ctx, 1)
@@ -710,6 +772,14 @@ def main():
         "metric": METRIC, "value": batched_rate, "unit": "cell-steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": t_wall / args.steps * 1e3, "higher_is_better": True,
+        "timing": {"repeats": REPEATS, "ms_per_step_runs": ms_runs,
+                   "ms_per_step_median": q(ms_runs, 0.5),
+                   "ms_per_step_iqr": [q(ms_runs, 0.25), q(ms_runs, 0.75)],
+                   "two_run_subtraction": {"N1": K, "N2": 2 * K,
+                                           "ms_per_step_median": q(ms_pairs, 0.5),
+                                           "ms_per_step_iqr": [q(ms_pairs, 0.25),
+                                                               q(ms_pairs, 0.75)]},
+                   "path": "captured HIP graphs replayed (runs of 2^i steps)"},
         "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
         "config": {"workload": "thermal_switching_64x64x1_R1024_heun", "replicas": R,
                    "grid": [nx, ny, 1], "cell_nm": 4, "dt_s": dt, "T_K": 300,
@@ -718,11 +788,11 @@ def main():
                       "steps": K_t, "seconds": t_trial},
         "speedup_vs_per_trial": batched_rate / trial_rate,
         "parity_max_dm_batched_vs_per_trial": gate,
-        "event_seconds": t_ev, "switched_replicas": switched, "simulated_steps": step,
+        "switched_replicas": switched, "simulated_steps": step,
         "tiles": list(tiles), "kernels": kernels, "roofline": roof,
     }
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline()
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out))
 
 

@@ -23,6 +23,17 @@
  *  - All device work is queued asynchronously on the stream given to
  *    mmx_set_stream (default: the null stream).  Calls that return host data
  *    (mmx_rk45 statistics, mmx_build_demag) synchronise that stream.
+ *  - Non-finite states: the Heun and rotation correctors (every kernel
+ *    variant), the single-cell kernels and the normalised RK4 update raise a
+ *    device flag when a new state has a non-finite component.  The
+ *    synchronising calls mmx_sync, mmx_rk45 and mmx_relax report it as
+ *    MMX_ENONFINITE (and clear it); work already queued is not undone.
+ *    mmx_rk45 also returns MMX_ENONFINITE when its step size fell to dt_min
+ *    on non-finite error estimates.
+ *  - Integrator calls replay captured HIP graphs of their step sequences
+ *    (kept between calls with the same arrays and configuration; every setter
+ *    call invalidates them), on a library stream ordered after and before the
+ *    bound stream by events.
  *  - One context per host thread at a time; calls on one context that overlap
  *    from several threads race.
  */
@@ -47,7 +58,7 @@ typedef enum {
   MMX_EHIP = -3,        /* HIP runtime error                                 */
   MMX_ESTATE = -4,      /* call out of order (e.g. demag not built)          */
   MMX_EUNSUP = -5,      /* valid but unsupported combination                 */
-  MMX_ENONFINITE = -6,  /* a non-finite value was produced on the device     */
+  MMX_ENONFINITE = -6,  /* a non-finite state was produced on the device     */
   MMX_EDTMIN = -8       /* adaptive step size fell below dt_min              */
 } mmx_status;
 
@@ -284,6 +295,11 @@ mmx_status mmx_relax(mmx_ctx* ctx, void* m, double torque_tol, double t_max, dou
 mmx_status mmx_rk45(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, double dt0,
                     const double* dt_replay, int64_t n_replay, void* energy_trace,
                     int64_t trace_cap, mmx_rk_stats* stats);
+
+/* Synchronises the bound stream; MMX_ENONFINITE if a corrector or a
+ * normalised update produced a non-finite state since the last check (the
+ * flag is cleared), else MMX_OK. */
+mmx_status mmx_sync(mmx_ctx* ctx);
 
 /* Accepted step sizes of the last mmx_rk45 call (host array, up to cap
  * entries); *count receives the number available. */

@@ -106,6 +106,7 @@ _SIGS = {
     "mmx_rk45": [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                  ctypes.POINTER(ctypes.c_double), ctypes.c_int64, _P, ctypes.c_int64,
                  ctypes.POINTER(mmx_rk_stats)],
+    "mmx_sync": [_P],
     "mmx_rk45_dts": [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
                      ctypes.POINTER(ctypes.c_int64)],
     "mmx_energy": [_P, _P, _P],
@@ -306,6 +307,12 @@ def mmx_rk45_surrogate(ctx, net, params, m, t0, t_end, tol, dt0=1e-14, gate_tol=
                                    int(gate_cap), ctypes.byref(st)))
     n = min(int(gate_cap), st.gate_checks)
     return st, [log[i] for i in range(n)]
+
+
+def mmx_sync(ctx) -> None:
+    """Synchronise the bound stream; raises MMXError (MMX_ENONFINITE) if a
+    non-finite state was produced since the last check."""
+    _check("mmx_sync", _lib.mmx_sync(ctx))
 
 
 def mmx_rk45_dts(ctx, cap=None):

@@ -6,10 +6,12 @@
 // the y transform + tensor product + inverse works on column chunks in place,
 // and the inverse x transform of row chunks feeds the local fields, torque and
 // Heun update directly.  HBM is touched only for the magnetisation itself
-// (stencil neighbours and the predictor state).  Each thread keeps the
-// predictor slope of its cells in a global buffer between the two Heun
-// stages (read back by the same thread).  The per-line arithmetic (transforms, tensor product,
-// local terms, torque, update) is the same as in the three-kernel path.
+// (stencil neighbours and the predictor state).  The corrector takes the
+// predictor's slope from the predictor state, (m + m~)/2 + dt/2 k, with the
+// epilogue of the three-kernel path (heun_correct), so no slope is stored.
+// The local terms, torque and update are those of the three-kernel path; the
+// transforms are LDS Stockham passes, so results agree with that path to
+// round-off, not bit for bit.
 #pragma once
 #include "common.h"
 #include "fft_lds.h"
@@ -32,7 +34,6 @@ struct HeunFusedArgs {
   int Ty, Py;
   T* m;                 // state, updated in place
   T* ms;                // predictor state (stencil source of the corrector)
-  T* k1;                // predictor slope
   double* tsw;          // switching times or null
   double dt;
   uint64_t step0;
@@ -215,23 +216,22 @@ __global__ void __launch_bounds__(kFusedBlock) k_heun_fused(HeunFusedArgs<T> a) 
           }
           T k[3];
           llg_torque(mc, H, f.gpm, f.alpha, k);
+          const T tau[3] = {0, 0, 0};
           if (stage == 0) {
+            T k1v[3], mn[3];
+            heun_predict(f, false, mc, H, k, tau, dt, k1v, mn);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-              a.k1[rb + (size_t)c * f.N + cell] = k[c];
-              a.ms[rb + (size_t)c * f.N + cell] = mc[c] + dt * k[c];
-            }
+            for (int c = 0; c < 3; ++c) a.ms[rb + (size_t)c * f.N + cell] = mn[c];
           } else {
             // own cell of m is read and written only by this thread here
-            T mo[3], k1v[3], mn[3];
+            T mo[3], mn[3];
+            const T k1v[3] = {0, 0, 0};
             ld3(a.m + rb, (unsigned)f.N, (unsigned)cell, mo);
-            ld3(a.k1 + rb, (unsigned)f.N, (unsigned)cell, k1v);
+            heun_correct(f, false, mc, H, k, tau, mo, k1v, dt, mn);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) mn[c] = mo[c] + T(0.5) * dt * (k1v[c] + k[c]);
-            const T inv = T(1) / sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) a.m[rb + (size_t)c * f.N + cell] = mn[c] * inv;
-            mz_acc += (double)(mn[2] * inv);
+            for (int c = 0; c < 3; ++c) a.m[rb + (size_t)c * f.N + cell] = mn[c];
+            if (f.nonfinite && !(fabs(mn[0]) + fabs(mn[1]) + fabs(mn[2]) <= T(3))) *f.nonfinite = 1;
+            mz_acc += (double)mn[2];
           }
         }
         __syncthreads();

@@ -138,6 +138,7 @@ struct XArgs {
   FftPlan plan;
   int nx, ny, nz, N, Sy, Kx, hx, L, xone;
   const int* done;
+  int* nonfinite;  // normalised combine: set to 1 if a combined state is not finite
 };
 
 template <typename T>
@@ -177,6 +178,7 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
         if (a.normalise) {
           const T inv = T(1) / sqrt(mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2]);
           mv[0] *= inv; mv[1] *= inv; mv[2] *= inv;
+          if (a.nonfinite && !(fabs(mv[0]) + fabs(mv[1]) + fabs(mv[2]) <= T(3))) *a.nonfinite = 1;
         }
         if (a.mout) {
 #pragma unroll
@@ -590,6 +592,7 @@ struct FArgs {
   // vector, polarisation, Lambda^2 and the field-like coefficient eps'
   int noprec;         // damping-only dynamics: the precession term is dropped
   int* nblk_out;      // Heun corrector: receives its workgroups per replica (partial-sum stride)
+  int* nonfinite;     // set to 1 by a corrector whose new state is not finite (null: no check)
   const double* Jrep;
   double stt_c;
   T sttp[3], stt_P, stt_L2, stt_e2;
@@ -840,6 +843,15 @@ __device__ inline void add_cross(const T m[3], const T t[3], T o[3]) {
   o[2] += m[0] * t[1] - m[1] * t[0];
 }
 
+// m_z of a corrected state for the per-workgroup sums of the switching
+// check, made non-finite when any component of the state is (x - x is 0 for
+// every finite x and NaN otherwise), so that the workgroup sum tells whether
+// the new state is finite without a separate reduction
+template <typename T>
+__device__ inline double mz_checked(const T mn[3]) {
+  return (double)(mn[2] + ((mn[0] - mn[0]) + (mn[1] - mn[1])));
+}
+
 // Heun-stage epilogues shared by the field kernels.  Predictor: m~ = m + dt k
 // (Heun; the slope is not kept) or k1 <- Omega, m~ = rotation of m by
 // dt Omega.  Corrector at m~ (mc) from the saved state mo: Heun's
@@ -1051,7 +1063,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
         mout_r[c * N + cell] = mn[c];
         if (fwd) F[(c * L + l) * 2 * hx + x] = mn[c];
       }
-      acc[0] += (double)mn[2];
+      acc[0] += mz_checked(mn);
     } else if (MODE == FM_RK7) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) out_r[c * N + cell] = k[c];
@@ -1103,6 +1115,8 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       } else {
         for (int v = 0; v < nv; ++v) a.partial[((size_t)r * nblk + blk) * nv + v] = red[v * kBlock];
         if (MODE == FM_HEUN2 && a.nblk_out && blk == 0 && r == 0) *a.nblk_out = (int)nblk;
+        if (MODE == FM_HEUN2 && a.nonfinite && !(fabs(red[0]) <= 1.7976931348623157e308))
+          *a.nonfinite = 1;
       }
     }
   }

@@ -92,6 +92,8 @@ __global__ void __launch_bounds__(256) k_macrospin(FArgs<T> a, T* m, double dt_d
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) m[(size_t)r * 3 + c] = mv[c];
+  // a non-finite state stays non-finite through later steps and resets
+  if (a.nonfinite && !(fabs(mv[0]) + fabs(mv[1]) + fabs(mv[2]) <= T(3))) *a.nonfinite = 1;
   if (tsw) tsw[r] = ts;
   if (refill) {
     rf.tgen[r] = (int)gen;

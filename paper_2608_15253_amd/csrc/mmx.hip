@@ -224,20 +224,57 @@ struct ProfScope {
 
 }  // namespace
 
+// Captured step sequences kept between calls: Heun / rotation runs of 2^i
+// steps (i < kHeunGraphs) and chunks of RK45 attempts, each valid for the
+// call signature it was captured with (the context's configuration epoch,
+// which every setter advances, and the arrays and scalars the captured
+// launches hold).
+constexpr int kHeunGraphs = 6;  // 1, 2, 4, ..., 32 steps
+struct GraphKey {
+  uint64_t epoch = 0;
+  const void* p[8] = {};
+  double d = 0;
+  long long i[4] = {};
+  bool operator==(const GraphKey& o) const {
+    if (epoch != o.epoch || d != o.d) return false;
+    for (int j = 0; j < 8; ++j)
+      if (p[j] != o.p[j]) return false;
+    for (int j = 0; j < 4; ++j)
+      if (i[j] != o.i[j]) return false;
+    return true;
+  }
+};
+struct GraphSet {
+  GraphKey key;
+  bool valid = false;
+  std::vector<hipGraphExec_t> exec;
+  std::vector<int> nblk;  // per group: workgroups per replica of its last corrector
+  void clear() {
+    for (auto& g : exec)
+      if (g) (void)hipGraphExecDestroy(g);
+    exec.clear();
+    nblk.clear();
+    valid = false;
+  }
+};
+
 struct mmx_ctx {
   Prof prof;
   int prec = MMX_F32;
   int path = MMX_PATH_AUTO;
   size_t max_lds = 64 * 1024;  // dynamic LDS per workgroup on this device
-  // graph replay: library stream, fencing events, step counter, last graph
+  // graph replay: library stream, fencing events, step counter, cached graphs
   hipStream_t cap_stream = nullptr;
   hipEvent_t ev_user = nullptr, ev_cap = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  GraphSet heun_graphs, rk_graphs;
+  uint64_t epoch = 1;  // configuration epoch: advanced by every setter
   DevBuf stepdev;
   const unsigned long long* cur_stepdev = nullptr;
+  DevBuf nfflag;  // int: set by kernels that produced a non-finite state
   ~mmx_ctx() {
     if (cap_stream) (void)hipStreamSynchronize(cap_stream);
-    if (gexec) (void)hipGraphExecDestroy(gexec);
+    heun_graphs.clear();
+    rk_graphs.clear();
     if (ev_user) (void)hipEventDestroy(ev_user);
     if (ev_cap) (void)hipEventDestroy(ev_cap);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -268,6 +305,32 @@ namespace {
 size_t esize(const mmx_ctx* c) { return c->prec == MMX_F64 ? 8 : 4; }
 
 mmx_status ensure_graph_stream(mmx_ctx* ctx);
+
+// Captures the launches `body` queues on ctx->stream into an executable graph
+// (*out), on the library's own stream (capture is not possible on the null
+// stream); nothing runs.
+template <typename F>
+mmx_status capture_graph(mmx_ctx* ctx, F&& body, hipGraphExec_t* out) {
+  hipStream_t user = ctx->stream, cs = ctx->cap_stream;
+  ctx->stream = cs;
+  hipGraph_t graph = nullptr;
+  mmx_status cap = MMX_OK;
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    cap = body();
+    e = hipStreamEndCapture(cs, &graph);
+  }
+  ctx->stream = user;
+  if (cap != MMX_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return cap;
+  }
+  if (e != hipSuccess) return fail(MMX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return fail(MMX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return MMX_OK;
+}
 
 template <typename T>
 size_t cpxb() { return sizeof(cpx<T>); }
@@ -478,6 +541,7 @@ struct Combine {
   double coef[6] = {0, 0, 0, 0, 0, 0};
   int kidx[6] = {0, 0, 0, 0, 0, 0};  // which k buffer (0..5)
   int normalise = 0;
+  int check_finite = 0;  // a normalised result that is a new state: flag non-finite values
   void* mout = nullptr;
 };
 
@@ -585,6 +649,7 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   }
   a.noprec = ctx->noprec;
   a.nblk_out = G.nblk_dev.p ? G.nblk_dev.as<int>() : nullptr;
+  a.nonfinite = ctx->nfflag.as<int>();
   a.rot = ctx->rot;
   if (ctx->refill) {
     a.tgen = G.tgen.as<int>();
@@ -720,6 +785,7 @@ mmx_status launch_xfwd(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb
   x.dth = dth;
   x.mout = reinterpret_cast<T*>(cb.mout);
   x.normalise = cb.normalise;
+  x.nonfinite = (cb.normalise && cb.check_finite) ? ctx->nfflag.as<int>() : nullptr;
   x.do_fft = demag ? 1 : 0;
   x.S = G.S.as<cpx<T>>();
   x.tw = G.tw_x.as<cpx<T>>();
@@ -1090,36 +1156,37 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
       if (h.done) break;
     }
   } else {
-    // the attempt sequence is static (dt, t and acceptance live on the device),
-    // so `chunk` attempts are captured once and replayed until done
+    // the attempt sequence is static (dt, t and acceptance live on the
+    // device), so `chunk` attempts are captured once (and kept for later
+    // calls with the same arrays and configuration) and replayed until done
     MMX_TRY(ensure_graph_stream(ctx));
     hipStream_t cs = ctx->cap_stream;
+    GraphKey key;
+    key.epoch = ctx->epoch;
+    key.p[0] = m;
+    key.p[1] = trace;
+    key.p[2] = replay ? ctx->replay.p : nullptr;
+    key.p[3] = ctx->dts.p;
+    key.p[4] = ctx->st.p;
+    key.p[5] = ctx->Etmp.p;
+    key.i[0] = cap;
+    key.i[1] = ctx->dts_cap;
+    GraphSet& gs = ctx->rk_graphs;
+    if (!gs.valid || !(gs.key == key)) {
+      HIP_TRY(hipStreamSynchronize(cs));
+      gs.clear();
+      gs.exec.assign(1, nullptr);
+      gs.key = key;
+      gs.valid = true;
+      MMX_TRY(capture_graph(ctx, [&]() -> mmx_status {
+        for (int i = 0; i < chunk; ++i) MMX_TRY(one_step());
+        return MMX_OK;
+      }, &gs.exec[0]));
+    }
     HIP_TRY(hipEventRecord(ctx->ev_user, s));
     HIP_TRY(hipStreamWaitEvent(cs, ctx->ev_user, 0));
-    if (ctx->gexec) {
-      HIP_TRY(hipStreamSynchronize(cs));
-      (void)hipGraphExecDestroy(ctx->gexec);
-      ctx->gexec = nullptr;
-    }
-    ctx->stream = cs;
-    hipGraph_t graph = nullptr;
-    mmx_status cap = MMX_OK;
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      for (int i = 0; i < chunk && cap == MMX_OK; ++i) cap = one_step();
-      e = hipStreamEndCapture(cs, &graph);
-    }
-    ctx->stream = s;
-    if (cap != MMX_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return cap;
-    }
-    if (e != hipSuccess) return fail(MMX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(MMX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
     for (;;) {
-      HIP_TRY(hipGraphLaunch(ctx->gexec, cs));
+      HIP_TRY(hipGraphLaunch(gs.exec[0], cs));
       HIP_TRY(hipMemcpyAsync(&h, ctx->st.p, sizeof(RkState), hipMemcpyDeviceToHost, cs));
       HIP_TRY(hipStreamSynchronize(cs));
       if (h.done) break;
@@ -1134,7 +1201,13 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
     stats->accepted = h.accepted;
     stats->rejected = h.rejected;
   }
-  if (h.dtmin_hit) return fail(MMX_EDTMIN, "step size fell below dt_min");
+  if (h.dtmin_hit) {
+    // every attempt down to dt_min failed on a non-finite error estimate: the
+    // state (or its derivative) is not finite, not merely too stiff
+    if (!(h.last_err == h.last_err))
+      return fail(MMX_ENONFINITE, "non-finite state or derivative in RK45 (step size fell to dt_min)");
+    return fail(MMX_EDTMIN, "step size fell below dt_min");
+  }
   return MMX_OK;
 }
 
@@ -1194,7 +1267,6 @@ mmx_status heun_fused(mmx_ctx* ctx, Group& G, const FusedTiles& ft, T* mg, doubl
   a.Py = G.Py;
   a.m = mg;
   a.ms = G.ms.as<T>();
-  a.k1 = G.k[0].as<T>();
   a.tsw = tsw;
   a.dt = dt;
   a.C = ft.C;
@@ -1471,49 +1543,64 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       MMX_TRY(spectrum_of(G, mb + G.off));
     }
   }
-  const int64_t chunk = 32;  // steps per captured graph
-  int64_t done_steps = 0;
-  if (n_steps >= 2 * chunk && !ctx->prof.on) {
-    // capture `chunk` steps once into a graph on the library's own stream
-    // (capture is not possible on the null stream) and replay it
+  if (!ctx->prof.on && n_steps > 0) {
+    // n_steps = a sum of runs of 2^i steps (i < kHeunGraphs, largest first);
+    // each run length is captured once into a graph (the step index lives in
+    // device memory and is advanced in the graph) and kept for later calls
+    // with the same arrays and configuration, so every call of any length
+    // replays captured steps
     MMX_TRY(ensure_graph_stream(ctx));
     hipStream_t user = ctx->stream, cs = ctx->cap_stream;
+    GraphKey key;
+    key.epoch = ctx->epoch;
+    key.p[0] = m;
+    key.p[1] = tsw;
+    key.p[2] = refill ? rf->m_init : nullptr;
+    key.p[3] = refill ? rf->times : nullptr;
+    key.p[4] = refill ? rf->counts : nullptr;
+    key.d = dt;
+    key.i[0] = rot;
+    key.i[1] = refill ? 1 : 0;
+    key.i[2] = refill ? rf->cap : 0;
+    GraphSet& gs = ctx->heun_graphs;
+    if (!gs.valid || !(gs.key == key)) {
+      HIP_TRY(hipStreamSynchronize(cs));
+      gs.clear();
+      gs.exec.assign(kHeunGraphs, nullptr);
+      gs.nblk.assign(ctx->groups.size(), 1);
+      gs.key = key;
+      gs.valid = true;
+    }
+    std::vector<int> runs;
+    for (int64_t left = n_steps; left > 0;) {
+      int i = kHeunGraphs - 1;
+      while ((int64_t(1) << i) > left) --i;
+      runs.push_back(i);
+      left -= int64_t(1) << i;
+    }
+    unsigned long long* sd = ctx->stepdev.as<unsigned long long>();
+    for (int i : runs) {
+      if (gs.exec[i]) continue;
+      ctx->cur_stepdev = sd;
+      const mmx_status st = capture_graph(ctx, [&]() -> mmx_status {
+        for (int j = 0; j < (1 << i); ++j) MMX_TRY(one_step(step0));
+        return MMX_OK;
+      }, &gs.exec[i]);
+      ctx->cur_stepdev = nullptr;
+      MMX_TRY(st);
+      for (int gi : staged) gs.nblk[gi] = ctx->groups[gi]->nblk_last;
+    }
     HIP_TRY(hipEventRecord(ctx->ev_user, user));
     HIP_TRY(hipStreamWaitEvent(cs, ctx->ev_user, 0));
-    unsigned long long* sd = ctx->stepdev.as<unsigned long long>();
     k_set_u64<<<1, 1, 0, cs>>>(sd, (unsigned long long)step0);
     HIP_TRY(hipGetLastError());
-    if (ctx->gexec) {
-      HIP_TRY(hipStreamSynchronize(cs));
-      (void)hipGraphExecDestroy(ctx->gexec);
-      ctx->gexec = nullptr;
-    }
-    ctx->stream = cs;
-    ctx->cur_stepdev = sd;
-    hipGraph_t graph = nullptr;
-    mmx_status cap = MMX_OK;
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-      for (int64_t i = 0; i < chunk && cap == MMX_OK; ++i) cap = one_step(step0);
-      e = hipStreamEndCapture(cs, &graph);
-    }
-    ctx->stream = user;
-    ctx->cur_stepdev = nullptr;
-    if (cap != MMX_OK) {
-      if (graph) (void)hipGraphDestroy(graph);
-      return cap;
-    }
-    if (e != hipSuccess) return fail(MMX_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&ctx->gexec, graph, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(graph);
-    if (e != hipSuccess) return fail(MMX_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
-    const int64_t reps = n_steps / chunk;
-    for (int64_t i = 0; i < reps; ++i) HIP_TRY(hipGraphLaunch(ctx->gexec, cs));
-    done_steps = reps * chunk;
+    for (int i : runs) HIP_TRY(hipGraphLaunch(gs.exec[i], cs));
     HIP_TRY(hipEventRecord(ctx->ev_cap, cs));
     HIP_TRY(hipStreamWaitEvent(user, ctx->ev_cap, 0));
+    for (int gi : staged) ctx->groups[gi]->nblk_last = gs.nblk[gi];
+  } else {
+    for (int64_t i = 0; i < n_steps; ++i) MMX_TRY(one_step(step0 + (uint64_t)i));
   }
-  for (int64_t i = done_steps; i < n_steps; ++i) MMX_TRY(one_step(step0 + (uint64_t)i));
   for (int gi : staged) {  // the last step's switching check
     if (!folds[gi]) continue;
     Group& G = *ctx->groups[gi];
@@ -1562,6 +1649,7 @@ mmx_status rk4_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps) {
         fc.kidx[j] = j;
       }
       fc.normalise = 1;
+      fc.check_finite = 1;
       fc.mout = mg;
       MMX_TRY(launch_xfwd<T>(ctx, G, mg, fc, false, nullptr, dt, nullptr));
     }
@@ -1700,6 +1788,19 @@ mmx_status topo_impl(mmx_ctx* ctx, const void* m, void* Q) {
 mmx_status check_ctx(const mmx_ctx* c) {
   if (!c) return fail(MMX_EINVAL, "null context");
   return MMX_OK;
+}
+
+// Synchronises the bound stream and reports (and clears) the device flag that
+// correctors and normalised combines set when they produce a non-finite state.
+mmx_status take_nonfinite(mmx_ctx* ctx) {
+  int f = 0;
+  HIP_TRY(hipMemcpyAsync(&f, ctx->nfflag.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (!f) return MMX_OK;
+  k_fill_i32<<<1, 64, 0, ctx->stream>>>(ctx->nfflag.as<int>(), 1, 0);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return fail(MMX_ENONFINITE, "a non-finite magnetisation was produced since the last check");
 }
 
 // ---------------------------------------------------------------------------
@@ -1909,6 +2010,8 @@ mmx_status mmx_create(const mmx_group* groups, int32_t n_groups, mmx_prec prec, 
   ctx->total_elems = off;
   HIP_TRY(ctx->st.alloc(sizeof(RkState)));
   HIP_TRY(hipMemset(ctx->st.p, 0, sizeof(RkState)));
+  HIP_TRY(ctx->nfflag.alloc(sizeof(int)));
+  HIP_TRY(hipMemset(ctx->nfflag.p, 0, sizeof(int)));
   *out = ctx.release();
   return MMX_OK;
 }
@@ -1927,6 +2030,7 @@ mmx_status mmx_set_stream(mmx_ctx* ctx, void* stream) {
 
 mmx_status mmx_set_material(mmx_ctx* ctx, int32_t group, const mmx_material* mat) {
   MMX_TRY(check_group_idx(ctx, group));
+  ctx->epoch++;
   if (!mat) return fail(MMX_EINVAL, "material is null");
   if (!(mat->Ms > 0)) return fail(MMX_EINVAL, "Ms must be > 0");
   if (mat->A < 0 || mat->alpha < 0) return fail(MMX_EINVAL, "A and alpha must be >= 0");
@@ -1940,6 +2044,7 @@ mmx_status mmx_set_material(mmx_ctx* ctx, int32_t group, const mmx_material* mat
 
 mmx_status mmx_set_material_ext(mmx_ctx* ctx, int32_t group, const mmx_material_ext* ext) {
   MMX_TRY(check_group_idx(ctx, group));
+  ctx->epoch++;
   if (!ext) return fail(MMX_EINVAL, "ext is null");
   Group& G = *ctx->groups[group];
   if (ext->Db != 0 && G.mat.A == 0) return fail(MMX_EINVAL, "bulk DMI needs A > 0 (edge condition)");
@@ -1964,6 +2069,7 @@ mmx_status mmx_set_material_ext(mmx_ctx* ctx, int32_t group, const mmx_material_
 
 mmx_status mmx_set_exchange_cells(mmx_ctx* ctx, int32_t group, const double* A) {
   MMX_TRY(check_group_idx(ctx, group));
+  ctx->epoch++;
   Group& G = *ctx->groups[group];
   if (!A) {
     HIP_TRY(G.Acell.alloc(0));
@@ -1986,6 +2092,7 @@ mmx_status mmx_set_exchange_cells(mmx_ctx* ctx, int32_t group, const double* A) 
 
 mmx_status mmx_set_terms(mmx_ctx* ctx, uint32_t mask) {
   MMX_TRY(check_ctx(ctx));
+  ctx->epoch++;
   if (mask & ~(uint32_t)MMX_ALL_TERMS) return fail(MMX_EINVAL, "unknown term bits");
   ctx->terms = mask;
   return MMX_OK;
@@ -1993,6 +2100,7 @@ mmx_status mmx_set_terms(mmx_ctx* ctx, uint32_t mask) {
 
 mmx_status mmx_set_field(mmx_ctx* ctx, int32_t group, const double B[3]) {
   MMX_TRY(check_group_idx(ctx, group));
+  ctx->epoch++;
   if (!B) return fail(MMX_EINVAL, "B is null");
   for (int c = 0; c < 3; ++c) ctx->groups[group]->B[c] = B[c];
   return MMX_OK;
@@ -2000,6 +2108,7 @@ mmx_status mmx_set_field(mmx_ctx* ctx, int32_t group, const double B[3]) {
 
 mmx_status mmx_set_thermal(mmx_ctx* ctx, int32_t group, const double* T, const uint64_t* seeds) {
   MMX_TRY(check_group_idx(ctx, group));
+  ctx->epoch++;
   if (!T || !seeds) return fail(MMX_EINVAL, "T and seeds must not be null");
   Group& G = *ctx->groups[group];
   for (int r = 0; r < G.R; ++r)
@@ -2014,6 +2123,7 @@ mmx_status mmx_set_thermal(mmx_ctx* ctx, int32_t group, const double* T, const u
 mmx_status mmx_set_stt(mmx_ctx* ctx, int32_t group, const double* J, const double p[3],
                        double P, double Lambda, double eps_prime) {
   MMX_TRY(check_group_idx(ctx, group));
+  ctx->epoch++;
   if (!J || !p) return fail(MMX_EINVAL, "J and p must not be null");
   const double pn = std::sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
   if (!(pn > 0) || !std::isfinite(pn)) return fail(MMX_EINVAL, "p must be a nonzero vector");
@@ -2034,6 +2144,7 @@ mmx_status mmx_set_stt(mmx_ctx* ctx, int32_t group, const double* J, const doubl
 
 mmx_status mmx_build_demag(mmx_ctx* ctx) {
   MMX_TRY(check_ctx(ctx));
+  ctx->epoch++;
   MMX_TRY(check_materials(ctx));
   for (auto& g : ctx->groups) {
     mmx_status s = (ctx->prec == MMX_F64) ? build_demag_group<double>(ctx, *g)
@@ -2078,6 +2189,7 @@ mmx_status mmx_rk4(mmx_ctx* ctx, void* m, double dt, int64_t n_steps) {
 
 mmx_status mmx_set_precession(mmx_ctx* ctx, int32_t on) {
   MMX_TRY(check_ctx(ctx));
+  ctx->epoch++;
   ctx->noprec = on ? 0 : 1;
   return MMX_OK;
 }
@@ -2090,9 +2202,10 @@ mmx_status mmx_relax(mmx_ctx* ctx, void* m, double torque_tol, double t_max, dou
   if (!(torque_tol >= 0) || !(t_max > 0) || !(tol > 0))
     return fail(MMX_EINVAL, "torque_tol >= 0, t_max > 0 and tol > 0 required");
   if (ctx->terms & MMX_THERMAL) return fail(MMX_EUNSUP, "thermal field in the relaxer");
-  return ctx->prec == MMX_F64
-             ? relax_impl<double>(ctx, m, torque_tol, t_max, tol, stats, max_torque_out)
-             : relax_impl<float>(ctx, m, torque_tol, t_max, tol, stats, max_torque_out);
+  MMX_TRY(ctx->prec == MMX_F64
+              ? relax_impl<double>(ctx, m, torque_tol, t_max, tol, stats, max_torque_out)
+              : relax_impl<float>(ctx, m, torque_tol, t_max, tol, stats, max_torque_out));
+  return take_nonfinite(ctx);
 }
 
 mmx_status mmx_depondt(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
@@ -2128,11 +2241,17 @@ mmx_status mmx_rk45(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, 
   MMX_TRY(check_materials(ctx));
   if (!m) return fail(MMX_EINVAL, "null array");
   if (!dt_replay && !(dt0 > 0)) return fail(MMX_EINVAL, "dt0 must be > 0");
-  return ctx->prec == MMX_F64
-             ? rk45_impl<double>(ctx, m, t0, t_end, tol, dt0, dt_replay, n_replay, energy_trace,
-                                 trace_cap, stats)
-             : rk45_impl<float>(ctx, m, t0, t_end, tol, dt0, dt_replay, n_replay, energy_trace,
-                                trace_cap, stats);
+  MMX_TRY(ctx->prec == MMX_F64
+              ? rk45_impl<double>(ctx, m, t0, t_end, tol, dt0, dt_replay, n_replay, energy_trace,
+                                  trace_cap, stats)
+              : rk45_impl<float>(ctx, m, t0, t_end, tol, dt0, dt_replay, n_replay, energy_trace,
+                                 trace_cap, stats));
+  return take_nonfinite(ctx);
+}
+
+mmx_status mmx_sync(mmx_ctx* ctx) {
+  MMX_TRY(check_ctx(ctx));
+  return take_nonfinite(ctx);
 }
 
 mmx_status mmx_rk45_dts(mmx_ctx* ctx, double* dts, int64_t cap, int64_t* count) {
@@ -2162,6 +2281,7 @@ mmx_status mmx_topological_charge(mmx_ctx* ctx, const void* m, void* Q) {
 
 mmx_status mmx_set_tiles(mmx_ctx* ctx, int32_t group, const int32_t tiles[3]) {
   MMX_TRY(check_group_idx(ctx, group));
+  ctx->epoch++;
   if (!tiles) return fail(MMX_EINVAL, "tiles is null");
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   Group& G = *ctx->groups[group];
@@ -2181,6 +2301,7 @@ mmx_status mmx_get_tiles(mmx_ctx* ctx, int32_t group, int32_t tiles[3]) {
 
 mmx_status mmx_set_path(mmx_ctx* ctx, int32_t path) {
   MMX_TRY(check_ctx(ctx));
+  ctx->epoch++;
   if (path != MMX_PATH_AUTO && path != MMX_PATH_STAGED && path != MMX_PATH_FUSED)
     return fail(MMX_EINVAL, "unknown path");
   ctx->path = path;
@@ -2189,6 +2310,7 @@ mmx_status mmx_set_path(mmx_ctx* ctx, int32_t path) {
 
 mmx_status mmx_autotune(mmx_ctx* ctx) {
   MMX_TRY(check_ctx(ctx));
+  ctx->epoch++;
   MMX_TRY(check_materials(ctx));
   return ctx->prec == MMX_F64 ? autotune_impl<double>(ctx) : autotune_impl<float>(ctx);
 }

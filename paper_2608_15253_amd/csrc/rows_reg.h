@@ -283,7 +283,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
         if (ROT) ld3(k1_r, N, cell, k1v);
         else k1v[0] = k1v[1] = k1v[2] = T(0);
         heun_correct(a, ROT, mc, H, kv, tau, mo, k1v, dt, mn_out);
-        acc += (double)mn_out[2];
+        acc += mz_checked(mn_out);
       }
     }
     // the new state is the forward transform's input; it replaces the field
@@ -341,6 +341,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
       const size_t nblk = (size_t)gridDim.x * gridDim.y;
       a.partial[(size_t)r * nblk + blk] = red[0];
       if (a.nblk_out && blk == 0 && r == 0) *a.nblk_out = (int)nblk;
+      if (a.nonfinite && !(fabs(red[0]) <= 1.7976931348623157e308)) *a.nonfinite = 1;
     }
   }
 }

@@ -242,35 +242,89 @@ def test_fused_path_matches_staged_and_oracle(name, prec):
 
 @pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
 def test_graph_replays_equal_eager_steps(prec):
-    """Long Heun runs replay a captured graph of 32 steps whose thermal-noise
-    step index lives in device memory; every replay must equal eager
-    one-step calls bit for bit, including the switching times, with eager
-    work and synchronisation between graph runs."""
+    """Heun runs replay captured graphs of 1, 2, 4, ..., 32 steps whose
+    thermal-noise step index lives in device memory, kept between calls; every
+    replay must equal eager steps (the profiling mode launches eagerly) bit
+    for bit, including the switching times, with eager work and
+    synchronisation between graph runs, calls of lengths that reuse and that
+    add captured runs, and a setter between calls (which must drop the
+    captured graphs: the changed field has to act)."""
     import paper_2608_15253_amd as mmx
     case = Case((40, 24, 1), (4e-9, 4e-9, 4e-9), R=3, alpha=0.5, Ku=1e5, B=(0, 0, -1.5),
                 T=300.0, seeds=list(replica_seeds(8, 3)),
                 terms=("exchange", "anisotropy", "zeeman", "demag", "thermal"))
     m0 = _round(uniform(case.n, (0.05, 0.0, 1.0), replicas=case.R), prec)
+    calls = [(70, 0), (3, 70), (20, 73), (96, 93), (1, 189), (20, 190)]
     res = {}
     for mode in ("graph", "eager"):
         ctx = open_ctx(case, prec)
         try:
             mmx.mmx_set_path(ctx, mmx.MMX_PATH_STAGED)
+            if mode == "eager":
+                mmx.mmx_profile_enable(ctx, 1)
             md = dev(m0, prec)
             ts = dev(-np.ones(case.R), 2)
-            if mode == "graph":
-                mmx.mmx_heun(ctx, md, 1e-13, 70, 0, ts)      # 2 replays + 6 eager
-                mmx.mmx_heun(ctx, md, 1e-13, 3, 70, ts)      # eager in between
-                host(md)
-                mmx.mmx_heun(ctx, md, 1e-13, 96, 73, ts)     # new capture, 3 replays
-            else:
-                for k in range(169):
-                    mmx.mmx_heun(ctx, md, 1e-13, 1, k, ts)
+            for i, (n, s0) in enumerate(calls):
+                if i == 4:
+                    mmx.mmx_set_field(ctx, 0, (0.0, 0.02, -1.4))
+                mmx.mmx_heun(ctx, md, 1e-13, n, s0, ts)
+                if i == 1:
+                    host(md)
             res[mode] = (host(md), host(ts))
         finally:
             mmx.mmx_destroy(ctx)
     assert np.array_equal(res["graph"][0], res["eager"][0])
     assert np.array_equal(res["graph"][1], res["eager"][1])
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_nonfinite_state_is_reported(prec):
+    """A NaN written into m from the host: the Heun corrector (register row
+    kernel in FP32), the rotation scheme, RK4 and the single-cell kernel flag
+    the non-finite state and mmx_sync returns MMX_ENONFINITE once (the flag is
+    cleared); RK45 returns MMX_ENONFINITE instead of MMX_EDTMIN; finite runs
+    report nothing."""
+    import paper_2608_15253_amd as mmx
+    case = Case((64, 32, 1), (4e-9, 4e-9, 4e-9), R=2, alpha=0.1, Ku=5e5, B=(0, 0, -0.1),
+                terms=("exchange", "anisotropy", "zeeman", "demag"))
+    m0 = _round(uniform(case.n, (0.1, 0.0, 1.0), replicas=case.R), prec)
+    bad = m0.copy()
+    bad[1, 0, 0, 5, 7] = np.nan
+    ctx = open_ctx(case, prec)
+    try:
+        for run in ("heun", "depondt", "rk4"):
+            md = dev(m0, prec)
+            getattr(mmx, "mmx_" + run)(ctx, md, 1e-14, 3, *([0] if run != "rk4" else []))
+            mmx.mmx_sync(ctx)                       # finite: no error
+            md = dev(bad, prec)
+            getattr(mmx, "mmx_" + run)(ctx, md, 1e-14, 3, *([0] if run != "rk4" else []))
+            with pytest.raises(mmx.MMXError) as e:
+                mmx.mmx_sync(ctx)
+            assert e.value.status == -6, run
+            mmx.mmx_sync(ctx)                       # cleared
+        md = dev(bad, prec)
+        with pytest.raises(mmx.MMXError) as e:
+            mmx.mmx_rk45(ctx, md, 0.0, 1e-12, 1e-6)
+        assert e.value.status == -6
+    finally:
+        mmx.mmx_destroy(ctx)
+    # single-cell macrospins (one thread per replica)
+    ms = Case((1, 1, 1), (4e-9, 4e-9, 4e-9), R=4, alpha=0.1, Ku=5e5, B=(0, 0, -0.1),
+              terms=("anisotropy", "zeeman"))
+    mm = np.tile(np.array([0.1, 0.0, 1.0]) / np.hypot(0.1, 1.0), (4, 1)).reshape(4, 3, 1, 1, 1)
+    ctx = open_ctx(ms, prec)
+    try:
+        md = dev(mm, prec)
+        mmx.mmx_heun(ctx, md, 1e-13, 10, 0)
+        mmx.mmx_sync(ctx)
+        mm[2, 1] = np.inf
+        md = dev(mm, prec)
+        mmx.mmx_heun(ctx, md, 1e-13, 10, 0)
+        with pytest.raises(mmx.MMXError) as e:
+            mmx.mmx_sync(ctx)
+        assert e.value.status == -6
+    finally:
+        mmx.mmx_destroy(ctx)
 
 
 @pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
@@ -287,7 +341,7 @@ def test_uneven_groups_in_one_context(prec):
              for g, (n, R) in enumerate(shapes)]
     m0s = [_round(uniform(c.n, (0.1, 0.0, 1.0), replicas=c.R), prec) for c in cases]
     flat = np.concatenate([m.ravel() for m in m0s])
-    nsteps, dt = 70, 1e-14      # >= 64 steps: the captured-graph path
+    nsteps, dt = 70, 1e-14      # captured runs of 64, 4 and 2 steps
     ctx = open_ctx(cases[0], prec, groups=cases)
     try:
         md = dev(flat, prec)
