@@ -315,6 +315,20 @@ mmx_status mmx_energy(mmx_ctx* ctx, const void* m, void* E);
  * differences (periodic wrap, the cell itself beyond open edges). */
 mmx_status mmx_topological_charge(mmx_ctx* ctx, const void* m, void* Q);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the charges of
+ * mmx_topological_charge, equal to them bit for bit, computed with the
+ * per-workgroup partial sums in a static device array of the library (1 MiB
+ * per device, 131072 doubles, reserved when the library is loaded and set up
+ * by mmx_create, held until the process ends) instead of a buffer allocated
+ * per call.  Allocates nothing and does not synchronise: the result is
+ * queued on the bound stream.  The array is shared by every context on a
+ * device, so calls on one device that overlap (several streams or host
+ * threads) race; calls queued on one stream are ordered.  MMX_EINVAL if a
+ * group needs more partial sums (replicas x min(256, ceil(n_x n_y / 256)))
+ * than the array holds, before anything is launched. */
+mmx_status mmx_topological_charge_noalloc(mmx_ctx* ctx, const void* m, void* Q);
+
 /* Tile sizes of group g: tiles[0] = grid rows per workgroup of the x
  * transform / local-field kernels, tiles[1] = spectrum columns per workgroup
  * of the y transform, tiles[2] = of the z transform, or, for 3-D groups of

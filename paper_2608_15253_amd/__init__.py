@@ -111,6 +111,7 @@ _SIGS = {
                      ctypes.POINTER(ctypes.c_int64)],
     "mmx_energy": [_P, _P, _P],
     "mmx_topological_charge": [_P, _P, _P],
+    "mmx_topological_charge_noalloc": [_P, _P, _P],
     "mmx_fno_create": [ctypes.c_int32] * 9 + [ctypes.POINTER(_P)],
     "mmx_fno_set_stream": [_P, _P],
     "mmx_fno_param_count": [_P, ctypes.POINTER(ctypes.c_int64)],
@@ -333,6 +334,13 @@ def mmx_topological_charge(ctx, m, Q) -> None:
 
 
 MMX_PATH_AUTO, MMX_PATH_STAGED, MMX_PATH_FUSED = 0, 1, 2
+
+
+def mmx_topological_charge_noalloc(ctx, m, Q) -> None:
+    """Topological charges with the library's static scratch (no allocation,
+    no synchronisation)."""
+    _check("mmx_topological_charge_noalloc",
+           _lib.mmx_topological_charge_noalloc(ctx, _ptr(m), _ptr(Q)))
 
 
 def mmx_set_path(ctx, path) -> None:

@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -20,6 +21,14 @@
 #include "rows_reg.h"
 
 using namespace mmx;
+
+// Per-workgroup partial sums of mmx_topological_charge_noalloc live in this
+// file-scope array: 1 MiB (131072 doubles) on every device the library runs
+// on, held until the process ends.  Host code never passes its name to a
+// kernel (on the host it is a stand-in, not a device address); it uses the
+// device address taken once per device by scratch_init.
+constexpr size_t kScratchDoubles = size_t(1) << 17;
+static __device__ __align__(256) double scratch[kScratchDoubles];
 
 namespace {
 
@@ -261,6 +270,8 @@ struct GraphSet {
 struct mmx_ctx {
   Prof prof;
   int prec = MMX_F32;
+  int device = 0;              // HIP device the context was created on
+  double* scratch = nullptr;   // device address of `scratch` on that device
   int path = MMX_PATH_AUTO;
   size_t max_lds = 64 * 1024;  // dynamic LDS per workgroup on this device
   // graph replay: library stream, fencing events, step counter, cached graphs
@@ -1760,6 +1771,36 @@ mmx_status energy_impl(mmx_ctx* ctx, const void* m, void* E) {
   return MMX_OK;
 }
 
+// workgroups per replica of the topological-charge kernel
+int topo_blocks(const Group& G) {
+  const int plane = G.nx * G.ny;
+  return std::max(1, std::min(256, (plane + kBlock - 1) / kBlock));
+}
+
+// Q of every replica with the per-workgroup partial sums in `part` (reused
+// from its start by every group, in stream order); no allocation, no
+// synchronisation
+template <typename T>
+mmx_status topo_into(mmx_ctx* ctx, const void* m, void* Q, double* part) {
+  const T* mb = reinterpret_cast<const T*>(m);
+  double* Qb = reinterpret_cast<double*>(Q);
+  int roff = 0;
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    const int nblk = topo_blocks(G);
+    dim3 grid(nblk, G.R);
+    k_topo<T><<<grid, kBlock, 0, ctx->stream>>>(mb + G.off, G.nx, G.ny, G.N, G.g.pbc[0],
+                                                G.g.pbc[1], 1.0 / (2 * G.g.cell[0]),
+                                                1.0 / (2 * G.g.cell[1]), part, nblk);
+    HIP_TRY(hipGetLastError());
+    k_topo_reduce<<<(G.R + 63) / 64, 64, 0, ctx->stream>>>(
+        part, nblk, G.R, G.g.cell[0] * G.g.cell[1] / (4 * kPi), Qb + roff);
+    HIP_TRY(hipGetLastError());
+    roff += G.R;
+  }
+  return MMX_OK;
+}
+
 template <typename T>
 mmx_status topo_impl(mmx_ctx* ctx, const void* m, void* Q) {
   const T* mb = reinterpret_cast<const T*>(m);
@@ -1767,8 +1808,7 @@ mmx_status topo_impl(mmx_ctx* ctx, const void* m, void* Q) {
   int roff = 0;
   for (auto& gp : ctx->groups) {
     Group& G = *gp;
-    const int plane = G.nx * G.ny;
-    const int nblk = std::max(1, std::min(256, (plane + kBlock - 1) / kBlock));
+    const int nblk = topo_blocks(G);
     DevBuf part;
     HIP_TRY(part.alloc((size_t)G.R * nblk * sizeof(double)));
     dim3 grid(nblk, G.R);
@@ -1787,6 +1827,26 @@ mmx_status topo_impl(mmx_ctx* ctx, const void* m, void* Q) {
 
 mmx_status check_ctx(const mmx_ctx* c) {
   if (!c) return fail(MMX_EINVAL, "null context");
+  return MMX_OK;
+}
+
+// Device address of the static scratch array on each device (taken once per
+// device, with that device current).
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+mmx_status scratch_init(int dev, double** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(MMX_EUNSUP, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(MMX_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = g_scratch_dev[dev];
   return MMX_OK;
 }
 
@@ -1996,6 +2056,8 @@ mmx_status mmx_create(const mmx_group* groups, int32_t n_groups, mmx_prec prec, 
   auto ctx = std::make_unique<mmx_ctx>();
   ctx->prec = prec;
   ctx->max_lds = prop.sharedMemPerBlock;
+  ctx->device = dev;
+  MMX_TRY(scratch_init(dev, &ctx->scratch));
   size_t off = 0;
   for (int i = 0; i < n_groups; ++i) {
     auto G = std::make_unique<Group>();
@@ -2277,6 +2339,23 @@ mmx_status mmx_topological_charge(mmx_ctx* ctx, const void* m, void* Q) {
   MMX_TRY(check_ctx(ctx));
   if (!m || !Q) return fail(MMX_EINVAL, "null array");
   return ctx->prec == MMX_F64 ? topo_impl<double>(ctx, m, Q) : topo_impl<float>(ctx, m, Q);
+}
+
+mmx_status mmx_topological_charge_noalloc(mmx_ctx* ctx, const void* m, void* Q) {
+  MMX_TRY(check_ctx(ctx));
+  if (!m || !Q) return fail(MMX_EINVAL, "null array");
+  if (!ctx->scratch) return fail(MMX_ESTATE, "static scratch not set up");
+  for (auto& gp : ctx->groups) {
+    const size_t need = (size_t)gp->R * topo_blocks(*gp);
+    if (need > kScratchDoubles)
+      return fail(MMX_EINVAL, "mmx_topological_charge_noalloc: a group needs " +
+                                  std::to_string(need) + " partial sums (replicas x " +
+                                  std::to_string(topo_blocks(*gp)) +
+                                  " workgroups), above the static scratch of " +
+                                  std::to_string(kScratchDoubles));
+  }
+  return ctx->prec == MMX_F64 ? topo_into<double>(ctx, m, Q, ctx->scratch)
+                              : topo_into<float>(ctx, m, Q, ctx->scratch);
 }
 
 mmx_status mmx_set_tiles(mmx_ctx* ctx, int32_t group, const int32_t tiles[3]) {
