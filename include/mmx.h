@@ -11,9 +11,14 @@
  *  - Units are SI: metres, A/m, J/m, J/m^2, J/m^3, tesla, kelvin, seconds.
  *  - Device arrays are owned by the caller (e.g. torch tensors), are not
  *    freed or retained by the library, and must stay alive until the work
- *    queued on the bound stream has finished.  The library owns its context
- *    and the device buffers it allocates in mmx_create / mmx_build_demag
- *    (plans, tensor spectrum, stage buffers); mmx_destroy frees them.
+ *    queued on the bound stream has finished.  Every device buffer of a
+ *    context (twiddle tables, tensor spectrum, stage buffers, controller
+ *    state, partial sums) is a region of one workspace of
+ *    mmx_workspace_bytes bytes, allocated by mmx_create and freed by
+ *    mmx_destroy unless the caller supplies its own with mmx_bind; after
+ *    mmx_create no call allocates device memory except mmx_build_demag
+ *    (its FP64 tensor staging, freed before it returns) and the network
+ *    calls (mmx_fno_*, which own their buffers).
  *  - Magnetisation layout ("D1", Results "A replica-batched engine" and the
  *    replica-batching figure legend: replica-outermost, component-major,
  *    x-fastest): group g, replica r, component c, cell (x, y, z) lives at
@@ -124,6 +129,21 @@ void mmx_destroy(mmx_ctx* ctx);
 
 /* Binds the HIP stream (hipStream_t passed as void*) used by every later call. */
 mmx_status mmx_set_stream(mmx_ctx* ctx, void* hip_stream);
+
+/* Size in bytes of the context's device workspace (all of its device
+ * buffers; Methods, "GPU implementation": state and stage buffers stay on the
+ * device, with no per-step transfer). */
+mmx_status mmx_workspace_bytes(const mmx_ctx* ctx, size_t* bytes);
+
+/* Moves the context's workspace into caller-owned device memory `ws` (at
+ * least mmx_workspace_bytes bytes, 256-byte aligned, e.g. a torch tensor;
+ * the caller keeps it alive until mmx_destroy or the next mmx_bind) and binds
+ * `hip_stream` like mmx_set_stream.  Synchronises the previous stream, copies
+ * the current contents (tensor spectrum, tables, parameters) and frees the
+ * library's own allocation; captured graphs are dropped.  ws = null moves the
+ * workspace back into a library allocation.  MMX_EINVAL for a short or
+ * misaligned workspace. */
+mmx_status mmx_bind(mmx_ctx* ctx, void* ws, size_t bytes, void* hip_stream);
 
 /* Material of group g (Methods, "Physics and discretization"). */
 mmx_status mmx_set_material(mmx_ctx* ctx, int32_t group, const mmx_material* mat);
@@ -300,6 +320,34 @@ mmx_status mmx_rk45(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, 
  * normalised update produced a non-finite state since the last check (the
  * flag is cleared), else MMX_OK. */
 mmx_status mmx_sync(mmx_ctx* ctx);
+
+/* Checkpoint of an adaptive run (Methods, "Integrators"): after mmx_rk45 or
+ * mmx_rk45_resume (not a dt replay), the controller state (time, the last
+ * step-size proposal before clipping to t_end, last error, step counts) and
+ * the first-same-as-last slope k1 of every replica (device values of the
+ * final state), as a host blob: header, then k1 in layout D1 with the
+ * context's element type.  blob = null: *bytes receives the size.  The
+ * magnetisation itself is the caller's array and is not included.
+ * Synchronous.  MMX_ESTATE if no adaptive run precedes it, or another
+ * integrator or a setter was called since (they reuse the stage buffers or
+ * change the dynamics). */
+mmx_status mmx_checkpoint(const mmx_ctx* ctx, void* host_blob, size_t* bytes);
+
+/* Loads a checkpoint into a context of the same precision and groups (same
+ * mmx_group descriptions; materials, field and terms must be set as when it
+ * was taken); the next mmx_rk45_resume continues from it.  Synchronous.
+ * MMX_EINVAL for a blob that is not a checkpoint or too short, MMX_ESHAPE
+ * for another layout. */
+mmx_status mmx_restore(mmx_ctx* ctx, const void* host_blob, size_t bytes);
+
+/* Continues the adaptive run of the last mmx_rk45 / mmx_rk45_resume call or
+ * of the restored checkpoint from its time and step-size proposal to t_end,
+ * with the saved first-same-as-last slope as the first stage (m must be the
+ * state the run ended in); arguments, output and errors as mmx_rk45.  A run
+ * continued in a context restored from a checkpoint equals its continuation
+ * in the original context bit for bit. */
+mmx_status mmx_rk45_resume(mmx_ctx* ctx, void* m, double t_end, double tol, void* energy_trace,
+                           int64_t trace_cap, mmx_rk_stats* stats);
 
 /* Accepted step sizes of the last mmx_rk45 call (host array, up to cap
  * entries); *count receives the number available. */

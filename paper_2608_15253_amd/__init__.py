@@ -107,6 +107,12 @@ _SIGS = {
                  ctypes.POINTER(ctypes.c_double), ctypes.c_int64, _P, ctypes.c_int64,
                  ctypes.POINTER(mmx_rk_stats)],
     "mmx_sync": [_P],
+    "mmx_workspace_bytes": [_P, ctypes.POINTER(ctypes.c_size_t)],
+    "mmx_bind": [_P, _P, ctypes.c_size_t, _P],
+    "mmx_checkpoint": [_P, _P, ctypes.POINTER(ctypes.c_size_t)],
+    "mmx_restore": [_P, _P, ctypes.c_size_t],
+    "mmx_rk45_resume": [_P, _P, ctypes.c_double, ctypes.c_double, _P, ctypes.c_int64,
+                        ctypes.POINTER(mmx_rk_stats)],
     "mmx_rk45_dts": [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_int64,
                      ctypes.POINTER(ctypes.c_int64)],
     "mmx_energy": [_P, _P, _P],
@@ -314,6 +320,41 @@ def mmx_sync(ctx) -> None:
     """Synchronise the bound stream; raises MMXError (MMX_ENONFINITE) if a
     non-finite state was produced since the last check."""
     _check("mmx_sync", _lib.mmx_sync(ctx))
+
+
+def mmx_workspace_bytes(ctx) -> int:
+    n = ctypes.c_size_t()
+    _check("mmx_workspace_bytes", _lib.mmx_workspace_bytes(ctx, ctypes.byref(n)))
+    return n.value
+
+
+def mmx_bind(ctx, workspace, stream) -> None:
+    """Move the context's device workspace into ``workspace`` (a device tensor
+    of at least mmx_workspace_bytes bytes, or None for a library allocation)
+    and bind ``stream``."""
+    nbytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    _check("mmx_bind", _lib.mmx_bind(ctx, _ptr(workspace), nbytes, stream))
+
+
+def mmx_checkpoint(ctx) -> bytes:
+    n = ctypes.c_size_t()
+    _check("mmx_checkpoint", _lib.mmx_checkpoint(ctx, None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check("mmx_checkpoint", _lib.mmx_checkpoint(ctx, buf, ctypes.byref(n)))
+    return buf.raw[:n.value]
+
+
+def mmx_restore(ctx, blob: bytes) -> None:
+    buf = ctypes.create_string_buffer(blob, len(blob))
+    _check("mmx_restore", _lib.mmx_restore(ctx, buf, len(blob)))
+
+
+def mmx_rk45_resume(ctx, m, t_end, tol, energy_trace=None, trace_cap=0) -> mmx_rk_stats:
+    st = mmx_rk_stats()
+    _check("mmx_rk45_resume", _lib.mmx_rk45_resume(ctx, _ptr(m), float(t_end), float(tol),
+                                                   _ptr(energy_trace), int(trace_cap),
+                                                   ctypes.byref(st)))
+    return st
 
 
 def mmx_rk45_dts(ctx, cap=None):

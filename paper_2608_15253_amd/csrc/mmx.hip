@@ -135,6 +135,13 @@ struct DevBuf {
   template <typename U> U* as() const { return reinterpret_cast<U*>(p); }
 };
 
+// A region of the context's device arena (not owned; see arena_layout).
+struct Buf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <typename U> U* as() const { return reinterpret_cast<U*>(p); }
+};
+
 struct Group {
   mmx_group g{};
   int nx = 1, ny = 1, nz = 1, N = 1, R = 1;
@@ -147,13 +154,16 @@ struct Group {
   int mat_set = 0;
   double B[3] = {0, 0, 0};
   size_t off = 0;  // element offset of this group in caller arrays
-  // device buffers
-  DevBuf tw_x, wpost, tw_y, tw_z, Nt, S, ms, m7, k[7], Trep, seeds, partial, E;
-  DevBuf tgen, tstart, tflag, S_init;  // retire/refill trials
-  DevBuf Jrep;  // spin-transfer current density per replica (A/m^2)
+  // device buffers (regions of the context's arena)
+  Buf tw_x, wpost, tw_y, tw_z, Nt, S, ms, m7, k[7], Trep, seeds, partial, E;
+  Buf tgen, tstart, tflag, S_init;  // retire/refill trials
+  Buf Jrep;  // spin-transfer current density per replica (A/m^2)
   mmx_material_ext ext{};  // bulk DMI, cubic anisotropy, RKKY
-  DevBuf Acell;            // per-cell exchange stiffness (T[N]) or empty
-  DevBuf nblk_dev;         // int: the last corrector's workgroups per replica
+  Buf Acell;               // per-cell exchange stiffness (T[N]), used if acell_on
+  Buf nblk_dev;            // int: the last corrector's workgroups per replica
+  Buf topo_part;           // per-workgroup partial sums of the topological charge
+  int acell_on = 0, jrep_on = 0;
+  std::vector<std::vector<unsigned char>> tables;  // host twiddle tables (tw_x, wpost, tw_y, tw_z)
   double stt_p[3] = {0, 0, 1}, stt_P = 0, stt_lambda = 1, stt_eps2 = 0;
   int nblk = 1;       // k_fields workgroups per replica
   int nblk_last = 1;  // workgroups per replica of the last field-kernel launch
@@ -279,9 +289,9 @@ struct mmx_ctx {
   hipEvent_t ev_user = nullptr, ev_cap = nullptr;
   GraphSet heun_graphs, rk_graphs;
   uint64_t epoch = 1;  // configuration epoch: advanced by every setter
-  DevBuf stepdev;
+  Buf stepdev;
   const unsigned long long* cur_stepdev = nullptr;
-  DevBuf nfflag;  // int: set by kernels that produced a non-finite state
+  Buf nfflag;  // int: set by kernels that produced a non-finite state
   ~mmx_ctx() {
     if (cap_stream) (void)hipStreamSynchronize(cap_stream);
     heun_graphs.clear();
@@ -289,24 +299,36 @@ struct mmx_ctx {
     if (ev_user) (void)hipEventDestroy(ev_user);
     if (ev_cap) (void)hipEventDestroy(ev_cap);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
+    if (arena && arena_owned) (void)hipFree(arena);
   }
   std::vector<std::unique_ptr<Group>> groups;
   uint32_t terms = MMX_EXCH | MMX_DMI_INTERFACIAL | MMX_ANIS_UNIAXIAL | MMX_ZEEMAN | MMX_DEMAG;
   hipStream_t stream = nullptr;
   size_t total_elems = 0;
-  DevBuf st;       // RkState
-  DevBuf dts;      // accepted step sizes
-  DevBuf replay;   // dt replay list
+  // every device buffer of the context is a region of one arena: allocated by
+  // mmx_create (owned) or supplied by the caller through mmx_bind
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+  bool arena_owned = false;
+  Buf st;          // RkState
+  Buf dts;         // accepted step sizes
+  Buf replay;      // dt replay list
   long long dts_cap = 0;
   long long last_accepted = 0;
-  DevBuf Etmp;     // per-replica energies for traces
+  Buf Etmp;        // per-replica energies for traces
   // learned-demag stages: network field input and exact-demag output of k_fields
   const float* hext = nullptr;
   double hext_scale = 0, hext_mz = 0;
   void* hd_out = nullptr;
-  DevBuf sg_h, sg_hd, sg_part, sg_err;  // surrogate integrator buffers
+  Buf sg_h, sg_hd, sg_part, sg_err;  // surrogate integrator buffers (FP32 one-film contexts)
   int noprec = 0;  // damping-only dynamics (mmx_set_precession(ctx, 0), mmx_relax)
-  DevBuf maxbuf;   // max-reduction partials (mmx_relax)
+  Buf maxbuf;      // max-reduction partials (mmx_relax)
+  // controller state and FSAL slope (k[0] of every group) left by the last
+  // adaptive run, valid for continuation while the configuration epoch is
+  // unchanged and no other integrator has used the stage buffers
+  RkState rk_last{};
+  int rk_valid = 0;
+  uint64_t rk_epoch = 0;
   int rot = 0;     // Heun epilogues take the rotation update (mmx_depondt*)
   int refill = 0;  // per-replica trial generation and start step (mmx_depondt_refill)
 };
@@ -453,43 +475,118 @@ mmx_status setup_group(mmx_ctx* ctx, Group& G) {
       if (W <= G.Kx && lds_yz<T>(G, W) <= G.max_lds / 4) { G.Wz = W; break; }
     MMX_TRY(yz_attr<T>(G));
   }
-  // twiddles
-  auto up = [&](DevBuf& b, const void* src, size_t bytes) -> mmx_status {
-    HIP_TRY(b.alloc(bytes));
-    HIP_TRY(hipMemcpy(b.p, src, bytes, hipMemcpyHostToDevice));
-    return MMX_OK;
+  // twiddle tables, uploaded into the arena by arena_init
+  auto keep = [&](const std::vector<cpx<T>>& t) {
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(t.data());
+    G.tables.emplace_back(b, b + t.size() * sizeof(cpx<T>));
   };
-  {
-    auto t = twiddles<T>(G.hx, G.hx);
-    MMX_TRY(up(G.tw_x, t.data(), t.size() * cpxb<T>()));
-    auto w = twiddles<T>(G.xone ? 1 : G.Px, G.hx + 1);
-    MMX_TRY(up(G.wpost, w.data(), w.size() * cpxb<T>()));
-    auto ty = twiddles<T>(G.Py, G.Py);
-    MMX_TRY(up(G.tw_y, ty.data(), ty.size() * cpxb<T>()));
-    auto tz = twiddles<T>(G.Pz, G.Pz);
-    MMX_TRY(up(G.tw_z, tz.data(), tz.size() * cpxb<T>()));
+  G.tables.clear();
+  keep(twiddles<T>(G.hx, G.hx));
+  keep(twiddles<T>(G.xone ? 1 : G.Px, G.hx + 1));
+  keep(twiddles<T>(G.Py, G.Py));
+  keep(twiddles<T>(G.Pz, G.Pz));
+  return MMX_OK;
+}
+
+// ---------------------------------------------------------------------------
+// device arena: every buffer of a context, laid out in one allocation
+// ---------------------------------------------------------------------------
+constexpr long long kDtsCap = 1 << 18;  // accepted-step and replay list capacity
+constexpr size_t kArenaAlign = 256;
+
+int topo_blocks(const Group& G);
+
+// Walks every device buffer of the context in a fixed order, calling
+// take(buf, bytes) for each; the offsets follow from the sizes alone.
+template <typename F>
+void arena_walk(mmx_ctx* ctx, F&& take) {
+  const size_t w = esize(ctx), c = 2 * w;  // real and complex element sizes
+  int R_total = 0;
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    R_total += G.R;
+    const size_t st = (size_t)G.R * 3 * G.N * w;
+    take(G.tw_x, (size_t)G.hx * c);
+    take(G.wpost, (size_t)(G.hx + 1) * c);
+    take(G.tw_y, (size_t)G.Py * c);
+    take(G.tw_z, (size_t)G.Pz * c);
+    take(G.Nt, (size_t)kTensorStride * G.Tz * G.Ty * G.Kx * w);
+    take(G.S, (size_t)G.R * 3 * G.nz * G.Sy * G.Kx * c);
+    take(G.ms, st);
+    take(G.m7, st);
+    for (int j = 0; j < 7; ++j) take(G.k[j], st);
+    take(G.Trep, (size_t)G.R * sizeof(double));
+    take(G.seeds, (size_t)G.R * sizeof(uint64_t));
+    // sized for one grid row per workgroup, the finest split any field kernel uses
+    take(G.partial, (size_t)G.R * G.ny * G.nz * 5 * sizeof(double));
+    take(G.E, (size_t)G.R * 6 * sizeof(double));
+    take(G.tgen, (size_t)G.R * sizeof(int));
+    take(G.tflag, (size_t)G.R * sizeof(int));
+    take(G.tstart, (size_t)G.R * sizeof(unsigned long long));
+    take(G.S_init, (size_t)G.R * 3 * G.nz * G.Sy * G.Kx * c);
+    take(G.Jrep, (size_t)G.R * sizeof(double));
+    take(G.Acell, (size_t)G.N * w);
+    take(G.nblk_dev, sizeof(int));
+    take(G.topo_part, (size_t)G.R * topo_blocks(G) * sizeof(double));
   }
-  const size_t st = (size_t)G.R * 3 * G.N * sizeof(T);
-  HIP_TRY(G.ms.alloc(st));
-  HIP_TRY(G.k[0].alloc(st));
-  HIP_TRY(G.S.alloc((size_t)G.R * 3 * G.nz * G.Sy * G.Kx * cpxb<T>()));
-  // sized for one grid row per workgroup, the finest split any field kernel uses
-  HIP_TRY(G.partial.alloc((size_t)G.R * G.ny * G.nz * 5 * sizeof(double)));
-  HIP_TRY(G.E.alloc((size_t)G.R * 6 * sizeof(double)));
-  std::vector<double> T0(G.R, 0.0);
-  std::vector<uint64_t> s0(G.R, 0);
-  MMX_TRY(up(G.Trep, T0.data(), G.R * sizeof(double)));
-  MMX_TRY(up(G.seeds, s0.data(), G.R * sizeof(uint64_t)));
+  take(ctx->st, sizeof(RkState));
+  take(ctx->dts, (size_t)kDtsCap * sizeof(double));
+  take(ctx->replay, (size_t)kDtsCap * sizeof(double));
+  take(ctx->Etmp, (size_t)R_total * 6 * sizeof(double));
+  take(ctx->maxbuf, 257 * sizeof(double));
+  take(ctx->stepdev, sizeof(unsigned long long));
+  take(ctx->nfflag, sizeof(int));
+  // learned demag stages (FP32 contexts of one film only)
+  const bool sg = ctx->prec == MMX_F32 && ctx->groups.size() == 1 && ctx->groups[0]->nz == 1;
+  const Group& G0 = *ctx->groups[0];
+  const size_t nel = sg ? (size_t)G0.R * 3 * G0.N : 0;
+  take(ctx->sg_h, nel * sizeof(float));
+  take(ctx->sg_hd, nel * sizeof(float));
+  take(ctx->sg_part, sg ? (size_t)G0.R * 64 * 2 * sizeof(double) : 0);
+  take(ctx->sg_err, sg ? (size_t)G0.R * sizeof(double) : 0);
+}
+
+size_t arena_size(mmx_ctx* ctx) {
+  size_t off = 0;
+  arena_walk(ctx, [&](Buf& b, size_t bytes) {
+    (void)b;
+    off = (off + kArenaAlign - 1) / kArenaAlign * kArenaAlign + bytes;
+  });
+  return (off + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+}
+
+// Points every buffer into the arena at `base`.
+void arena_assign(mmx_ctx* ctx, void* base) {
+  size_t off = 0;
+  arena_walk(ctx, [&](Buf& b, size_t bytes) {
+    off = (off + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+    b.p = bytes ? static_cast<unsigned char*>(base) + off : nullptr;
+    b.bytes = bytes;
+    off += bytes;
+  });
+  ctx->dts_cap = kDtsCap;
+}
+
+// Allocates the context's arena and fills its initial contents: twiddle
+// tables, zero temperatures, keys and flags, a cleared controller state.
+mmx_status arena_init(mmx_ctx* ctx) {
+  ctx->arena_bytes = arena_size(ctx);
+  HIP_TRY(hipMalloc(&ctx->arena, ctx->arena_bytes));
+  ctx->arena_owned = true;
+  HIP_TRY(hipMemset(ctx->arena, 0, ctx->arena_bytes));
+  arena_assign(ctx, ctx->arena);
+  for (auto& gp : ctx->groups) {
+    Group& G = *gp;
+    Buf* dst[4] = {&G.tw_x, &G.wpost, &G.tw_y, &G.tw_z};
+    for (int i = 0; i < 4; ++i)
+      HIP_TRY(hipMemcpy(dst[i]->p, G.tables[i].data(), G.tables[i].size(), hipMemcpyHostToDevice));
+  }
   return MMX_OK;
 }
 
 template <typename T>
-mmx_status ensure_rk_buffers(Group& G) {
-  const size_t st = (size_t)G.R * 3 * G.N * sizeof(T);
-  if (!G.m7.p) HIP_TRY(G.m7.alloc(st));
-  for (int j = 1; j < 7; ++j)
-    if (!G.k[j].p) HIP_TRY(G.k[j].alloc(st));
-  return MMX_OK;
+mmx_status ensure_rk_buffers(Group&) {
+  return MMX_OK;  // stage buffers are part of the arena
 }
 
 // ---------------------------------------------------------------------------
@@ -534,7 +631,6 @@ mmx_status build_demag_group(mmx_ctx* ctx, Group& G) {
   MMX_TRY(line_fft(G.Py, Py * Px, 1, Px, (unsigned)Px, (unsigned)(6 * Pz)));     // columns
   MMX_TRY(line_fft(G.Pz, Pz * Py * Px, 1, Py * Px, (unsigned)(Py * Px), 6u));    // pillars
   const double scale = -G.mat.Ms / ((double)G.Px * G.Py * G.Pz);
-  HIP_TRY(G.Nt.alloc((size_t)kTensorStride * G.Tz * G.Ty * G.Kx * sizeof(T)));
   const long tot = (long)6 * G.Tz * G.Ty * G.Kx;
   k_compress<T><<<(unsigned)((tot + 255) / 256), 256, 0, s>>>(G.Nt.as<T>(), K.as<cpx<double>>(), G.Px,
                                                              G.Py, G.Pz, G.Kx, G.Ty, G.Tz, scale);
@@ -635,7 +731,7 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   a.crkky = (T)(G.ext.rkky / (mu0Ms * G.g.cell[2]));
   a.rkz0 = G.ext.rkky_z[0];
   a.rkz1 = G.ext.rkky_z[1];
-  a.Acell = G.Acell.p ? G.Acell.as<T>() : nullptr;
+  a.Acell = G.acell_on ? G.Acell.as<T>() : nullptr;
   a.exs = (T)(2.0 / mu0Ms);
   a.dhalf = (T)(0.5 * G.mat.D);
   a.dbhalf = (T)(0.5 * G.ext.Db);
@@ -647,7 +743,7 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   a.plan = G.plan_xi;  // inverse transform: full input
   a.tw = G.tw_x.as<cpx<T>>();
   a.wpost = G.wpost.as<cpx<T>>();
-  if ((t & T_STT) && G.Jrep.p && G.stt_P != 0) {
+  if ((t & T_STT) && G.jrep_on && G.stt_P != 0) {
     const double d = G.g.cell[2] * G.nz;  // free-layer thickness
     a.Jrep = G.Jrep.as<double>();
     a.stt_c = kHbar / (kMu0 * kQe * G.mat.Ms * d);
@@ -659,7 +755,7 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
     a.terms &= ~(unsigned)T_STT;
   }
   a.noprec = ctx->noprec;
-  a.nblk_out = G.nblk_dev.p ? G.nblk_dev.as<int>() : nullptr;
+  a.nblk_out = G.nblk_dev.as<int>();
   a.nonfinite = ctx->nfflag.as<int>();
   a.rot = ctx->rot;
   if (ctx->refill) {
@@ -1001,6 +1097,8 @@ mmx_status rk_begin(mmx_ctx* ctx, double t0, double t_end, double tol, double dt
   if (!(t_end > t0)) return fail(MMX_EINVAL, "t_end must exceed t0");
   if (!(tol > 0) && !replay) return fail(MMX_EINVAL, "tol must be > 0");
   if (replay && n_replay < 1) return fail(MMX_EINVAL, "empty dt replay");
+  if (replay && n_replay > kDtsCap)
+    return fail(MMX_EINVAL, "dt replay longer than " + std::to_string(kDtsCap) + " steps");
   for (auto& g : ctx->groups) MMX_TRY(ensure_rk_buffers<T>(*g));
   hipStream_t s = ctx->stream;
   // controller state
@@ -1019,18 +1117,10 @@ mmx_status rk_begin(mmx_ctx* ctx, double t0, double t_end, double tol, double dt
     h.final_flag = (t0 + h.dt >= t_end) ? 1 : 0;
     if (h.final_flag) h.dt = t_end - t0;
   }
-  if (!ctx->st.p) HIP_TRY(ctx->st.alloc(sizeof(RkState)));
   HIP_TRY(hipMemcpyAsync(ctx->st.p, &h, sizeof(RkState), hipMemcpyHostToDevice, s));
-  const long long want_cap = replay ? n_replay + 16 : std::max<long long>(ctx->dts_cap, 1 << 16);
-  if (ctx->dts_cap < want_cap) {
-    HIP_TRY(ctx->dts.alloc(want_cap * sizeof(double)));
-    ctx->dts_cap = want_cap;
-  }
-  if (replay) {
-    HIP_TRY(ctx->replay.alloc(n_replay * sizeof(double)));
+  if (replay)
     HIP_TRY(hipMemcpyAsync(ctx->replay.p, replay, n_replay * sizeof(double),
                            hipMemcpyHostToDevice, s));
-  }
   return MMX_OK;
 }
 
@@ -1120,16 +1210,16 @@ mmx_status rk_first_stage(mmx_ctx* ctx, T* mb) {
 template <typename T>
 mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, double dt0,
                      const double* replay, int64_t n_replay, void* trace, int64_t cap,
-                     mmx_rk_stats* stats, double* dt_prop = nullptr) {
+                     mmx_rk_stats* stats, double* dt_prop = nullptr, bool resume = false) {
   RkState h;
   MMX_TRY(rk_begin<T>(ctx, t0, t_end, tol, dt0, replay, n_replay, h));
+  ctx->rk_valid = 0;
   hipStream_t s = ctx->stream;
   RkState* st = ctx->st.as<RkState>();
   T* mb = reinterpret_cast<T*>(m);
   // trace helpers
   int R_total = 0;
   for (auto& g : ctx->groups) R_total += g->R;
-  if (trace && !ctx->Etmp.p) HIP_TRY(ctx->Etmp.alloc((size_t)R_total * 6 * sizeof(double)));
   auto energy_into_trace = [&](int force0) -> mmx_status {
     int roff = 0;
     for (auto& gp : ctx->groups) {
@@ -1148,7 +1238,8 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
     HIP_TRY(hipGetLastError());
     return MMX_OK;
   };
-  MMX_TRY(rk_first_stage<T>(ctx, mb));
+  // a continuation starts from the saved first-same-as-last slope in k[0]
+  if (!resume) MMX_TRY(rk_first_stage<T>(ctx, mb));
   if (trace) MMX_TRY(energy_into_trace(1));
   double e[7];
   for (int j = 0; j < 7; ++j) e[j] = (j < 6 ? DP_A[6][j] : 0.0) - DP_B4[j];
@@ -1205,6 +1296,11 @@ mmx_status rk45_impl(mmx_ctx* ctx, void* m, double t0, double t_end, double tol,
   }
   ctx->last_accepted = h.accepted;
   if (dt_prop) *dt_prop = h.dt_prop;
+  if (!replay && !h.dtmin_hit) {
+    ctx->rk_last = h;
+    ctx->rk_valid = 1;
+    ctx->rk_epoch = ctx->epoch;
+  }
   if (stats) {
     stats->t = h.t;
     stats->dt = h.dt;
@@ -1226,7 +1322,6 @@ mmx_status ensure_graph_stream(mmx_ctx* ctx) {
   if (!ctx->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
   if (!ctx->ev_user) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_user, hipEventDisableTiming));
   if (!ctx->ev_cap) HIP_TRY(hipEventCreateWithFlags(&ctx->ev_cap, hipEventDisableTiming));
-  if (!ctx->stepdev.p) HIP_TRY(ctx->stepdev.alloc(sizeof(unsigned long long)));
   return MMX_OK;
 }
 
@@ -1349,9 +1444,6 @@ mmx_status heun_macrospin(mmx_ctx* ctx, Group& G, T* mg, double dt, int64_t n_st
 template <typename T>
 mmx_status refill_begin(mmx_ctx* ctx, Group& G, const RefillArgs& rf, int roff, uint64_t step0) {
   hipStream_t s = ctx->stream;
-  HIP_TRY(G.tgen.ensure((size_t)G.R * sizeof(int)));
-  HIP_TRY(G.tflag.ensure((size_t)G.R * sizeof(int)));
-  HIP_TRY(G.tstart.ensure((size_t)G.R * sizeof(unsigned long long)));
   const unsigned nb = (unsigned)((G.R + 255) / 256);
   k_fill_i32<<<nb, 256, 0, s>>>(G.tgen.as<int>(), G.R, 0);
   k_fill_i32<<<nb, 256, 0, s>>>(G.tflag.as<int>(), G.R, 0);
@@ -1371,6 +1463,7 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
                      void* tsw, int rot = 0, const RefillArgs* rf = nullptr) {
   if (!(dt > 0)) return fail(MMX_EINVAL, "dt must be > 0");
   if (n_steps < 0) return fail(MMX_EINVAL, "n_steps must be >= 0");
+  ctx->rk_valid = 0;  // the stage buffers are reused
   hipStream_t s = ctx->stream;
   T* mb = reinterpret_cast<T*>(m);
   double* tsw_d = reinterpret_cast<double*>(tsw);
@@ -1405,9 +1498,9 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       const FusedTiles ft = fused_tiles<T>(ctx, G);
       if (ctx->path == MMX_PATH_FUSED && !ft.ok)
         return fail(MMX_EUNSUP, "group does not fit the replica-resident path");
-      const bool stt = ((ctx->terms & MMX_STT) && G.Jrep.p && G.stt_P != 0) ||
+      const bool stt = ((ctx->terms & MMX_STT) && G.jrep_on && G.stt_P != 0) ||
                        G.ext.Db != 0 || ((ctx->terms & MMX_ANIS_CUBIC) && (G.ext.Kc1 != 0 || G.ext.Kc2 != 0)) ||
-                       ((ctx->terms & MMX_RKKY) && G.ext.rkky != 0) || G.Acell.p;
+                       ((ctx->terms & MMX_RKKY) && G.ext.rkky != 0) || G.acell_on;
       if (stt && ctx->path == MMX_PATH_FUSED)
         return fail(MMX_EUNSUP, "the spin-transfer torque and further field terms run on the "
                                 "staged path only");
@@ -1441,7 +1534,6 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       Group& G = *ctx->groups[gi];
       if (!yconv_reg_applies<T>(G)) continue;
       folds[gi] = 1;
-      HIP_TRY(G.nblk_dev.ensure(sizeof(int)));
       const size_t np = G.partial.bytes / sizeof(double);
       k_fill_f64<<<(unsigned)((np + 255) / 256), 256, 0, s>>>(G.partial.as<double>(), np, 1.0);
       k_fill_i32<<<1, 64, 0, s>>>(G.nblk_dev.as<int>(), 1, 1);
@@ -1542,7 +1634,6 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       const int roff = roffs[gi];
       MMX_TRY(refill_begin<T>(ctx, G, *rf, roff, step0));
       if (n_steps > 0 && (ctx->terms & MMX_DEMAG)) {
-        HIP_TRY(G.S_init.ensure(G.S.bytes));
         MMX_TRY(spectrum_of(G, reinterpret_cast<const T*>(rf->m_init) + G.off));
         HIP_TRY(hipMemcpyAsync(G.S_init.p, G.S.p, G.S.bytes, hipMemcpyDeviceToDevice, s));
       }
@@ -1633,6 +1724,7 @@ mmx_status rk4_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps) {
   if (!(dt > 0)) return fail(MMX_EINVAL, "dt must be > 0");
   if (n_steps < 0) return fail(MMX_EINVAL, "n_steps must be >= 0");
   if (ctx->terms & MMX_THERMAL) return fail(MMX_EUNSUP, "thermal field with RK4");
+  ctx->rk_valid = 0;
   for (auto& gp : ctx->groups) MMX_TRY(ensure_rk_buffers<T>(*gp));
   T* mb = reinterpret_cast<T*>(m);
   for (int64_t i = 0; i < n_steps; ++i) {
@@ -1672,7 +1764,6 @@ mmx_status rk4_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps) {
 template <typename T>
 mmx_status max_torque(mmx_ctx* ctx, const T* mb, double* out) {
   constexpr int nb = 256;
-  HIP_TRY(ctx->maxbuf.ensure((nb + 1) * sizeof(double)));
   for (auto& gp : ctx->groups) MMX_TRY(ensure_rk_buffers<T>(*gp));
   double mx = 0;
   for (auto& gp : ctx->groups) {
@@ -1731,6 +1822,7 @@ mmx_status relax_impl(mmx_ctx* ctx, void* m, double torque_tol, double t_max, do
     stats->rejected = rej;
   }
   if (tq_out) *tq_out = tq;
+  ctx->rk_valid = 0;  // the saved slope belongs to the damping-only dynamics
   return MMX_OK;
 }
 
@@ -1809,17 +1901,15 @@ mmx_status topo_impl(mmx_ctx* ctx, const void* m, void* Q) {
   for (auto& gp : ctx->groups) {
     Group& G = *gp;
     const int nblk = topo_blocks(G);
-    DevBuf part;
-    HIP_TRY(part.alloc((size_t)G.R * nblk * sizeof(double)));
+    double* part = G.topo_part.as<double>();
     dim3 grid(nblk, G.R);
     k_topo<T><<<grid, kBlock, 0, ctx->stream>>>(mb + G.off, G.nx, G.ny, G.N, G.g.pbc[0],
                                                 G.g.pbc[1], 1.0 / (2 * G.g.cell[0]),
-                                                1.0 / (2 * G.g.cell[1]), part.as<double>(), nblk);
+                                                1.0 / (2 * G.g.cell[1]), part, nblk);
     HIP_TRY(hipGetLastError());
     k_topo_reduce<<<(G.R + 63) / 64, 64, 0, ctx->stream>>>(
-        part.as<double>(), nblk, G.R, G.g.cell[0] * G.g.cell[1] / (4 * kPi), Qb + roff);
+        part, nblk, G.R, G.g.cell[0] * G.g.cell[1] / (4 * kPi), Qb + roff);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize(ctx->stream));  // `part` is freed on return
     roff += G.R;
   }
   return MMX_OK;
@@ -1891,7 +1981,7 @@ mmx_status apply_tiles(Group& G, int L, int Wy, int Wz) {
   G.Wz = Wz;
   const int nblk = ((G.ny + G.L - 1) / G.L) * G.nz;
   if ((size_t)G.R * nblk * 5 * sizeof(double) > G.partial.bytes)
-    HIP_TRY(G.partial.alloc((size_t)G.R * nblk * 5 * sizeof(double)));
+    return fail(MMX_EINVAL, "tile sizes need more partial sums than reserved");
   G.nblk = nblk;
   return MMX_OK;
 }
@@ -1924,6 +2014,7 @@ mmx_status time_eval(mmx_ctx* ctx, Group& G, float& ms) {
 
 template <typename T>
 mmx_status autotune_impl(mmx_ctx* ctx) {
+  ctx->rk_valid = 0;
   for (auto& gp : ctx->groups) {
     Group& G = *gp;
     if (!G.demag_built) continue;
@@ -2070,10 +2161,7 @@ mmx_status mmx_create(const mmx_group* groups, int32_t n_groups, mmx_prec prec, 
     ctx->groups.push_back(std::move(G));
   }
   ctx->total_elems = off;
-  HIP_TRY(ctx->st.alloc(sizeof(RkState)));
-  HIP_TRY(hipMemset(ctx->st.p, 0, sizeof(RkState)));
-  HIP_TRY(ctx->nfflag.alloc(sizeof(int)));
-  HIP_TRY(hipMemset(ctx->nfflag.p, 0, sizeof(int)));
+  MMX_TRY(arena_init(ctx.get()));
   *out = ctx.release();
   return MMX_OK;
 }
@@ -2134,7 +2222,7 @@ mmx_status mmx_set_exchange_cells(mmx_ctx* ctx, int32_t group, const double* A) 
   ctx->epoch++;
   Group& G = *ctx->groups[group];
   if (!A) {
-    HIP_TRY(G.Acell.alloc(0));
+    G.acell_on = 0;
     return MMX_OK;
   }
   for (int i = 0; i < G.N; ++i)
@@ -2146,9 +2234,9 @@ mmx_status mmx_set_exchange_cells(mmx_ctx* ctx, int32_t group, const double* A) 
     if (es == 8) reinterpret_cast<double*>(buf.data())[i] = A[i];
     else reinterpret_cast<float*>(buf.data())[i] = (float)A[i];
   }
-  HIP_TRY(G.Acell.ensure(buf.size()));
   HIP_TRY(hipMemcpyAsync(G.Acell.p, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  G.acell_on = 1;
   return MMX_OK;
 }
 
@@ -2194,9 +2282,9 @@ mmx_status mmx_set_stt(mmx_ctx* ctx, int32_t group, const double* J, const doubl
   Group& G = *ctx->groups[group];
   for (int r = 0; r < G.R; ++r)
     if (!std::isfinite(J[r])) return fail(MMX_EINVAL, "current densities must be finite");
-  HIP_TRY(G.Jrep.ensure((size_t)G.R * sizeof(double)));
   HIP_TRY(hipMemcpyAsync(G.Jrep.p, J, G.R * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
+  G.jrep_on = 1;
   for (int c = 0; c < 3; ++c) G.stt_p[c] = p[c] / pn;
   G.stt_P = P;
   G.stt_lambda = Lambda;
@@ -2308,6 +2396,148 @@ mmx_status mmx_rk45(mmx_ctx* ctx, void* m, double t0, double t_end, double tol, 
                                   trace_cap, stats)
               : rk45_impl<float>(ctx, m, t0, t_end, tol, dt0, dt_replay, n_replay, energy_trace,
                                  trace_cap, stats));
+  return take_nonfinite(ctx);
+}
+
+mmx_status mmx_workspace_bytes(const mmx_ctx* ctx, size_t* bytes) {
+  MMX_TRY(check_ctx(ctx));
+  if (!bytes) return fail(MMX_EINVAL, "bytes is null");
+  *bytes = ctx->arena_bytes;
+  return MMX_OK;
+}
+
+mmx_status mmx_bind(mmx_ctx* ctx, void* ws, size_t bytes, void* stream) {
+  MMX_TRY(check_ctx(ctx));
+  if (ws && bytes < ctx->arena_bytes)
+    return fail(MMX_EINVAL, "workspace smaller than mmx_workspace_bytes (" +
+                                std::to_string(ctx->arena_bytes) + " bytes)");
+  if (ws && (reinterpret_cast<uintptr_t>(ws) % kArenaAlign) != 0)
+    return fail(MMX_EINVAL, "workspace must be 256-byte aligned");
+  if (ws == ctx->arena) {
+    ctx->stream = reinterpret_cast<hipStream_t>(stream);
+    return MMX_OK;
+  }
+  // finish everything that uses the current arena, then move its contents
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  if (ctx->cap_stream) HIP_TRY(hipStreamSynchronize(ctx->cap_stream));
+  ctx->heun_graphs.clear();
+  ctx->rk_graphs.clear();
+  ctx->epoch++;
+  void* dst = ws;
+  bool owned = false;
+  if (!dst) {  // back to a library-owned arena
+    HIP_TRY(hipMalloc(&dst, ctx->arena_bytes));
+    owned = true;
+  }
+  const hipError_t e = hipMemcpy(dst, ctx->arena, ctx->arena_bytes, hipMemcpyDeviceToDevice);
+  if (e != hipSuccess) {
+    if (owned) (void)hipFree(dst);
+    return fail(MMX_EHIP, std::string("workspace copy: ") + hipGetErrorString(e));
+  }
+  if (ctx->arena_owned) HIP_TRY(hipFree(ctx->arena));
+  ctx->arena = dst;
+  ctx->arena_owned = owned;
+  arena_assign(ctx, dst);
+  ctx->stream = reinterpret_cast<hipStream_t>(stream);
+  return MMX_OK;
+}
+
+// Checkpoint blob: header, then the saved first-same-as-last slope of every
+// group (element type of the context, layout D1).
+struct CkptHeader {
+  char magic[8];
+  int32_t prec, n_groups;
+  uint64_t total_elems, shape_hash;
+  double t, dt_prop, last_err;
+  int64_t accepted, rejected;
+};
+
+uint64_t shape_hash(const mmx_ctx* ctx) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a over the group descriptions
+  for (auto& gp : ctx->groups) {
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(&gp->g);
+    for (size_t i = 0; i < sizeof(mmx_group); ++i) h = (h ^ b[i]) * 1099511628211ull;
+  }
+  return h;
+}
+
+mmx_status mmx_checkpoint(const mmx_ctx* ctx, void* blob, size_t* bytes) {
+  MMX_TRY(check_ctx(ctx));
+  if (!bytes) return fail(MMX_EINVAL, "bytes is null");
+  const size_t need = sizeof(CkptHeader) + ctx->total_elems * esize(ctx);
+  if (!blob) {
+    *bytes = need;
+    return MMX_OK;
+  }
+  if (*bytes < need) return fail(MMX_EINVAL, "checkpoint buffer too small");
+  if (!ctx->rk_valid || ctx->rk_epoch != ctx->epoch)
+    return fail(MMX_ESTATE, "no adaptive run to checkpoint (or the configuration changed)");
+  CkptHeader hd{};
+  std::memcpy(hd.magic, "MMXCKPT1", 8);
+  hd.prec = ctx->prec;
+  hd.n_groups = (int32_t)ctx->groups.size();
+  hd.total_elems = ctx->total_elems;
+  hd.shape_hash = shape_hash(ctx);
+  hd.t = ctx->rk_last.t;
+  hd.dt_prop = ctx->rk_last.dt_prop;
+  hd.last_err = ctx->rk_last.last_err;
+  hd.accepted = ctx->rk_last.accepted;
+  hd.rejected = ctx->rk_last.rejected;
+  std::memcpy(blob, &hd, sizeof(hd));
+  unsigned char* out = static_cast<unsigned char*>(blob) + sizeof(hd);
+  for (auto& gp : ctx->groups) {
+    const size_t nb = (size_t)gp->R * 3 * gp->N * esize(ctx);
+    HIP_TRY(hipMemcpyAsync(out, gp->k[0].p, nb, hipMemcpyDeviceToHost, ctx->stream));
+    out += nb;
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  *bytes = need;
+  return MMX_OK;
+}
+
+mmx_status mmx_restore(mmx_ctx* ctx, const void* blob, size_t bytes) {
+  MMX_TRY(check_ctx(ctx));
+  if (!blob || bytes < sizeof(CkptHeader)) return fail(MMX_EINVAL, "checkpoint too short");
+  CkptHeader hd;
+  std::memcpy(&hd, blob, sizeof(hd));
+  if (std::memcmp(hd.magic, "MMXCKPT1", 8) != 0) return fail(MMX_EINVAL, "not a checkpoint");
+  if (hd.prec != ctx->prec || hd.n_groups != (int32_t)ctx->groups.size() ||
+      hd.total_elems != ctx->total_elems || hd.shape_hash != shape_hash(ctx))
+    return fail(MMX_ESHAPE, "checkpoint of a different precision or group layout");
+  if (bytes < sizeof(CkptHeader) + ctx->total_elems * esize(ctx))
+    return fail(MMX_EINVAL, "checkpoint too short");
+  const unsigned char* in = static_cast<const unsigned char*>(blob) + sizeof(hd);
+  for (auto& gp : ctx->groups) {
+    const size_t nb = (size_t)gp->R * 3 * gp->N * esize(ctx);
+    HIP_TRY(hipMemcpyAsync(gp->k[0].p, in, nb, hipMemcpyHostToDevice, ctx->stream));
+    in += nb;
+  }
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->rk_last = RkState{};
+  ctx->rk_last.t = hd.t;
+  ctx->rk_last.dt_prop = hd.dt_prop;
+  ctx->rk_last.last_err = hd.last_err;
+  ctx->rk_last.accepted = hd.accepted;
+  ctx->rk_last.rejected = hd.rejected;
+  ctx->rk_valid = 1;
+  ctx->rk_epoch = ctx->epoch;
+  return MMX_OK;
+}
+
+mmx_status mmx_rk45_resume(mmx_ctx* ctx, void* m, double t_end, double tol, void* energy_trace,
+                           int64_t trace_cap, mmx_rk_stats* stats) {
+  MMX_TRY(check_ctx(ctx));
+  MMX_TRY(check_materials(ctx));
+  if (!m) return fail(MMX_EINVAL, "null array");
+  if (!ctx->rk_valid || ctx->rk_epoch != ctx->epoch)
+    return fail(MMX_ESTATE, "nothing to continue: no adaptive run or restored checkpoint "
+                            "with the current configuration");
+  const double t0 = ctx->rk_last.t, dt0 = ctx->rk_last.dt_prop;
+  MMX_TRY(ctx->prec == MMX_F64
+              ? rk45_impl<double>(ctx, m, t0, t_end, tol, dt0, nullptr, 0, energy_trace,
+                                  trace_cap, stats, nullptr, true)
+              : rk45_impl<float>(ctx, m, t0, t_end, tol, dt0, nullptr, 0, energy_trace,
+                                 trace_cap, stats, nullptr, true));
   return take_nonfinite(ctx);
 }
 

@@ -89,14 +89,15 @@ mmx_status rk45_surrogate_impl(mmx_ctx* ctx, mmx_fno* f, const float* prm, void*
   if (!(gate_tol >= 0)) return fail(MMX_EINVAL, "gate_tol must be >= 0");
   if (exact_after_fail < 0) return fail(MMX_EINVAL, "exact_after_fail must be >= 0");
   if (gate_cap > 0 && !gate_log) return fail(MMX_EINVAL, "gate_log is null");
+  ctx->rk_valid = 0;  // the learned-stage run reuses the stage buffers
   RkState h;
   MMX_TRY(rk_begin<float>(ctx, t0, t_end, tol, dt0, nullptr, 0, h));
   const size_t nel = (size_t)G.R * 3 * G.N;
-  if (ctx->sg_h.bytes < nel * sizeof(float)) HIP_TRY(ctx->sg_h.alloc(nel * sizeof(float)));
-  if (ctx->sg_hd.bytes < nel * sizeof(float)) HIP_TRY(ctx->sg_hd.alloc(nel * sizeof(float)));
   const size_t npart = (size_t)G.R * kGateBlocks * 2 * sizeof(double);
-  if (ctx->sg_part.bytes < npart) HIP_TRY(ctx->sg_part.alloc(npart));
-  if (ctx->sg_err.bytes < G.R * sizeof(double)) HIP_TRY(ctx->sg_err.alloc(G.R * sizeof(double)));
+  // the arena of an FP32 one-film context holds these buffers
+  if (ctx->sg_h.bytes < nel * sizeof(float) || ctx->sg_hd.bytes < nel * sizeof(float) ||
+      ctx->sg_part.bytes < npart || ctx->sg_err.bytes < G.R * sizeof(double))
+    return fail(MMX_ESTATE, "learned-stage buffers missing from the context");
   hipStream_t s = ctx->stream;
   FnoStreamGuard guard(f, s);
   FnoHook hook;
