@@ -2,7 +2,8 @@
 boundaries by FFT convolution with the Newell tensor zero padded to 2N,
 periodic boundaries by an image-sum kernel).
 
-H_i = -Ms sum_j K(i - j) m_j with K from ``newell.kernel_real_space``.  Two
+H_i = -sum_j K(i - j) Ms_j m_j with K from ``newell.kernel_real_space`` (Ms a
+scalar, or one value per cell: the convolution acts on M = Ms m).  Two
 evaluations of the same definition: a direct O(N^2) sum (tiny grids) and the
 FFT convolution on the padded grid (numpy's complex FFT as the primitive).
 """
@@ -26,9 +27,10 @@ def _kernel_hat(grid):
 
 
 def demag_direct(m, grid, Ms):
-    """Direct sum H_i = -Ms sum_j K(i - j) m_j over all source cells.  ``m`` has
-    shape (3, nz, ny, nx).  Offsets index the same kernel array as the FFT path,
-    taken modulo the FFT size (open axes: |i - j| < N never wraps)."""
+    """Direct sum H_i = -sum_j K(i - j) Ms_j m_j over all source cells.  ``m``
+    has shape (3, nz, ny, nx), ``Ms`` a scalar or (nz, ny, nx).  Offsets index
+    the same kernel array as the FFT path, taken modulo the FFT size (open
+    axes: |i - j| < N never wraps)."""
     nx, ny, nz = grid.n
     Px, Py, Pz = grid.padded
     K = _kernel(grid)
@@ -36,7 +38,7 @@ def demag_direct(m, grid, Ms):
     H = np.zeros((3, nz, ny, nx))
     zs, ys, xs = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     zs, ys, xs = zs.ravel(), ys.ravel(), xs.ravel()
-    msrc = m.reshape(3, -1)
+    msrc = (Ms * m).reshape(3, -1)
     for k in range(zs.size):
         iz, iy, ix = zs[k], ys[k], xs[k]
         kz = (iz - zs) % Pz
@@ -46,12 +48,12 @@ def demag_direct(m, grid, Ms):
             acc = 0.0
             for b in range(3):
                 acc += np.dot(K[full[a, b], kz, ky, kx], msrc[b])
-            H[a, iz, iy, ix] = -Ms * acc
+            H[a, iz, iy, ix] = -acc
     return H
 
 
 def demag_fft(m, grid, Ms):
-    """FFT convolution: pad Ms*m with zeros to the FFT grid, multiply the
+    """FFT convolution: pad M = Ms m with zeros to the FFT grid, multiply the
     spectra by the (symmetric) tensor spectrum, transform back and crop."""
     nx, ny, nz = grid.n
     Px, Py, Pz = grid.padded

@@ -32,6 +32,17 @@ for a batch of replicas sharing one geometry and material.
 * Thermal (Brown) field H = sigma eta with
   sigma = sqrt(2 alpha kB T / (mu0^2 Ms V gamma0 dt)) (Results, "A
   replica-batched engine"), V the cell volume.
+* Per-cell materials (Methods: material parameters per cell; reading of what
+  that means for each term): every field term that carries 1 / (mu0 Ms) takes
+  the cell's own Ms_i; the demag convolution acts on M_j = Ms_j m_j; the
+  anisotropy and the thermal field take the cell's Ku_i, alpha_i and Ms_i.  A
+  per-cell interfacial D keeps the energy density D_i [m_z div m - (m . grad)
+  m_z] of each cell with central differences; collecting its terms per
+  neighbour pair gives each pair the coupling (D_i + D_j) / 2, so the field of
+  cell i is (1 / mu0 Ms_i D_a) [D_{i,i+1} m_z(i+1) - D_{i-1,i} m_z(i-1)] along
+  x and y (and the matching m_a terms in H_z), which reduces to the uniform
+  formula when D is uniform.  A ghost neighbour takes the edge cell's D_i,
+  and the edge condition uses D_i / 2A_i.
 """
 from __future__ import annotations
 
@@ -49,6 +60,25 @@ _NP_AXIS = {0: -1, 1: -2, 2: -3}
 
 def _comp(m, c):
     return m[..., c, :, :, :]
+
+
+def cell_param(mat, name):
+    """Parameter ``name`` (Ms, alpha, Ku or D) of the material: its per-cell
+    array (nz, ny, nx) if set, else the scalar."""
+    arr = getattr(mat, name + "_cells")
+    return getattr(mat, name) if arr is None else np.asarray(arr, dtype=np.float64)
+
+
+def _edge_slices(grid, axis, ndim):
+    """Index tuples of the first and last layer of cells along ``axis`` for an
+    array with ``ndim`` dimensions whose last three are (nz, ny, nx)."""
+    ax = _NP_AXIS[axis]
+    n = grid.n[axis]
+    first = [slice(None)] * ndim
+    last = [slice(None)] * ndim
+    first[ndim + ax] = slice(0, 1)
+    last[ndim + ax] = slice(n - 1, n)
+    return tuple(first), tuple(last)
 
 
 def _edge_derivative(mc, axis, D, A, Db=0.0):
@@ -93,7 +123,8 @@ def neighbours(m, grid, mat, axis):
     first[m.ndim + ax] = slice(0, 1)
     last[m.ndim + ax] = slice(n - 1, n)
     first, last = tuple(first), tuple(last)
-    use_dmi = (mat.D != 0.0 and axis in (0, 1)) or mat.Db != 0.0
+    D = cell_param(mat, "D")
+    use_dmi = (bool(np.any(D != 0.0)) and axis in (0, 1)) or mat.Db != 0.0
     m_first = m[first]
     m_last = m[last]
     if use_dmi:
@@ -102,8 +133,12 @@ def neighbours(m, grid, mat, axis):
             a_first, a_last = Ac[first[-3:]], Ac[last[-3:]]
         else:
             a_first = a_last = mat.A
-        mm[first] = m_first - h * _edge_derivative(m_first, axis, mat.D, a_first, mat.Db)
-        mp[last] = m_last + h * _edge_derivative(m_last, axis, mat.D, a_last, mat.Db)
+        if mat.D_cells is not None:
+            d_first, d_last = D[first[-3:]], D[last[-3:]]
+        else:
+            d_first = d_last = mat.D
+        mm[first] = m_first - h * _edge_derivative(m_first, axis, d_first, a_first, mat.Db)
+        mp[last] = m_last + h * _edge_derivative(m_last, axis, d_last, a_last, mat.Db)
     else:
         mm[first] = m_first
         mp[last] = m_last
@@ -133,8 +168,9 @@ def _neighbour_A(Ac, grid, axis):
 
 def exchange_field(m, grid, mat):
     H = np.zeros_like(m)
+    Ms = cell_param(mat, "Ms")
     if mat.A_cells is None:
-        pref = 2.0 * mat.A / (MU0 * mat.Ms)
+        pref = 2.0 * mat.A / (MU0 * Ms)
         for axis in range(3):
             if grid.n[axis] == 1:
                 continue
@@ -148,15 +184,43 @@ def exchange_field(m, grid, mat):
         mm, mp = neighbours(m, grid, mat, axis)
         am, ap = _neighbour_A(Ac, grid, axis)
         wm, wp = _harmonic(Ac, am), _harmonic(Ac, ap)
-        H += 2.0 / (MU0 * mat.Ms) * (wm * (mm - m) + wp * (mp - m)) / grid.cell[axis] ** 2
+        H += 2.0 / (MU0 * Ms) * (wm * (mm - m) + wp * (mp - m)) / grid.cell[axis] ** 2
     return H
+
+
+def _neighbour_D(Dc, grid, axis):
+    """(D at i-1, D at i+1) along ``axis``: periodic wrap, or the cell's own
+    value where the neighbour is a ghost."""
+    ax = _NP_AXIS[axis]
+    dm, dp = np.roll(Dc, 1, axis=ax), np.roll(Dc, -1, axis=ax)
+    if not grid.pbc[axis]:
+        first, last = _edge_slices(grid, axis, 3)
+        dm[first] = Dc[first]
+        dp[last] = Dc[last]
+    return dm, dp
 
 
 def dmi_field(m, grid, mat):
     H = np.zeros_like(m)
+    Ms = cell_param(mat, "Ms")
+    if mat.D_cells is not None:
+        # pair couplings (D_i + D_j) / 2 of the per-cell energy density
+        Dc = np.asarray(mat.D_cells, dtype=np.float64)
+        if not np.any(Dc != 0.0):
+            return H
+        for axis in (0, 1):
+            if grid.n[axis] == 1:
+                continue
+            mm, mp = neighbours(m, grid, mat, axis)
+            dm, dp = _neighbour_D(Dc, grid, axis)
+            wm, wp = 0.5 * (Dc + dm), 0.5 * (Dc + dp)
+            pref = 1.0 / (MU0 * Ms * grid.cell[axis])
+            H[..., axis, :, :, :] += pref * (wp * _comp(mp, 2) - wm * _comp(mm, 2))
+            H[..., 2, :, :, :] -= pref * (wp * _comp(mp, axis) - wm * _comp(mm, axis))
+        return H
     if mat.D == 0.0:
         return H
-    pref = 2.0 * mat.D / (MU0 * mat.Ms)
+    pref = 2.0 * mat.D / (MU0 * Ms)
     for axis in (0, 1):
         if grid.n[axis] == 1:
             continue
@@ -173,7 +237,7 @@ def bulk_dmi_field(m, grid, mat):
     H = np.zeros_like(m)
     if mat.Db == 0.0:
         return H
-    pref = -2.0 * mat.Db / (MU0 * mat.Ms)
+    pref = -2.0 * mat.Db / (MU0 * cell_param(mat, "Ms"))
     for axis in range(3):
         if grid.n[axis] == 1:
             continue
@@ -210,7 +274,7 @@ def cubic_field(m, mat):
     mi = [sum(a[c] * _comp(m, c) for c in range(3)) for a in ax]
     g = [2 * mat.Kc1 * mi[i] * (mi[(i + 1) % 3] ** 2 + mi[(i + 2) % 3] ** 2) +
          2 * mat.Kc2 * mi[i] * mi[(i + 1) % 3] ** 2 * mi[(i + 2) % 3] ** 2 for i in range(3)]
-    pref = -1.0 / (MU0 * mat.Ms)
+    pref = -1.0 / (MU0 * cell_param(mat, "Ms"))
     return pref * np.stack([sum(g[i] * ax[i][c] for i in range(3)) for c in range(3)], axis=-4)
 
 
@@ -227,19 +291,23 @@ def rkky_field(m, grid, mat):
     if mat.rkky == 0.0:
         return H
     z0, z1 = mat.rkky_z
-    pref = mat.rkky / (MU0 * mat.Ms * grid.cell[2])
-    H[..., z0, :, :] += pref * m[..., z1, :, :]
-    H[..., z1, :, :] += pref * m[..., z0, :, :]
+    Ms = cell_param(mat, "Ms")
+    pref = mat.rkky / (MU0 * Ms * grid.cell[2])
+    p0 = pref[z0] if np.ndim(pref) else pref
+    p1 = pref[z1] if np.ndim(pref) else pref
+    H[..., z0, :, :] += p0 * m[..., z1, :, :]
+    H[..., z1, :, :] += p1 * m[..., z0, :, :]
     return H
 
 
 def anisotropy_field(m, mat):
-    if mat.Ku == 0.0:
+    Ku = cell_param(mat, "Ku")
+    if not np.any(Ku != 0.0):
         return np.zeros_like(m)
     u = np.asarray(mat.u, float)
     u = u / np.linalg.norm(u)
     mu = sum(u[c] * _comp(m, c) for c in range(3))
-    pref = 2.0 * mat.Ku / (MU0 * mat.Ms)
+    pref = 2.0 * Ku / (MU0 * cell_param(mat, "Ms"))
     return pref * np.stack([u[c] * mu for c in range(3)], axis=-4)
 
 
@@ -251,8 +319,13 @@ def zeeman_field(m, mat):
 
 
 def thermal_sigma(grid, mat, dt):
-    if mat.T == 0.0 or mat.alpha == 0.0:
+    """sigma of the Brown field: a scalar, or one value per cell (nz, ny, nx)
+    with per-cell alpha or Ms."""
+    alpha, Ms = cell_param(mat, "alpha"), cell_param(mat, "Ms")
+    if mat.T == 0.0 or not np.any(alpha != 0.0):
         return 0.0
+    if np.ndim(alpha) or np.ndim(Ms):
+        return np.sqrt(2.0 * alpha * KB * mat.T / (MU0 ** 2 * Ms * grid.volume * GAMMA0 * dt))
     return math.sqrt(2.0 * mat.alpha * KB * mat.T /
                      (MU0 ** 2 * mat.Ms * grid.volume * GAMMA0 * dt))
 
@@ -264,7 +337,7 @@ def thermal_field(grid, mat, dt, seed, step, gen=0):
     nx, ny, nz = grid.n
     seeds = np.atleast_1d(np.asarray(seed, dtype=np.uint64))
     s = thermal_sigma(grid, mat, dt)
-    if s == 0.0:
+    if np.all(np.asarray(s) == 0.0):
         out = np.zeros((seeds.size, 3, nz, ny, nx))
     else:
         out = s * _philox.gaussian_eta(seeds, grid.ncells, step, gen).reshape(seeds.size, 3, nz, ny, nx)
@@ -278,7 +351,7 @@ def terms(m, grid, mat):
            "dmi_bulk": bulk_dmi_field(m, grid, mat),
            "cubic": cubic_field(m, mat),
            "rkky": rkky_field(m, grid, mat),
-           "demag": (_demag.demag_field(m, grid, mat.Ms) if mat.demag
+           "demag": (_demag.demag_field(m, grid, cell_param(mat, "Ms")) if mat.demag
                      else np.zeros_like(m)),
            "anisotropy": anisotropy_field(m, mat),
            "zeeman": zeeman_field(m, mat)}

@@ -50,7 +50,8 @@ DT_MIN = 1e-20
 
 def rhs(m, grid, mat, H_th=None):
     """LLG right-hand side at m, with the spin-transfer torque when set."""
-    k = llg_rhs(m, _fields.effective_field(m, grid, mat, H_th), mat.alpha, mat.precess)
+    k = llg_rhs(m, _fields.effective_field(m, grid, mat, H_th), _fields.cell_param(mat, "alpha"),
+                mat.precess)
     if mat.stt:
         k = k + stt_torque(m, mat, grid.n[2] * grid.cell[2])
     return k

@@ -46,8 +46,9 @@ def stt_torque(m, mat, thickness):
     with d the free-layer thickness (the grid's extent along z), p the fixed
     layer's unit magnetisation and J the current density: J > 0 drives m away
     from p; eps' acts as a field b_J eps' along p.  ``mat.stt_J`` may hold one
-    value per replica of a batch."""
-    alpha = mat.alpha
+    value per replica of a batch; per-cell alpha and Ms enter cell by cell."""
+    from .fields import cell_param
+    alpha = cell_param(mat, "alpha")
     gp = GAMMA0 / (1.0 + alpha * alpha)
     batch = m.ndim == 5
     p = np.asarray(mat.stt_p, dtype=np.float64)
@@ -57,7 +58,7 @@ def stt_torque(m, mat, thickness):
     J = np.asarray(mat.stt_J, dtype=np.float64)
     if batch:
         J = np.broadcast_to(J.reshape(-1), (m.shape[0],)).reshape(-1, 1, 1, 1, 1)
-    bJ = HBAR * J / (MU0 * QE * mat.Ms * thickness)
+    bJ = HBAR * J / (MU0 * QE * cell_param(mat, "Ms") * thickness)
     L2 = mat.stt_lambda ** 2
     mp = np.sum(m * pv, axis=-4, keepdims=True)
     eps = mat.stt_P * L2 / ((L2 + 1.0) + (L2 - 1.0) * mp)

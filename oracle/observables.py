@@ -4,8 +4,9 @@ The paper reports total energies (Results, SP#1-type showcase) and classifies
 skyrmions by topological charge (Results, skyrmion phase diagram) without
 printing their discretisation.  Readings:
 
-* Energy (J): E = V sum_i [ -(mu0 Ms / 2) m_i . (H_ex + H_dmi + H_demag + H_anis)_i
-  - mu0 Ms m_i . H_zeeman ]; the anisotropy part equals -Ku V sum (m . u)^2.
+* Energy (J): E = V sum_i [ -(mu0 Ms_i / 2) m_i . (H_ex + H_dmi + H_demag + H_anis)_i
+  - mu0 Ms_i m_i . H_zeeman ] (Ms_i the cell's own with per-cell materials);
+  the anisotropy part equals -V sum Ku_i (m . u)^2.
   Bulk DMI and RKKY (bilinear) enter like the first group; the cubic
   anisotropy (quartic) as V sum of its energy density.
   The thermal field is excluded.
@@ -31,17 +32,18 @@ def energies(m, grid, mat):
     its energy density."""
     t = _fields.terms(m, grid, mat)
     V = grid.volume
+    Ms = _fields.cell_param(mat, "Ms")
     out = {}
     for name in ENERGY_TERMS:
         if name == "cubic":
             out[name] = V * float(np.sum(_fields.cubic_energy_density(m, mat))) \
                 if (mat.Kc1 or mat.Kc2) else 0.0
             continue
-        dot = float(np.sum(m * t[name]))
+        dot = float(np.sum(Ms * np.sum(m * t[name], axis=-4)))
         if name == "zeeman":
-            out[name] = -MU0 * mat.Ms * V * dot
+            out[name] = -MU0 * V * dot
         else:
-            out[name] = -0.5 * MU0 * mat.Ms * V * dot
+            out[name] = -0.5 * MU0 * V * dot
     out["total"] = sum(out[k] for k in ENERGY_TERMS)
     return out
 

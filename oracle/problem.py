@@ -1,7 +1,7 @@
-"""Problem description for the oracle: a finite-difference grid and a uniform
+"""Problem description for the oracle: a finite-difference grid and a
 material (Methods, "Physics and discretization": structured grid, x-fastest
-indexing; per-cell materials reduce to one value per group for the workloads
-checked here)."""
+indexing; per-cell materials): scalar parameters, each of Ms, A, alpha, Ku and
+D optionally replaced by an array of one value per cell."""
 from __future__ import annotations
 
 from dataclasses import dataclass
@@ -75,6 +75,13 @@ class Material:
     # in the exchange term (harmonic mean per neighbour pair) and in the edge
     # conditions (the edge cell's value)
     A_cells: object = None
+    # further per-cell parameters (arrays (nz, ny, nx)) or None: saturation
+    # magnetisation (A/m, > 0), damping, uniaxial anisotropy constant (J/m^3)
+    # and interfacial DMI constant (J/m^2); each replaces the scalar above
+    Ms_cells: object = None
+    alpha_cells: object = None
+    Ku_cells: object = None
+    D_cells: object = None
 
     @property
     def stt(self) -> bool:

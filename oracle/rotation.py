@@ -56,7 +56,7 @@ def rotate(v, w):
 def _omega_total(m, grid, mat, H_th):
     """Omega of the LLG equation plus, with a spin-transfer torque tau (which
     is perpendicular to m), m x tau: (m x tau) x m = tau."""
-    o = omega(m, _fields.effective_field(m, grid, mat, H_th), mat.alpha)
+    o = omega(m, _fields.effective_field(m, grid, mat, H_th), _fields.cell_param(mat, "alpha"))
     if mat.stt:
         o = o + np.cross(m, stt_torque(m, mat, grid.n[2] * grid.cell[2]), axis=-4)
     return o
