@@ -92,7 +92,7 @@ typedef struct {
   int32_t replicas;      /* R >= 1                                           */
 } mmx_group;
 
-/* Uniform material of a group (per-cell values are not supported). */
+/* Uniform material of a group (per-cell values: mmx_set_material_cells). */
 typedef struct {
   double Ms;     /* saturation magnetisation, A/m (> 0)                     */
   double A;      /* exchange stiffness, J/m                                 */
@@ -202,6 +202,30 @@ mmx_status mmx_set_material_ext(mmx_ctx* ctx, int32_t group, const mmx_material_
  * mmx_set_material_ext).  Synchronous.  MMX_EINVAL for a negative or
  * non-finite value. */
 mmx_status mmx_set_exchange_cells(mmx_ctx* ctx, int32_t group, const double* A);
+
+/* Per-cell materials of group `group` (Methods, "Physics and
+ * discretization": material parameters per cell).  Ms, A, alpha, Ku, D:
+ * device arrays of N_g values each (x fastest, like one component of m),
+ * element type of the context, copied (the caller may free them on return);
+ * a null pointer leaves that parameter uniform (the group's material; for A
+ * this also drops an earlier mmx_set_exchange_cells).  Fields: every term
+ * with a 1 / (mu0 Ms) prefactor takes the cell's Ms_i; the demag convolution
+ * acts on M_j = Ms_j m_j; anisotropy 2 Ku_i / (mu0 Ms_i) (m.u) u; the
+ * interfacial DMI keeps each cell's energy density D_i [m_z div m - (m.grad)
+ * m_z], so a neighbour pair couples with (D_i + D_j) / 2 and the field of
+ * cell i along x is (1 / mu0 Ms_i dx) [D_{i,i+1} m_z(i+1) - D_{i-1,i}
+ * m_z(i-1)] (similarly y, and the matching terms of H_z); a ghost neighbour
+ * takes the edge cell's D_i, the edge condition D_i / 2A_i; exchange as in
+ * mmx_set_exchange_cells with 1 / (mu0 Ms_i); the torque and the Brown field
+ * use alpha_i and Ms_i; the spin-transfer b_J uses Ms_i; energies weigh each
+ * cell by its Ms_i.  The group's material must be set first (its Ms is the
+ * reference of the derived arrays).  These parameters run on the field
+ * kernels of the staged path (the register row kernels, the
+ * replica-resident and the single-cell paths do not take them; the learned
+ * demag stages reject them).  Synchronous.  MMX_EINVAL for Ms <= 0, A < 0,
+ * alpha < 0 or a non-finite value, MMX_ESTATE before mmx_set_material. */
+mmx_status mmx_set_material_cells(mmx_ctx* ctx, int32_t group, const void* Ms, const void* A,
+                                  const void* alpha, const void* Ku, const void* D);
 
 /* Slonczewski spin-transfer torque of group `group` (Methods, "Physics and
  * discretization": spin torques added per integrator stage; Results, the

@@ -99,6 +99,7 @@ _SIGS = {
     "mmx_rk4": [_P, _P, ctypes.c_double, ctypes.c_int64],
     "mmx_set_material_ext": [_P, ctypes.c_int32, _P],
     "mmx_set_exchange_cells": [_P, ctypes.c_int32, _P],
+    "mmx_set_material_cells": [_P, ctypes.c_int32, _P, _P, _P, _P, _P],
     "mmx_set_precession": [_P, ctypes.c_int32],
     "mmx_relax": [_P, _P, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P, _P],
     "mmx_depondt_refill": [_P, _P, _P, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P,
@@ -260,6 +261,14 @@ def mmx_set_exchange_cells(ctx, group, A) -> None:
     Aa = np.ascontiguousarray(np.asarray(A, dtype=np.float64).ravel())
     _check("mmx_set_exchange_cells", _lib.mmx_set_exchange_cells(
         ctx, int(group), Aa.ctypes.data_as(ctypes.c_void_p)))
+
+
+def mmx_set_material_cells(ctx, group, Ms=None, A=None, alpha=None, Ku=None, D=None) -> None:
+    """Per-cell Ms, A, alpha, Ku, D of a group: device tensors of the context's
+    element type with one value per cell (None: uniform)."""
+    _check("mmx_set_material_cells",
+           _lib.mmx_set_material_cells(ctx, int(group), _ptr(Ms), _ptr(A), _ptr(alpha),
+                                       _ptr(Ku), _ptr(D)))
 
 
 def mmx_rk4(ctx, m, dt, n_steps) -> None:

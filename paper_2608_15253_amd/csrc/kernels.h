@@ -139,6 +139,7 @@ struct XArgs {
   int nx, ny, nz, N, Sy, Kx, hx, L, xone;
   const int* done;
   int* nonfinite;  // normalised combine: set to 1 if a combined state is not finite
+  const T* msr;    // per-cell Ms_i / Ms scaling the transform input (null: uniform)
 };
 
 template <typename T>
@@ -183,6 +184,10 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
         if (a.mout) {
 #pragma unroll
           for (int c = 0; c < 3; ++c) a.mout[rb + (size_t)c * a.N + cell] = mv[c];
+        }
+        if (a.msr) {  // the convolution acts on M = Ms_i m
+          const T w = a.msr[cell];
+          mv[0] *= w; mv[1] *= w; mv[2] *= w;
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -557,6 +562,19 @@ struct FArgs {
   // harmonic mean, field prefactor 2 / mu0 Ms, edge factors D/2 and Db/2 over A_i
   const T* Acell;
   T exs, dhalf, dbhalf;
+  // further per-cell parameters (null: the group's uniform material), one
+  // value per cell: Ms_i / Ms (transform input and energy weight), Ms / Ms_i
+  // (local fields, spin-transfer b_J), gamma0 mu0 / (1 + alpha_i^2), alpha_i,
+  // sqrt(alpha_i Ms / Ms_i) (thermal), 2 Ku_i / (mu0 Ms), D_i
+  const T* msr;
+  const T* mgi;
+  const T* gpc;
+  const T* alc;
+  const T* sgc;
+  const T* kuc;
+  const T* dmc;
+  T c2ms, Agrp;     // 2 / (mu0 Ms) and the group's uniform A
+  double sigunit;   // 2 kB / (mu0^2 Ms V gamma0): sigma_i^2 = sigunit T alpha_i Ms / Ms_i / dt
   unsigned terms;
   const double* Trep;
   const uint64_t* seeds;
@@ -653,6 +671,13 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, 
     kbc = Ai > T(0) ? a.dhalf / Ai : T(0);
     kbb = Ai > T(0) ? a.dbhalf / Ai : T(0);
   }
+  const T* __restrict__ Dc = EXT ? a.dmc : nullptr;
+  T Di = 0;
+  if (Dc) {  // the cell's own D / 2A_i
+    Di = Dc[cell];
+    const T Ae = Ac ? Ai : a.Agrp;
+    kbc = Ae > T(0) ? T(0.5) * Di / Ae : T(0);
+  }
   T curl[3] = {0, 0, 0};
 #pragma unroll
   for (int ax = 0; ax < 3; ++ax) {
@@ -697,10 +722,19 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, 
       }
     }
     if ((a.terms & T_DMI) && ax < 2) {
-      const T d_ax = (mp[ax] - mm[ax]) * a.ih2[ax];
-      const T d_z = (mp[2] - mm[2]) * a.ih2[ax];
-      Hdm[ax] += a.cdmi * d_z;
-      Hdm[2] -= a.cdmi * d_ax;
+      if (EXT && Dc) {
+        // pair couplings (D_i + D_j) / 2 of the per-cell energy density (a
+        // ghost takes the cell's own D)
+        const T wm = T(0.5) * (Di + Dc[jm]), wp = T(0.5) * (Di + Dc[jp]);
+        const T f = a.c2ms * a.ih2[ax];
+        Hdm[ax] += f * (wp * mp[2] - wm * mm[2]);
+        Hdm[2] -= f * (wp * mp[ax] - wm * mm[ax]);
+      } else {
+        const T d_ax = (mp[ax] - mm[ax]) * a.ih2[ax];
+        const T d_z = (mp[2] - mm[2]) * a.ih2[ax];
+        Hdm[ax] += a.cdmi * d_z;
+        Hdm[2] -= a.cdmi * d_ax;
+      }
     }
     if (bulk) {
       T d[3];
@@ -717,8 +751,9 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, 
   }
   if (a.terms & T_ANIS) {
     const T mu = mc[0] * a.u[0] + mc[1] * a.u[1] + mc[2] * a.u[2];
+    const T can = (EXT && a.kuc) ? a.kuc[cell] : a.can;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) Han[c] = a.can * mu * a.u[c];
+    for (int c = 0; c < 3; ++c) Han[c] = can * mu * a.u[c];
   }
   if (EXT && (a.terms & T_CUBIC)) {
     T Hc[3], dens;
@@ -732,6 +767,11 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, 
     ld3(mr, N, (unsigned)((int)cell + (zp - z) * (int)stride[2]), mo);
 #pragma unroll
     for (int c = 0; c < 3; ++c) Hex[c] += a.crkky * mo[c];
+  }
+  if (EXT && a.mgi) {  // every local term carries 1 / (mu0 Ms_i)
+    const T g = a.mgi[cell];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) { Hex[c] *= g; Hdm[c] *= g; Han[c] *= g; }
   }
   if (a.terms & T_ZEEMAN) { Hz[0] = a.hz[0]; Hz[1] = a.hz[1]; Hz[2] = a.hz[2]; }
 }
@@ -757,14 +797,14 @@ __device__ inline void llg_torque(const T mc[3], const T H[3], T gpm, T alpha, T
 //   tau = gamma' mu0 b_J [(eps - alpha eps') m x (m x p) - (eps' + alpha eps) m x p],
 //   eps = P Lambda^2 / ((Lambda^2 + 1) + (Lambda^2 - 1) m.p).
 template <typename T>
-__device__ inline void stt_tau(const FArgs<T>& a, T bJ, const T m[3], T tau[3]) {
+__device__ inline void stt_tau(const FArgs<T>& a, T gpm, T alpha, T bJ, const T m[3], T tau[3]) {
   const T* p = a.sttp;
   const T mp = m[0] * p[0] + m[1] * p[1] + m[2] * p[2];
   const T eps = a.stt_P * a.stt_L2 / ((a.stt_L2 + T(1)) + (a.stt_L2 - T(1)) * mp);
   const T x[3] = {m[1] * p[2] - m[2] * p[1], m[2] * p[0] - m[0] * p[2], m[0] * p[1] - m[1] * p[0]};
   const T xx[3] = {m[1] * x[2] - m[2] * x[1], m[2] * x[0] - m[0] * x[2], m[0] * x[1] - m[1] * x[0]};
-  const T c1 = a.gpm * bJ * (eps - a.alpha * a.stt_e2);
-  const T c2 = a.gpm * bJ * (a.stt_e2 + a.alpha * eps);
+  const T c1 = gpm * bJ * (eps - alpha * a.stt_e2);
+  const T c2 = gpm * bJ * (a.stt_e2 + alpha * eps);
 #pragma unroll
   for (int c = 0; c < 3; ++c) tau[c] = c1 * xx[c] - c2 * x[c];
 }
@@ -778,24 +818,31 @@ __device__ inline T stt_bj(const FArgs<T>& a, int r) {
 // Torque of the cell with the spin-transfer term added; tau receives that
 // term alone (zero without it) for the rotation scheme.
 template <typename T>
-__device__ inline void cell_torque(const FArgs<T>& a, T bJ, const T mc[3], const T H[3], T k[3],
-                                   T tau[3]) {
-  llg_torque(mc, H, a.gpm, a.alpha, k);
+__device__ inline void cell_torque(const FArgs<T>& a, T gpm, T alpha, T bJ, const T mc[3],
+                                   const T H[3], T k[3], T tau[3]) {
+  llg_torque(mc, H, gpm, alpha, k);
   if (a.noprec) {
     // damping-only dynamics: -gamma' mu0 alpha m x (m x H)
     const T cx = mc[1] * H[2] - mc[2] * H[1];
     const T cy = mc[2] * H[0] - mc[0] * H[2];
     const T cz = mc[0] * H[1] - mc[1] * H[0];
-    k[0] = -a.gpm * (a.alpha * (mc[1] * cz - mc[2] * cy));
-    k[1] = -a.gpm * (a.alpha * (mc[2] * cx - mc[0] * cz));
-    k[2] = -a.gpm * (a.alpha * (mc[0] * cy - mc[1] * cx));
+    k[0] = -gpm * (alpha * (mc[1] * cz - mc[2] * cy));
+    k[1] = -gpm * (alpha * (mc[2] * cx - mc[0] * cz));
+    k[2] = -gpm * (alpha * (mc[0] * cy - mc[1] * cx));
   }
   tau[0] = tau[1] = tau[2] = T(0);
   if (bJ != T(0)) {
-    stt_tau(a, bJ, mc, tau);
+    stt_tau(a, gpm, alpha, bJ, mc, tau);
 #pragma unroll
     for (int c = 0; c < 3; ++c) k[c] += tau[c];
   }
+}
+
+// the group's uniform damping
+template <typename T>
+__device__ inline void cell_torque(const FArgs<T>& a, T bJ, const T mc[3], const T H[3], T k[3],
+                                   T tau[3]) {
+  cell_torque(a, a.gpm, a.alpha, bJ, mc, H, k, tau);
 }
 
 // The LLG equation as a rotation, dm/dt = Omega x m with Omega =
@@ -860,11 +907,11 @@ __device__ inline double mz_checked(const T mn[3]) {
 // dt/2 (Omega_1 + Omega_2), not normalised.
 // tau: spin-transfer torque at (mc), entering Omega as mc x tau
 template <typename T>
-__device__ inline void heun_predict(const FArgs<T>& a, bool rot, const T mc[3], const T H[3],
+__device__ inline void heun_predict(T gpm, T alpha, bool rot, const T mc[3], const T H[3],
                                     const T k[3], const T tau[3], T dt, T k1v[3], T mn[3]) {
   if (rot) {
     T w[3];
-    llg_omega(mc, H, a.gpm, a.alpha, k1v);
+    llg_omega(mc, H, gpm, alpha, k1v);
     add_cross(mc, tau, k1v);
 #pragma unroll
     for (int c = 0; c < 3; ++c) w[c] = dt * k1v[c];
@@ -879,12 +926,12 @@ __device__ inline void heun_predict(const FArgs<T>& a, bool rot, const T mc[3], 
 }
 
 template <typename T>
-__device__ inline void heun_correct(const FArgs<T>& a, bool rot, const T mc[3], const T H[3],
+__device__ inline void heun_correct(T gpm, T alpha, bool rot, const T mc[3], const T H[3],
                                     const T k[3], const T tau[3], const T mo[3], const T k1v[3],
                                     T dt, T mn[3]) {
   if (rot) {
     T o[3], w[3];
-    llg_omega(mc, H, a.gpm, a.alpha, o);
+    llg_omega(mc, H, gpm, alpha, o);
     add_cross(mc, tau, o);
 #pragma unroll
     for (int c = 0; c < 3; ++c) w[c] = T(0.5) * dt * (k1v[c] + o[c]);
@@ -897,6 +944,19 @@ __device__ inline void heun_correct(const FArgs<T>& a, bool rot, const T mc[3], 
 #pragma unroll
     for (int c = 0; c < 3; ++c) mn[c] = u[c] * inv;
   }
+}
+
+// with the group's uniform damping
+template <typename T>
+__device__ inline void heun_predict(const FArgs<T>& a, bool rot, const T mc[3], const T H[3],
+                                    const T k[3], const T tau[3], T dt, T k1v[3], T mn[3]) {
+  heun_predict(a.gpm, a.alpha, rot, mc, H, k, tau, dt, k1v, mn);
+}
+template <typename T>
+__device__ inline void heun_correct(const FArgs<T>& a, bool rot, const T mc[3], const T H[3],
+                                    const T k[3], const T tau[3], const T mo[3], const T k1v[3],
+                                    T dt, T mn[3]) {
+  heun_correct(a.gpm, a.alpha, rot, mc, H, k, tau, mo, k1v, dt, mn);
 }
 
 // Step index and trial generation of the thermal noise of replica r.
@@ -975,7 +1035,8 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
   T sigma = 0;
   if ((a.terms & T_THERMAL) && a.Trep) {
     const double Tr = a.Trep[r];
-    if (Tr > 0) sigma = (T)sqrt(a.sig2pref * Tr / a.dt_th);
+    // per-cell damping or Ms: sigma_i = sqrt(sigunit T / dt) sqrt(alpha_i Ms / Ms_i)
+    if (Tr > 0) sigma = (T)sqrt((a.sgc ? a.sigunit : a.sig2pref) * Tr / a.dt_th);
   }
   const T kbc = a.kbc;  // free-edge condition of the material's D (0 when D = 0)
   const unsigned N = (unsigned)a.N;
@@ -1008,17 +1069,21 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       Hdd[2] += a.hext_mz * mc[2];
     }
     if (MODE == FM_ENERGY) {
-      acc[0] += (double)(mc[0] * Hex[0] + mc[1] * Hex[1] + mc[2] * Hex[2]);
-      acc[1] += (double)(mc[0] * Hdm[0] + mc[1] * Hdm[1] + mc[2] * Hdm[2]);
-      acc[2] += (double)(mc[0] * Hdd[0] + mc[1] * Hdd[1] + mc[2] * Hdd[2]);
-      acc[3] += (double)(mc[0] * Han[0] + mc[1] * Han[1] + mc[2] * Han[2]);
+      // per-cell Ms weighs each cell's -mu0 Ms_i m.H / 2 against the group's Ms
+      const double w = a.msr ? (double)a.msr[cell] : 1.0;
+      acc[0] += w * (double)(mc[0] * Hex[0] + mc[1] * Hex[1] + mc[2] * Hex[2]);
+      acc[1] += w * (double)(mc[0] * Hdm[0] + mc[1] * Hdm[1] + mc[2] * Hdm[2]);
+      acc[2] += w * (double)(mc[0] * Hdd[0] + mc[1] * Hdd[1] + mc[2] * Hdd[2]);
+      acc[3] += w * (double)(mc[0] * Han[0] + mc[1] * Han[1] + mc[2] * Han[2]);
       if (a.terms & T_CUBIC) {
         // the quartic cubic term enters by its energy density, not -m.H/2
         T Hc[3], dens;
         cubic_terms(a, mc, Hc, dens);
-        acc[3] += a.ecub * (double)dens - (double)(mc[0] * Hc[0] + mc[1] * Hc[1] + mc[2] * Hc[2]);
+        const double gi = a.mgi ? (double)a.mgi[cell] : 1.0;
+        acc[3] += a.ecub * (double)dens -
+                  w * gi * (double)(mc[0] * Hc[0] + mc[1] * Hc[1] + mc[2] * Hc[2]);
       }
-      acc[4] += (double)(mc[0] * Hz[0] + mc[1] * Hz[1] + mc[2] * Hz[2]);
+      acc[4] += w * (double)(mc[0] * Hz[0] + mc[1] * Hz[1] + mc[2] * Hz[2]);
       continue;
     }
     T H[3];
@@ -1029,27 +1094,33 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       uint32_t gen;
       const uint64_t sn = noise_step(a, r, step_now, gen);
       thermal_eta<T>(a.seeds[r], (uint32_t)cell, sn, eta, gen);
+      const T sg = a.sgc ? sigma * a.sgc[cell] : sigma;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) H[c] += sigma * eta[c];
+      for (int c = 0; c < 3; ++c) H[c] += sg * eta[c];
     }
     if (MODE == FM_FIELD) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) out_r[c * N + cell] = H[c];
       continue;
     }
+    // the cell's damping and spin-transfer strength (per-cell materials)
+    const T gpm = a.gpc ? a.gpc[cell] : a.gpm;
+    const T alpha = a.alc ? a.alc[cell] : a.alpha;
+    const T bJc = a.mgi ? bJ * a.mgi[cell] : bJ;
     T k[3], tau[3];
-    cell_torque(a, bJ, mc, H, k, tau);
+    cell_torque(a, gpm, alpha, bJc, mc, H, k, tau);
     if (MODE == FM_TORQUE || MODE == FM_RKK) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) out_r[c * N + cell] = k[c];
     } else if (MODE == FM_HEUN1) {
       T k1v[3], mn[3];
-      heun_predict(a, a.rot != 0, mc, H, k, tau, dt, k1v, mn);
+      heun_predict(gpm, alpha, a.rot != 0, mc, H, k, tau, dt, k1v, mn);
+      const T ws = a.msr ? a.msr[cell] : T(1);  // transform input M = Ms_i m
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         if (a.rot) k1_r[c * N + cell] = k1v[c];
         mout_r[c * N + cell] = mn[c];
-        if (fwd) F[(c * L + l) * 2 * hx + x] = mn[c];
+        if (fwd) F[(c * L + l) * 2 * hx + x] = a.msr ? ws * mn[c] : mn[c];
       }
     } else if (MODE == FM_HEUN2) {
       T mo[3], k1v[3];
@@ -1057,11 +1128,12 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
       if (a.rot) ld3(k1_r, N, cell, k1v);
       else k1v[0] = k1v[1] = k1v[2] = T(0);
       T mn[3];
-      heun_correct(a, a.rot != 0, mc, H, k, tau, mo, k1v, dt, mn);
+      heun_correct(gpm, alpha, a.rot != 0, mc, H, k, tau, mo, k1v, dt, mn);
+      const T ws = a.msr ? a.msr[cell] : T(1);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         mout_r[c * N + cell] = mn[c];
-        if (fwd) F[(c * L + l) * 2 * hx + x] = mn[c];
+        if (fwd) F[(c * L + l) * 2 * hx + x] = a.msr ? ws * mn[c] : mn[c];
       }
       acc[0] += mz_checked(mn);
     } else if (MODE == FM_RK7) {

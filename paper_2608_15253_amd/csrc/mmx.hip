@@ -163,6 +163,12 @@ struct Group {
   Buf nblk_dev;            // int: the last corrector's workgroups per replica
   Buf topo_part;           // per-workgroup partial sums of the topological charge
   int acell_on = 0, jrep_on = 0;
+  // per-cell Ms, alpha, Ku, D (mmx_set_material_cells): host values (empty:
+  // uniform) and the derived device arrays of FArgs (msr, mgi, gpc, alc, sgc,
+  // kuc, dmc)
+  std::vector<double> cMs, calpha, cKu, cD;
+  Buf cell[7];
+  int cells_on = 0;
   std::vector<std::vector<unsigned char>> tables;  // host twiddle tables (tw_x, wpost, tw_y, tw_z)
   double stt_p[3] = {0, 0, 1}, stt_P = 0, stt_lambda = 1, stt_eps2 = 0;
   int nblk = 1;       // k_fields workgroups per replica
@@ -526,6 +532,7 @@ void arena_walk(mmx_ctx* ctx, F&& take) {
     take(G.S_init, (size_t)G.R * 3 * G.nz * G.Sy * G.Kx * c);
     take(G.Jrep, (size_t)G.R * sizeof(double));
     take(G.Acell, (size_t)G.N * w);
+    for (int j = 0; j < 7; ++j) take(G.cell[j], (size_t)G.N * w);
     take(G.nblk_dev, sizeof(int));
     take(G.topo_part, (size_t)G.R * topo_blocks(G) * sizeof(double));
   }
@@ -706,8 +713,8 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   a.gpm = (T)(kGamma0 / (1.0 + G.mat.alpha * G.mat.alpha) * kMu0);
   a.alpha = (T)G.mat.alpha;
   unsigned t = terms;
-  if (G.mat.Ku == 0) t &= ~T_ANIS;
-  if (G.mat.D == 0) t &= ~T_DMI;
+  if (G.mat.Ku == 0 && G.cKu.empty()) t &= ~T_ANIS;
+  if (G.mat.D == 0 && G.cD.empty()) t &= ~T_DMI;
   if (G.ext.Db == 0) t &= ~T_DMI_BULK;
   if (G.ext.Kc1 == 0 && G.ext.Kc2 == 0) t &= ~T_CUBIC;
   if (G.ext.rkky == 0 || G.nz < 2) t &= ~T_RKKY;
@@ -732,6 +739,20 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   a.rkz0 = G.ext.rkky_z[0];
   a.rkz1 = G.ext.rkky_z[1];
   a.Acell = G.acell_on ? G.Acell.as<T>() : nullptr;
+  // per-cell Ms, alpha, Ku, D
+  a.c2ms = (T)(2.0 / mu0Ms);
+  a.Agrp = (T)G.mat.A;
+  a.sigunit = 2.0 * kKB / (kMu0 * kMu0 * G.mat.Ms * (G.g.cell[0] * G.g.cell[1] * G.g.cell[2]) * kGamma0);
+  if (G.cells_on) {
+    const bool ms = !G.cMs.empty(), al = !G.calpha.empty() || ms;
+    a.msr = ms ? G.cell[0].as<T>() : nullptr;
+    a.mgi = ms ? G.cell[1].as<T>() : nullptr;
+    a.gpc = !G.calpha.empty() ? G.cell[2].as<T>() : nullptr;
+    a.alc = !G.calpha.empty() ? G.cell[3].as<T>() : nullptr;
+    a.sgc = al ? G.cell[4].as<T>() : nullptr;
+    a.kuc = !G.cKu.empty() ? G.cell[5].as<T>() : nullptr;
+    a.dmc = !G.cD.empty() ? G.cell[6].as<T>() : nullptr;
+  }
   a.exs = (T)(2.0 / mu0Ms);
   a.dhalf = (T)(0.5 * G.mat.D);
   a.dbhalf = (T)(0.5 * G.ext.Db);
@@ -776,7 +797,7 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
   } else {
     if (!(mode == FM_HEUN1 || mode == FM_HEUN2 || mode == -1) || !(a.terms & T_DEMAG)) return false;
     if (mode != -1 && !a.fwd) return false;
-    if (G.xone || a.hext || a.hd_out) return false;
+    if (G.xone || a.hext || a.hd_out || G.cells_on) return false;
     // the register row kernels take neither the further field terms nor the
     // bulk-DMI edge ghosts
     if ((a.terms & (T_DMI_BULK | T_CUBIC | T_RKKY)) || a.kbb != 0 || a.Acell) return false;
@@ -893,6 +914,7 @@ mmx_status launch_xfwd(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb
   x.mout = reinterpret_cast<T*>(cb.mout);
   x.normalise = cb.normalise;
   x.nonfinite = (cb.normalise && cb.check_finite) ? ctx->nfflag.as<int>() : nullptr;
+  x.msr = (G.cells_on && !G.cMs.empty()) ? G.cell[0].as<T>() : nullptr;
   x.do_fft = demag ? 1 : 0;
   x.S = G.S.as<cpx<T>>();
   x.tw = G.tw_x.as<cpx<T>>();
@@ -1479,7 +1501,7 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
     int roff = 0;
     for (size_t gi = 0; gi < ctx->groups.size(); ++gi) {
       Group& G = *ctx->groups[gi];
-      if (G.N == 1 && !(ctx->terms & MMX_DEMAG) && ctx->path != MMX_PATH_STAGED) {
+      if (G.N == 1 && !(ctx->terms & MMX_DEMAG) && ctx->path != MMX_PATH_STAGED && !G.cells_on) {
         MacroRefill<T> mr{};
         if (refill) {
           MMX_TRY(refill_begin<T>(ctx, G, *rf, roff, step0));
@@ -1500,7 +1522,7 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
         return fail(MMX_EUNSUP, "group does not fit the replica-resident path");
       const bool stt = ((ctx->terms & MMX_STT) && G.jrep_on && G.stt_P != 0) ||
                        G.ext.Db != 0 || ((ctx->terms & MMX_ANIS_CUBIC) && (G.ext.Kc1 != 0 || G.ext.Kc2 != 0)) ||
-                       ((ctx->terms & MMX_RKKY) && G.ext.rkky != 0) || G.acell_on;
+                       ((ctx->terms & MMX_RKKY) && G.ext.rkky != 0) || G.acell_on || G.cells_on;
       if (stt && ctx->path == MMX_PATH_FUSED)
         return fail(MMX_EUNSUP, "the spin-transfer torque and further field terms run on the "
                                 "staged path only");
@@ -2087,6 +2109,35 @@ mmx_status autotune_impl(mmx_ctx* ctx) {
   return MMX_OK;
 }
 
+// Derived per-cell arrays of group G from its per-cell values (FP64 on the
+// host, rounded to the context precision once) and the group's material.
+template <typename T>
+mmx_status upload_cells(mmx_ctx* ctx, Group& G) {
+  if (!G.cells_on) return MMX_OK;
+  const size_t n = (size_t)G.N;
+  std::vector<T> v[7];
+  for (auto& x : v) x.assign(n, T(0));
+  const double Msg = G.mat.Ms;
+  for (size_t i = 0; i < n; ++i) {
+    const double Ms = G.cMs.empty() ? Msg : G.cMs[i];
+    const double al = G.calpha.empty() ? G.mat.alpha : G.calpha[i];
+    const double Ku = G.cKu.empty() ? G.mat.Ku : G.cKu[i];
+    const double D = G.cD.empty() ? G.mat.D : G.cD[i];
+    v[0][i] = (T)(Ms / Msg);
+    v[1][i] = (T)(Msg / Ms);
+    v[2][i] = (T)(kGamma0 / (1.0 + al * al) * kMu0);
+    v[3][i] = (T)al;
+    v[4][i] = (T)std::sqrt(al * Msg / Ms);
+    v[5][i] = (T)(2.0 * Ku / (kMu0 * Msg));
+    v[6][i] = (T)D;
+  }
+  for (int j = 0; j < 7; ++j)
+    HIP_TRY(hipMemcpyAsync(G.cell[j].p, v[j].data(), n * sizeof(T), hipMemcpyHostToDevice,
+                           ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  return MMX_OK;
+}
+
 mmx_status check_group_idx(const mmx_ctx* c, int32_t g) {
   MMX_TRY(check_ctx(c));
   if (g < 0 || g >= (int)c->groups.size()) return fail(MMX_EINVAL, "group index out of range");
@@ -2189,7 +2240,8 @@ mmx_status mmx_set_material(mmx_ctx* ctx, int32_t group, const mmx_material* mat
   G.mat = *mat;
   G.mat_set = 1;
   G.demag_built = 0;
-  return MMX_OK;
+  // the derived per-cell arrays are relative to the group's material
+  return ctx->prec == MMX_F64 ? upload_cells<double>(ctx, G) : upload_cells<float>(ctx, G);
 }
 
 mmx_status mmx_set_material_ext(mmx_ctx* ctx, int32_t group, const mmx_material_ext* ext) {
@@ -2238,6 +2290,61 @@ mmx_status mmx_set_exchange_cells(mmx_ctx* ctx, int32_t group, const double* A) 
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   G.acell_on = 1;
   return MMX_OK;
+}
+
+mmx_status mmx_set_material_cells(mmx_ctx* ctx, int32_t group, const void* Ms, const void* A,
+                                  const void* alpha, const void* Ku, const void* D) {
+  MMX_TRY(check_group_idx(ctx, group));
+  ctx->epoch++;
+  Group& G = *ctx->groups[group];
+  if (!G.mat_set) return fail(MMX_ESTATE, "set the group's material first");
+  const size_t n = (size_t)G.N, es = esize(ctx);
+  // read each given device array (context element type) to the host
+  auto fetch = [&](const void* src, std::vector<double>& out) -> mmx_status {
+    out.clear();
+    if (!src) return MMX_OK;
+    std::vector<unsigned char> raw(n * es);
+    HIP_TRY(hipMemcpyAsync(raw.data(), src, raw.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    out.resize(n);
+    for (size_t i = 0; i < n; ++i)
+      out[i] = es == 8 ? reinterpret_cast<const double*>(raw.data())[i]
+                       : (double)reinterpret_cast<const float*>(raw.data())[i];
+    return MMX_OK;
+  };
+  std::vector<double> vMs, vA, val, vKu, vD;
+  MMX_TRY(fetch(Ms, vMs));
+  MMX_TRY(fetch(A, vA));
+  MMX_TRY(fetch(alpha, val));
+  MMX_TRY(fetch(Ku, vKu));
+  MMX_TRY(fetch(D, vD));
+  for (size_t i = 0; i < n; ++i) {
+    if (!vMs.empty() && !(vMs[i] > 0 && std::isfinite(vMs[i])))
+      return fail(MMX_EINVAL, "per-cell Ms must be finite and > 0");
+    if (!vA.empty() && !(vA[i] >= 0 && std::isfinite(vA[i])))
+      return fail(MMX_EINVAL, "per-cell A must be finite and >= 0");
+    if (!val.empty() && !(val[i] >= 0 && std::isfinite(val[i])))
+      return fail(MMX_EINVAL, "per-cell alpha must be finite and >= 0");
+    if ((!vKu.empty() && !std::isfinite(vKu[i])) || (!vD.empty() && !std::isfinite(vD[i])))
+      return fail(MMX_EINVAL, "per-cell Ku and D must be finite");
+  }
+  // per-cell A: the exchange stiffness of mmx_set_exchange_cells
+  if (!vA.empty()) {
+    std::vector<unsigned char> buf(n * es);
+    for (size_t i = 0; i < n; ++i) {
+      if (es == 8) reinterpret_cast<double*>(buf.data())[i] = vA[i];
+      else reinterpret_cast<float*>(buf.data())[i] = (float)vA[i];
+    }
+    HIP_TRY(hipMemcpyAsync(G.Acell.p, buf.data(), buf.size(), hipMemcpyHostToDevice, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  G.acell_on = vA.empty() ? 0 : 1;
+  G.cMs = std::move(vMs);
+  G.calpha = std::move(val);
+  G.cKu = std::move(vKu);
+  G.cD = std::move(vD);
+  G.cells_on = (!G.cMs.empty() || !G.calpha.empty() || !G.cKu.empty() || !G.cD.empty()) ? 1 : 0;
+  return ctx->prec == MMX_F64 ? upload_cells<double>(ctx, G) : upload_cells<float>(ctx, G);
 }
 
 mmx_status mmx_set_terms(mmx_ctx* ctx, uint32_t mask) {

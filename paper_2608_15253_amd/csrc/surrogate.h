@@ -86,6 +86,7 @@ mmx_status rk45_surrogate_impl(mmx_ctx* ctx, mmx_fno* f, const float* prm, void*
   if (G.nz != 1 || G.nx != f->W || G.ny != f->H)
     return fail(MMX_ESHAPE, "network grid differs from the film");
   if (G.R > f->Bmax) return fail(MMX_ESHAPE, "more replicas than the network's batch_max");
+  if (G.cells_on) return fail(MMX_EUNSUP, "learned demag stages with per-cell materials");
   if (!(gate_tol >= 0)) return fail(MMX_EINVAL, "gate_tol must be >= 0");
   if (exact_after_fail < 0) return fail(MMX_EINVAL, "exact_after_fail must be >= 0");
   if (gate_cap > 0 && !gate_log) return fail(MMX_EINVAL, "gate_log is null");
