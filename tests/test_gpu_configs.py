@@ -4,10 +4,12 @@ replay), the 512 x 512 periodic skyrmion film in the precision form (local
 terms against the oracle at full size, demag by properties, FP32 against the
 FP64 path), and a 3-D block relaxation against the oracle.
 
-The 512 x 512 film is beyond the oracle for the demag term (its kernel with
-ten periodic images would take hours in numpy); there the FP64 GPU path, which
-matches the oracle to 1e-12 on every smaller periodic, DMI and anisotropy
-case, is the reference for the FP32 path.
+With the workload's ten periodic images the 512 x 512 film's demag kernel is
+beyond the oracle (hours in numpy); here the FP64 GPU path is the reference
+for the FP32 path.  The same film with one image per side, which the oracle
+builds in a minute, is checked against the oracle at full size in
+test_gpu_precision_form.py (the image count does not enter the parity: both
+sides share the image rule).
 """
 import numpy as np
 import pytest

@@ -118,15 +118,29 @@ def test_rk45_relaxation_matches_oracle(prec):
         mmx.mmx_destroy(ctx)
     assert st.t == t_end and st.accepted == len(dts)
     ref = oit.rk45_run(m0[0], case.grid, case.material(), 0.0, t_end, 1e-6, 1e-14)
-    if prec == 2:
-        # same controller decisions, same states
-        assert st.accepted == ref.accepted and st.rejected == ref.rejected
-        assert np.allclose(dts, ref.dts, rtol=1e-9, atol=0)
-        assert np.abs(got[0] - ref.m).max() <= 1e-11
     # dt replay: oracle integrates exactly the GPU's accepted steps
     rep = oit.rk45_run(m0[0], case.grid, case.material(), 0.0, t_end, 1e-6, dt_replay=dts)
     err = np.abs(got[0] - rep.m).max()
-    assert err <= TOLM[prec] * (10 if prec == 2 else 1), err
+    if prec == 2:
+        # The relaxation from a random state amplifies round-off (domains form
+        # from an unstable start): the FP64 bar is 1e-12 or, if larger, ten
+        # times the oracle's own spread over the same steps for a 1e-15
+        # perturbation of the initial state.
+        rng = np.random.default_rng(0)
+        mp = m0[0] + 1e-15 * rng.standard_normal(m0[0].shape)
+        mp /= np.linalg.norm(mp, axis=0, keepdims=True)
+        spread = np.abs(oit.rk45_run(mp, case.grid, case.material(), 0.0, t_end, 1e-6,
+                                     dt_replay=dts).m - rep.m).max()
+        bar = max(10 * spread, 1e-12)
+        print(f"FP64 replay error {err:.2e}, own-controller error "
+              f"{np.abs(got[0] - ref.m).max():.2e}, oracle spread {spread:.2e}")
+        # same controller decisions, same states
+        assert st.accepted == ref.accepted and st.rejected == ref.rejected
+        assert np.allclose(dts, ref.dts, rtol=1e-9, atol=0)
+        assert np.abs(got[0] - ref.m).max() <= bar
+        assert err <= bar, err
+    else:
+        assert err <= TOLM[prec], err
 
 
 @pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])

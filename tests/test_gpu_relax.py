@@ -85,5 +85,15 @@ def test_relax_matches_oracle_fp64():
           f"torque {tq:.3e} / {tq_ref:.3e}")
     assert st.t == t and tq <= 1e8
     assert abs(st.accepted - acc) <= 2 and abs(st.rejected - rej) <= 2
-    assert np.abs(got[0] - m).max() <= 1e-8
+    # Both sides take their own controller decisions over ~2 ns from a random
+    # state, which amplifies round-off: the bar is 1e-12 or, if larger, ten
+    # times the oracle's own spread for a 1e-15 perturbation of the start.
+    rng = np.random.default_rng(0)
+    mp = m0[0] + 1e-15 * rng.standard_normal(m0[0].shape)
+    mp /= np.linalg.norm(mp, axis=0, keepdims=True)
+    m2 = oit.relax_run(mp, case.grid, case.material(), 1e8, 2e-9, 1e-6)[0]
+    spread = np.abs(m2 - m).max()
+    err = np.abs(got[0] - m).max()
+    print(f"relax FP64 error {err:.2e}, oracle spread {spread:.2e}")
+    assert err <= max(10 * spread, 1e-12)
     assert abs(tq - tq_ref) <= 1e-6 * tq_ref
