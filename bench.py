@@ -293,6 +293,7 @@ def bench_skyrmion512(args):
                               width=5.05e-9, periodic=True)
     m0 = m0[None].astype(np.float32).astype(np.float64)
     out = {}
+    dts32 = None
     for prec, dt_ in ((mmx.MMX_F32, torch.float32), (mmx.MMX_F64, torch.float64)):
         ctx = _ctx_for([w], prec)
         m = torch.tensor(m0, dtype=dt_, device="cuda:0").contiguous()
@@ -301,6 +302,14 @@ def bench_skyrmion512(args):
         st = mmx.mmx_rk45(ctx, m, 0.0, t_end, x["tol"])
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
+        if prec == mmx.MMX_F32:
+            dts32 = mmx.mmx_rk45_dts(ctx)
+        else:
+            # the FP32 run's accepted steps replayed in FP64: the difference
+            # is the FP32 arithmetic alone (no divergence of step sequences)
+            mr = torch.tensor(m0, dtype=dt_, device="cuda:0").contiguous()
+            mmx.mmx_rk45(ctx, mr, 0.0, float(sum(dts32)), x["tol"], dt_replay=dts32)
+            out["replay64"] = mr.double().cpu().numpy()
         E = torch.zeros((1, 6), dtype=torch.float64, device="cuda:0")
         Q = torch.zeros(1, dtype=torch.float64, device="cuda:0")
         mmx.mmx_energy(ctx, m, E)
@@ -321,6 +330,7 @@ def bench_skyrmion512(args):
             "fp64": {"seconds": t64, "accepted": s64.accepted, "rejected": s64.rejected,
                      "energy_J": e64, "Q": q64},
             "max_dm_fp32_vs_fp64": float(np.abs(m32 - m64).max()),
+            "max_dm_fp32_vs_fp64_replay_of_fp32_steps": float(np.abs(m32 - out["replay64"]).max()),
             "rel_dE_total": abs(e32[5] - e64[5]) / abs(e64[5]), "dQ": abs(q32 - q64)}
 
 
@@ -542,6 +552,94 @@ def bench_fields_ext(args):
             "kernels": {k: {"avg_us": v[0] / v[1] * 1e3, "launches": v[1]} for k, v in prof.items()}}
 
 
+def bench_histogram(args):
+    """The batching form's stated output: 1024 replicas of the switching film
+    (64x64x1, 4 nm cells, Ku 5e5 along z, Bz = -0.15 T, 300 K, per-replica
+    Philox keys) advanced by Heun with dt = 1e-14 s for 2e5 steps (2 ns),
+    FP32; switching time = first step after which the replica-mean m_z is
+    negative; histogram of 200 bins over [0, 2 ns] plus the unswitched count.
+    The first --f64-replicas replicas (same keys) are run again in FP64 and
+    the two switching-time samples compared by a two-sample KS test; a few
+    replicas are checked against the FP64 oracle over a short horizon."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from scipy import stats
+    from workloads import replica_seeds, uniform
+    R, dt = args.replicas, 1e-14
+    nsteps = args.hist_steps
+    chunk = 10000
+    seeds = replica_seeds(3, R)
+    bz = args.hist_bz
+    out = {}
+    for prec, nrep in ((mmx.MMX_F32, R), (mmx.MMX_F64, args.f64_replicas)):
+        tdt = torch.float32 if prec == mmx.MMX_F32 else torch.float64
+        ctx = setup(nrep, prec, seeds[:nrep])
+        mmx.mmx_set_field(ctx, 0, (0.0, 0.0, bz))
+        m = torch.tensor(uniform((64, 64, 1), replicas=nrep), dtype=tdt, device="cuda:0")
+        tsw = torch.full((nrep,), -1.0, dtype=torch.float64, device="cuda:0")
+        mz = []
+        t0 = time.perf_counter()
+        for s0 in range(0, nsteps, chunk):
+            n = min(chunk, nsteps - s0)
+            mmx.mmx_heun(ctx, m, dt, n, s0, tsw)
+            mmx.mmx_sync(ctx)
+            mz.append(float(m.view(nrep, 3, -1)[:, 2].double().mean()))
+            print(f"  prec {prec}: step {s0 + n} of {nsteps}, {time.perf_counter() - t0:.1f} s, "
+                  f"<m_z> {mz[-1]:.4f}, switched {int((tsw > 0).sum())}", file=sys.stderr,
+                  flush=True)
+        el = time.perf_counter() - t0
+        ts = tsw.cpu().numpy()
+        mmx.mmx_destroy(ctx)
+        out[prec] = (ts, el, mz)
+    t_end = nsteps * dt
+    edges = np.linspace(0.0, t_end, 201)
+    res = {}
+    for prec, (ts, el, mz) in out.items():
+        sw = ts[ts > 0]
+        hist, _ = np.histogram(sw, bins=edges)
+        res["f32" if prec == mmx.MMX_F32 else "f64"] = {
+            "replicas": int(ts.size), "seconds": el, "switched": int(sw.size),
+            "unswitched": int(ts.size - sw.size),
+            "hist_counts": hist.tolist(), "mean_mz_every_1e4_steps": mz,
+            "t_sw_quantiles_s": (np.quantile(sw, [0.1, 0.5, 0.9]).tolist() if sw.size else None)}
+    s32 = out[mmx.MMX_F32][0]
+    s64 = out[mmx.MMX_F64][0]
+    a, b = s32[s32 > 0], s64[s64 > 0]
+    ks = stats.ks_2samp(a, b) if a.size >= 5 and b.size >= 5 else None
+    # the same keys give the same noise: per-replica switching times of the
+    # replicas run in both precisions
+    nr = s64.size
+    both = (s32[:nr] > 0) & (s64 > 0)
+    # oracle subset: the first replicas over a short horizon, FP64 GPU vs FP64 oracle
+    from oracle import Grid, Material
+    from oracle import integrators as oit
+    ro, so = 4, args.oracle_steps
+    ctx = setup(ro, mmx.MMX_F64, seeds[:ro])
+    mmx.mmx_set_field(ctx, 0, (0.0, 0.0, bz))
+    m0 = uniform((64, 64, 1), replicas=ro)
+    m = torch.tensor(m0, dtype=torch.float64, device="cuda:0")
+    mmx.mmx_heun(ctx, m, dt, so, 0, None)
+    gpu = m.cpu().numpy()
+    mmx.mmx_destroy(ctx)
+    grid = Grid((64, 64, 1), (4e-9, 4e-9, 4e-9))
+    mat = Material(Ms=8.0e5, A=1.3e-11, alpha=0.02, Ku=5e5, B=(0, 0, bz), T=300.0)
+    ref = oit.heun_run(m0, grid, mat, dt, so, seed=np.array(seeds[:ro]), step0=0)
+    return {"metric": "switching-time histogram, batching form (Heun, 2e5 steps)",
+            "value": R * 4096 * nsteps / out[mmx.MMX_F32][1], "unit": "cell-steps/s",
+            "n_gpus": 1, "steps": nsteps, "higher_is_better": True, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": "thermal_switching_64x64x1_R1024_heun_2e5", "dt_s": dt,
+                       "T_K": 300, "Bz_T": bz, "bins": 200, "t_range_s": [0.0, t_end]},
+            "histogram": res,
+            "ks_f32_vs_f64": ({"statistic": float(ks.statistic), "pvalue": float(ks.pvalue)}
+                              if ks is not None else None),
+            "same_key_replicas_switched_in_both": int(both.sum()),
+            "same_key_max_abs_dt_sw_s": (float(np.abs(s32[:nr][both] - s64[both]).max())
+                                         if both.any() else None),
+            "oracle_subset": {"replicas": ro, "steps": so,
+                              "max_abs_dm_gpu_f64_vs_oracle": float(np.abs(gpu - ref).max())}}
+
+
 def setup(R, prec, seeds, n=(64, 64, 1)):
     import torch
     import paper_2608_15253_amd as mmx
@@ -635,9 +733,17 @@ def main():
     ap.add_argument("--traffic-cmd", default="", help="command line recorded in the summary")
     ap.add_argument("--workload", default="switching",
                     choices=["switching", "uneven", "closure", "skyrmion512", "depondt", "stt",
-                             "throughput", "fields_ext"],
+                             "throughput", "fields_ext", "histogram"],
                     help="switching: the benchmark line; the others measure the other "
                          "workload configurations (one JSON line each)")
+    ap.add_argument("--hist-steps", type=int, default=200000,
+                    help="histogram: Heun steps (2e5 = 2 ns)")
+    ap.add_argument("--f64-replicas", type=int, default=256,
+                    help="histogram: replicas rerun in FP64")
+    ap.add_argument("--hist-bz", type=float, default=-0.15,
+                    help="histogram: applied field along z (T)")
+    ap.add_argument("--oracle-steps", type=int, default=1000,
+                    help="histogram: steps of the oracle subset check")
     ap.add_argument("--t-end", type=float, default=None,
                     help="closure / skyrmion512: integration horizon (s)")
     args = ap.parse_args()
@@ -655,7 +761,8 @@ def main():
                           "skyrmion512": bench_skyrmion512,
                           "depondt": bench_depondt, "stt": bench_stt,
                           "throughput": bench_throughput,
-                          "fields_ext": bench_fields_ext}[args.workload](args)))
+                          "fields_ext": bench_fields_ext,
+                          "histogram": bench_histogram}[args.workload](args)))
         return
     # the CPU baseline runs first: its worker processes are forked before
     # this process initialises the GPU

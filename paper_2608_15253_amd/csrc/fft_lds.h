@@ -99,6 +99,33 @@ struct Dft {
     v[0] = e[0]; v[2] = e[1]; v[4] = e[2]; v[6] = e[3];
     v[1] = o[0]; v[3] = o[1]; v[5] = o[2]; v[7] = o[3];
   }
+  // 12-point DFT as 3 x 4: DFT3 over n1 of x[4 n1 + n2], twiddle w12^(n2 k1),
+  // DFT4 over n2; output index k1 + 3 k2.
+  static __device__ inline void r12(cpx<T>* v) {
+    const T h = T(0.86602540378443864676);
+    // w12^j = cos(2 pi j / 12) -/+ i sin(2 pi j / 12) for j = 0..6
+    const T wc[7] = {T(1), h, T(0.5), T(0), T(-0.5), -h, T(-1)};
+    const T ws[7] = {T(0), T(0.5), h, T(1), h, T(0.5), T(0)};
+    cpx<T> a[4][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cpx<T> t[3] = {v[n2], v[4 + n2], v[8 + n2]};
+      r3(t);
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) {
+        const int j = n2 * k1;
+        const cpx<T> w = {wc[j], INV ? ws[j] : -ws[j]};
+        a[n2][k1] = (j == 0) ? t[k1] : cmul(t[k1], w);
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      cpx<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      r4(t);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 3 * k2] = t[k2];
+    }
+  }
   // 16-point DFT as 4 x 4: DFT4 over n1 of x[4 n1 + n2], twiddle w16^(n2 k1),
   // DFT4 over n2; output index k1 + 4 k2.
   static __device__ inline void r16(cpx<T>* v) {

@@ -786,8 +786,8 @@ FArgs<T> field_args(const mmx_ctx* ctx, const Group& G, uint32_t terms) {
   return a;
 }
 
-// Heun stages of FP32 films whose x half-length is 16, 32, 64, 128 or 256
-// (4 x 4, 4 x 8, 8 x 8, 8 x 16, 16 x 16): the register row kernel (mode
+// Heun stages of FP32 grids whose x half-length is 16, 32, 64, 96, 128 or 256
+// (4 x 4, 4 x 8, 8 x 8, 8 x 12, 8 x 16, 16 x 16): the register row kernel (mode
 // FM_HEUN1 / FM_HEUN2) or its forward-only part (mode -1, the half spectrum
 // of the state a.m); false if not applicable.
 template <typename T>
@@ -830,6 +830,7 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
       case 16: return MMX_ROWS(4, 4, 16);
       case 32: return MMX_ROWS(4, 8, 16);
       case 64: return MMX_ROWS(8, 8, 8);
+      case 96: return MMX_ROWS(8, 12, 8);
       case 128: return MMX_ROWS(8, 16, 8);
       case 256: return MMX_ROWS(16, 16, 4);
       default: return false;
@@ -2105,6 +2106,10 @@ mmx_status autotune_impl(mmx_ctx* ctx) {
       G.fused_faster = fused_ms < staged_ms ? 1 : 0;
     }
   }
+  // the timing runs step scratch states (a zero state normalises to NaN):
+  // they must not leave the non-finite flag for the caller's next check
+  k_fill_i32<<<1, 64, 0, ctx->stream>>>(ctx->nfflag.as<int>(), 1, 0);
+  HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   return MMX_OK;
 }

@@ -4,7 +4,7 @@
 // demag spectrum, local fields, torque, predictor or corrector update, and the
 // forward x transform
 // of the state just written, for films whose half-length x transform has
-// hx = N1 * N2 points (4 x 4, 4 x 8, 8 x 8, 8 x 16, 16 x 16).
+// hx = N1 * N2 points (4 x 4, 4 x 8, 8 x 8, 8 x 12, 8 x 16, 16 x 16).
 //
 // One wave holds RPW = 64 / N1 grid rows, N1 lanes per row.  A transform of
 // a row, X[c + N1 d] = sum_k x[k] w^(+-k (c + N1 d)), splits k = a + N2 b:
@@ -31,21 +31,39 @@
 
 namespace mmx {
 
+// Split of a line of hx = N1 N2 points over N1 lanes: lane q holds the a =
+// q + N1 s < N2 (s < S2); when N1 does not divide N2 the lanes with q >=
+// N2 - N1 (S2 - 1) have one value slot less, and NV = S2 N1 >= N2 slots per
+// component hold a line.
+template <int N1, int N2>
+struct RowSplit {
+  static constexpr int S2 = (N2 + N1 - 1) / N1, NV = S2 * N1, n = N1 * N2;
+  static constexpr bool even = N2 % N1 == 0;
+  // whether lane q holds a = q + N1 s
+  static __device__ inline bool has(int q, int s) { return even || q + N1 * s < N2; }
+  // table index of w^(a c) (a c < n); powers of two keep their mask form
+  static __device__ inline int tw(int ac) { return ((n & (n - 1)) == 0) ? (ac & (n - 1)) : ac; }
+};
+
 // One N1 x N2 transform of a line held by N1 lanes: in, v[s N1 + b] =
-// x[q + N1 s + N2 b] (s < N2 / N1, b < N1); out, v[d] = X[q + N1 d]
-// (d < N2).  E: N1 (N2 + 1) LDS slots of this line (workgroup barriers).
-template <typename T, int N1, int N2, bool INV>
-__device__ inline void line_transform(cpx<T> (&v)[N2], cpx<T>* E, int q,
+// x[q + N1 s + N2 b] (s < S2 with q + N1 s < N2, b < N1); out, v[d] =
+// X[q + N1 d] (d < N2).  E: N1 (N2 + 1) LDS slots of this line (workgroup
+// barriers).
+template <typename T, int N1, int N2, bool INV, int NV>
+__device__ inline void line_transform(cpx<T> (&v)[NV], cpx<T>* E, int q,
                                       const cpx<T>* __restrict__ tw) {
-  constexpr int n = N1 * N2, S2 = N2 / N1, STR = N2 + 1;
+  using RS = RowSplit<N1, N2>;
+  static_assert(NV == RS::NV, "line storage");
+  constexpr int S2 = RS::S2, STR = N2 + 1;
 #pragma unroll
   for (int s = 0; s < S2; ++s) {
     const int av = q + N1 * s;
+    if (!RS::has(q, s)) continue;
     dft_reg<T, INV, N1>(&v[s * N1]);
     E[av] = v[s * N1];
 #pragma unroll
     for (int cc = 1; cc < N1; ++cc) {
-      const cpx<T> w = tw[(av * cc) & (n - 1)];
+      const cpx<T> w = tw[RS::tw(av * cc)];
       E[cc * STR + av] = INV ? cmulc(v[s * N1 + cc], w) : cmul(v[s * N1 + cc], w);
     }
   }
@@ -61,8 +79,8 @@ __device__ inline void line_transform(cpx<T> (&v)[N2], cpx<T>* E, int q,
 // kx = q + N1 d and (lane 0) kx = hx; the partner X[hx - kx] comes through
 // LDS, one component at a time (hx slots of E).  Followed by no barrier: E
 // is reused only after the next one.
-template <typename T, int N1, int N2>
-__device__ inline void rows_store_spectrum(const cpx<T> (&v)[3][N2], cpx<T>* E, int q, bool live,
+template <typename T, int N1, int N2, int NV>
+__device__ inline void rows_store_spectrum(const cpx<T> (&v)[3][NV], cpx<T>* E, int q, bool live,
                                            cpx<T>* __restrict__ Srow, size_t cstride,
                                            const cpx<T>* __restrict__ wpost) {
   constexpr int hx = N1 * N2;
@@ -103,8 +121,9 @@ __device__ inline void rows_store_spectrum(const cpx<T> (&v)[3][N2], cpx<T>* E, 
 // an uninterrupted run takes.
 template <typename T, int N1, int N2>
 __global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
-  static_assert(N2 % N1 == 0 && 64 % N1 == 0, "row split");
-  constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = N2 / N1;
+  static_assert(N2 >= N1 && 64 % N1 == 0, "row split");
+  using SP = RowSplit<N1, N2>;
+  constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = SP::S2;
   constexpr int RS = hx + N1;  // transpose slots N1 (N2 + 1); split slots hx
   __shared__ cpx<T> Es[RPW * RS];
   const int lane = threadIdx.x, row = lane / N1, q = lane - row * N1;
@@ -126,7 +145,7 @@ __global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
   __syncthreads();
   const T* __restrict__ mr = a.m + rb;
   const unsigned row0 = (unsigned)a.nx * (unsigned)(y + a.ny * z);
-  cpx<T> v[3][N2];
+  cpx<T> v[3][SP::NV];
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -136,8 +155,8 @@ __global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
         const int k = q + N1 * s + N2 * b;
         const int x = 2 * k;
         cpx<T> p = {0, 0};
-        if (live && x < a.nx) p.re = mr[c * N + row0 + x];
-        if (live && x + 1 < a.nx) p.im = mr[c * N + row0 + x + 1];
+        if (SP::has(q, s) && live && x < a.nx) p.re = mr[c * N + row0 + x];
+        if (SP::has(q, s) && live && x + 1 < a.nx) p.im = mr[c * N + row0 + x + 1];
         v[c][s * N1 + b] = p;
       }
 #pragma unroll
@@ -158,8 +177,9 @@ template <typename T, int N1, int N2, int MODE, bool ROT, bool STT>
 __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   static_assert(MODE == FM_HEUN1 || MODE == FM_HEUN2, "Heun stages only");
   static_assert(sizeof(T) == sizeof(float), "FP32 row kernels");
-  static_assert(N2 % N1 == 0 && 64 % N1 == 0, "row split");
-  constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = N2 / N1;
+  static_assert(N2 >= N1 && 64 % N1 == 0, "row split");
+  using SP = RowSplit<N1, N2>;
+  constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = SP::S2;
   const int nx = a.nx, RS = rows_lds_stride(nx);  // LDS per row (dynamic)
   extern __shared__ unsigned char smem_raw[];
   cpx<T>* Es = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -197,7 +217,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
       sv[c][i] = live ? Srow[c * cstride + q + N1 * i] : cpx<T>{0, 0};
     slast[c] = (live && q == 0) ? Srow[c * cstride + hx] : cpx<T>{0, 0};
   }
-  cpx<T> v[3][N2];
+  cpx<T> v[3][SP::NV];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
@@ -208,6 +228,10 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
     for (int s = 0; s < S2; ++s)
 #pragma unroll
       for (int b = 0; b < N1; ++b) {
+        if (!SP::has(q, s)) {
+          v[c][s * N1 + b] = cpx<T>{0, 0};
+          continue;
+        }
         const int k = q + N1 * s + N2 * b;
         const cpx<T> Xk = E[k];
         cpx<T> Xc = E[hx - k];
@@ -320,8 +344,9 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
 #pragma unroll
       for (int b = 0; b < N1; ++b) {
         const int k = q + N1 * s + N2 * b;
-        v[c][s * N1 + b] = (2 * k < nx) ? cpx<T>{Hs[c * nx + 2 * k], Hs[c * nx + 2 * k + 1]}
-                                        : cpx<T>{0, 0};
+        v[c][s * N1 + b] = (SP::has(q, s) && 2 * k < nx)
+                               ? cpx<T>{Hs[c * nx + 2 * k], Hs[c * nx + 2 * k + 1]}
+                               : cpx<T>{0, 0};
       }
   __syncthreads();
 #pragma unroll

@@ -27,6 +27,7 @@ __device__ inline void dft_reg(cpx<T>* v) {
   if constexpr (R == 2) Dft<T, INV>::r2(v);
   if constexpr (R == 4) Dft<T, INV>::r4(v);
   if constexpr (R == 8) Dft<T, INV>::r8(v);
+  if constexpr (R == 12) Dft<T, INV>::r12(v);
   if constexpr (R == 16) Dft<T, INV>::r16(v);
 }
 

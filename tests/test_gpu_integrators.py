@@ -307,6 +307,9 @@ def test_nonfinite_state_is_reported(prec):
     bad[1, 0, 0, 5, 7] = np.nan
     ctx = open_ctx(case, prec)
     try:
+        # the autotuner's timing runs on scratch states leave no flag behind
+        mmx.mmx_autotune(ctx)
+        mmx.mmx_sync(ctx)
         for run in ("heun", "depondt", "rk4"):
             md = dev(m0, prec)
             getattr(mmx, "mmx_" + run)(ctx, md, 1e-14, 3, *([0] if run != "rk4" else []))
@@ -445,3 +448,33 @@ def test_folded_switching_check_equals_per_step_check():
     print(f"switching times {tone}")
     assert np.all(tone > 0) and np.all(tone < n * 1e-13)
     assert np.array_equal(one, split) and np.array_equal(tone, tsplit)
+
+
+@pytest.mark.parametrize("scheme", ["heun", "depondt"])
+@pytest.mark.parametrize("n", [(96, 40, 1), (96, 24, 2), (64, 20, 2)])
+def test_register_row_kernels_of_uneven_split_and_few_layers(n, scheme):
+    """FP32 Heun / rotation steps on grids whose row pass runs in the register
+    row kernel with the 8 x 12 (radix-3) split of a 96-point half row, and on
+    two-layer grids (one row kernel launch per layer, the fused y-z pass
+    between): against the oracle at the FP32 bar."""
+    import paper_2608_15253_amd as mmx
+    case = Case(n, (4e-9, 4e-9, 3e-9), R=2, alpha=0.05, Ku=5e5, B=(0.0, 0.02, -0.1), T=200.0,
+                seeds=list(replica_seeds(29, 2)),
+                terms=("exchange", "anisotropy", "zeeman", "demag", "thermal"))
+    print(f"[case] rows {n} {scheme}", flush=True)
+    m0 = _round(uniform(case.n, (0.2, 0.1, 1.0), replicas=case.R), 1)
+    ctx = open_ctx(case, 1)
+    try:
+        md = dev(m0, 1)
+        getattr(mmx, "mmx_" + scheme)(ctx, md, 2e-14, 12, 5)
+        mmx.mmx_sync(ctx)
+        got = host(md)
+    finally:
+        mmx.mmx_destroy(ctx)
+    seeds = np.array(case.seeds)
+    if scheme == "heun":
+        ref = oit.heun_run(m0, case.grid, case.material(), 2e-14, 12, seed=seeds, step0=5)
+    else:
+        from oracle import rotation as orot
+        ref = orot.depondt_run(m0, case.grid, case.material(), 2e-14, 12, seed=seeds, step0=5)
+    assert np.abs(got - ref).max() <= TOLM[1]
