@@ -1,0 +1,194 @@
+// Transforms of 3-D grids along y and z with the lines held in registers
+// (device code), the split of yconv_reg.h applied to other axes:
+//
+//  k_ypass_reg  the y transform of one (component, plane) line per column,
+//               forward (input rows y < ny, all Py spectrum rows out) or
+//               inverse (all rows in, rows y < ny out); no tensor product.
+//  k_zline_reg  the z transform of a pillar (ky, kx) of all three
+//               components, the full symmetric tensor product per (kz, ky,
+//               kx) and the inverse z transform, keeping the nz stored planes.
+//
+// A line x[j], j = a + N2 b (a < N2, b < N1), is split over N1 lanes: lane q
+// takes the N1-point DFTs over b for a = q + N1 s, twiddles, one LDS
+// transpose, and the N2-point DFT over a leaves it the outputs q + N1 d.
+// One wave holds NC = 64 / N1 lines of consecutive kx, so each global access
+// covers NC neighbouring columns of one row (plane).  With a zero-padded
+// axis (PRUNE) only b < N1 / 2 carries input and only those outputs are
+// written back.  The arithmetic equals the LDS Stockham passes up to the
+// order of the butterflies.
+#pragma once
+#include "common.h"
+#include "fft_lds.h"
+#include "kernels.h"
+#include "yconv_reg.h"
+
+namespace mmx {
+
+// y pass of 3-D grids: grid (ceil(Kx / NC), 3 nz, R), one wave per workgroup
+template <typename T, int N1, int N2, bool INV, bool PRUNE>
+__global__ void __launch_bounds__(64) k_ypass_reg(YArgs<T> a) {
+  static_assert(N2 % N1 == 0 && 64 % N1 == 0, "line split");
+  constexpr int n = N1 * N2, NC = 64 / N1, S2 = N2 / N1, STR = N2 + 1;
+  constexpr int NB = PRUNE ? N1 / 2 : N1;  // rows y = a + N2 b kept (b < NB)
+  __shared__ cpx<T> E[NC * N1 * STR];
+  __shared__ cpx<T> twl[n];
+  if (a.done && *a.done) return;
+  const int lane = threadIdx.x, wc = lane / N1, q = lane - wc * N1;
+  int tile, line, rep;
+  xcd_block(tile, line, rep);
+  const int kx = tile * NC + wc;
+  const bool live = kx < a.Kx;
+  const unsigned Kx = (unsigned)a.Kx;
+  // the (component, plane) line of the replica; 32-bit offsets on the
+  // workgroup-uniform base
+  cpx<T>* __restrict__ P = a.S + ((size_t)rep * 3 * a.nz + line) * (size_t)a.Sy * Kx;
+  auto at = [&](unsigned row) -> cpx<T>& {
+    return *reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(P) +
+                                      (row * Kx + (unsigned)kx) * (unsigned)sizeof(cpx<T>));
+  };
+  for (int i = lane; i < n; i += 64) twl[i] = a.tw[i];
+  __syncthreads();
+  const cpx<T>* tw = twl;
+  cpx<T>* Ew = E + wc * N1 * STR;
+  cpx<T> X[N2];
+  if constexpr (!INV) {
+    cpx<T> v[S2][N1];
+#pragma unroll
+    for (int s = 0; s < S2; ++s)
+#pragma unroll
+      for (int b = 0; b < N1; ++b)
+        v[s][b] = (b < NB && live) ? at((unsigned)(q + N1 * s + N2 * b)) : cpx<T>{0, 0};
+#pragma unroll
+    for (int s = 0; s < S2; ++s) {
+      const int av = q + N1 * s;
+      dft_reg<T, false, N1>(v[s]);
+      Ew[av] = v[s][0];
+#pragma unroll
+      for (int cc = 1; cc < N1; ++cc) Ew[cc * STR + av] = cmul(v[s][cc], tw[av * cc]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int av = 0; av < N2; ++av) X[av] = Ew[q * STR + av];
+    dft_reg<T, false, N2>(X);
+    if (live) {
+#pragma unroll
+      for (int d = 0; d < N2; ++d) at((unsigned)(q + N1 * d)) = X[d];
+    }
+  } else {
+#pragma unroll
+    for (int d = 0; d < N2; ++d) X[d] = live ? at((unsigned)(q + N1 * d)) : cpx<T>{0, 0};
+    dft_reg<T, true, N2>(X);
+    Ew[q * STR] = X[0];
+#pragma unroll
+    for (int av = 1; av < N2; ++av) Ew[q * STR + av] = cmulc(X[av], tw[av * q]);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S2; ++s) {
+      const int av = q + N1 * s;
+      cpx<T> u[N1];
+#pragma unroll
+      for (int cc = 0; cc < N1; ++cc) u[cc] = Ew[cc * STR + av];
+      dft_reg<T, true, N1>(u);
+      if (live) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) at((unsigned)(av + N2 * b)) = u[b];
+      }
+    }
+  }
+}
+
+// z pass of 3-D grids with the tensor product: grid (ceil(Kx / NC), Py, R),
+// one wave per workgroup; the Pz = N1 N2 point pillar of component c at
+// (ky, kx) is S[((r 3 + c) nz + z) Sy Kx + ky Kx + kx], z < nz
+template <typename T, int N1, int N2, bool PRUNE>
+__global__ void __launch_bounds__(64) k_zline_reg(YArgs<T> a) {
+  static_assert(N2 % N1 == 0 && 64 % N1 == 0, "line split");
+  constexpr int n = N1 * N2, NC = 64 / N1, S2 = N2 / N1, STR = N2 + 1;
+  constexpr int NB = PRUNE ? N1 / 2 : N1;
+  __shared__ cpx<T> E[NC * N1 * STR];
+  __shared__ cpx<T> twl[n];
+  if (a.done && *a.done) return;
+  const int lane = threadIdx.x, wc = lane / N1, q = lane - wc * N1;
+  int tile, ky, rep;
+  xcd_block(tile, ky, rep);
+  const int kx = tile * NC + wc;
+  const bool live = kx < a.Kx;
+  const unsigned Kx = (unsigned)a.Kx, plane = (unsigned)a.Sy * Kx, nz = (unsigned)a.nz;
+  cpx<T>* __restrict__ P = a.S + (size_t)rep * 3 * nz * plane;
+  // element (c, z) of this pillar: 32-bit byte offset on the uniform base
+  auto at = [&](int c, unsigned z) -> cpx<T>& {
+    const unsigned i = ((unsigned)c * nz + z) * plane + (unsigned)ky * Kx + (unsigned)kx;
+    return *reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(P) + i * (unsigned)sizeof(cpx<T>));
+  };
+  // the z pass arguments carry the z twiddles exp(-2 pi i k / Pz) in tw
+  for (int i = lane; i < n; i += 64) twl[i] = a.tw[i];
+  __syncthreads();
+  const cpx<T>* tw = twl;
+  cpx<T>* Ew = E + wc * N1 * STR;
+  cpx<T> X[3][N2];
+  cpx<T> v[S2][N1];
+  auto load = [&](int c) {
+#pragma unroll
+    for (int s = 0; s < S2; ++s)
+#pragma unroll
+      for (int b = 0; b < N1; ++b)
+        v[s][b] = (b < NB && live) ? at(c, (unsigned)(q + N1 * s + N2 * b)) : cpx<T>{0, 0};
+  };
+  load(0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+#pragma unroll
+    for (int s = 0; s < S2; ++s) {
+      const int av = q + N1 * s;
+      dft_reg<T, false, N1>(v[s]);
+      Ew[av] = v[s][0];
+#pragma unroll
+      for (int cc = 1; cc < N1; ++cc) Ew[cc * STR + av] = cmul(v[s][cc], tw[av * cc]);
+    }
+    if (c < 2) load(c + 1);
+    __syncthreads();
+#pragma unroll
+    for (int av = 0; av < N2; ++av) X[c][av] = Ew[q * STR + av];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) dft_reg<T, false, N2>(X[c]);
+  if (live) {
+    // lane q holds kz = q + N1 d of all three components: the product is local
+    const bool ylo = 2 * ky <= a.Py;
+    const int ty = ylo ? ky : a.Py - ky;
+    const T sy = ylo ? T(1) : T(-1);
+#pragma unroll
+    for (int d = 0; d < N2; ++d) {
+      const int kz = q + N1 * d;
+      const bool zlo = 2 * kz <= n;
+      const int tz = zlo ? kz : n - kz;
+      const T sz = zlo ? T(1) : T(-1);
+      tensor_apply(a.Nt, ((size_t)tz * a.Ty + ty) * Kx + kx, sy, sz, sy * sz, true, X[0][d],
+                   X[1][d], X[2][d]);
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    dft_reg<T, true, N2>(X[c]);
+    Ew[q * STR] = X[c][0];
+#pragma unroll
+    for (int av = 1; av < N2; ++av) Ew[q * STR + av] = cmulc(X[c][av], tw[av * q]);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < S2; ++s) {
+      const int av = q + N1 * s;
+      cpx<T> u[N1];
+#pragma unroll
+      for (int cc = 0; cc < N1; ++cc) u[cc] = Ew[cc * STR + av];
+      dft_reg<T, true, N1>(u);
+      if (live) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) at(c, (unsigned)(av + N2 * b)) = u[b];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace mmx

@@ -126,6 +126,48 @@ struct Dft {
       for (int k2 = 0; k2 < 4; ++k2) v[k1 + 3 * k2] = t[k2];
     }
   }
+  // A B-point DFT as A x B: DFT_A over n1 of x[B n1 + n2], twiddle
+  // w^(n2 k1) from the tables (cos, sin of 2 pi j / (A B)), DFT_B over n2;
+  // output index k1 + A k2.
+  template <int A, int B>
+  static __device__ inline void split(cpx<T>* v, const T* wc, const T* ws) {
+    cpx<T> a[B][A];
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) {
+      cpx<T> t[A];
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) t[n1] = v[B * n1 + n2];
+      if constexpr (A == 3) r3(t);
+      if constexpr (A == 4) r4(t);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        const int j = n2 * k1;
+        const cpx<T> w = {wc[j], INV ? ws[j] : -ws[j]};
+        a[n2][k1] = (j == 0) ? t[k1] : cmul(t[k1], w);
+      }
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      cpx<T> t[B];
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) t[n2] = a[n2][k1];
+      if constexpr (B == 8) r8(t);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) v[k1 + A * k2] = t[k2];
+    }
+  }
+  // 24-point DFT as 3 x 8
+  static __device__ inline void r24(cpx<T>* v) {
+    const T wc[15] = {T(1.0), T(0.9659258262890683), T(0.8660254037844386), T(0.7071067811865476), T(0.5), T(0.25881904510252074), T(0.0), T(-0.25881904510252074), T(-0.5), T(-0.7071067811865476), T(-0.8660254037844386), T(-0.9659258262890683), T(-1.0), T(-0.9659258262890683), T(-0.8660254037844386)};
+    const T ws[15] = {T(0.0), T(0.25881904510252074), T(0.5), T(0.7071067811865476), T(0.8660254037844386), T(0.9659258262890683), T(1.0), T(0.9659258262890683), T(0.8660254037844386), T(0.7071067811865476), T(0.5), T(0.25881904510252074), T(0.0), T(-0.25881904510252074), T(-0.5)};
+    split<3, 8>(v, wc, ws);
+  }
+  // 32-point DFT as 4 x 8
+  static __device__ inline void r32(cpx<T>* v) {
+    const T wc[22] = {T(1.0), T(0.9807852804032304), T(0.9238795325112867), T(0.8314696123025452), T(0.7071067811865476), T(0.5555702330196022), T(0.3826834323650898), T(0.19509032201612828), T(0.0), T(-0.19509032201612828), T(-0.3826834323650898), T(-0.5555702330196022), T(-0.7071067811865476), T(-0.8314696123025452), T(-0.9238795325112867), T(-0.9807852804032304), T(-1.0), T(-0.9807852804032304), T(-0.9238795325112867), T(-0.8314696123025452), T(-0.7071067811865476), T(-0.5555702330196022)};
+    const T ws[22] = {T(0.0), T(0.19509032201612828), T(0.3826834323650898), T(0.5555702330196022), T(0.7071067811865476), T(0.8314696123025452), T(0.9238795325112867), T(0.9807852804032304), T(1.0), T(0.9807852804032304), T(0.9238795325112867), T(0.8314696123025452), T(0.7071067811865476), T(0.5555702330196022), T(0.3826834323650898), T(0.19509032201612828), T(0.0), T(-0.19509032201612828), T(-0.3826834323650898), T(-0.5555702330196022), T(-0.7071067811865476), T(-0.8314696123025452)};
+    split<4, 8>(v, wc, ws);
+  }
   // 16-point DFT as 4 x 4: DFT4 over n1 of x[4 n1 + n2], twiddle w16^(n2 k1),
   // DFT4 over n2; output index k1 + 4 k2.
   static __device__ inline void r16(cpx<T>* v) {

@@ -19,6 +19,7 @@
 #include "setup_kernels.h"
 #include "yconv_reg.h"
 #include "rows_reg.h"
+#include "axis_reg.h"
 
 using namespace mmx;
 
@@ -175,6 +176,9 @@ struct Group {
   int nblk_last = 1;  // workgroups per replica of the last field-kernel launch
   int demag_built = 0;
   int fused_faster = 0;  // set by mmx_autotune when the replica-resident path timed faster
+  // few-layer 3-D groups: 1 = separate register y passes around the z pass
+  // instead of the fused y-z kernel (mmx_autotune times both)
+  int yz_split = 1;
 };
 
 // Opt-in per-kernel timing with HIP events recorded on the bound stream
@@ -955,6 +959,72 @@ bool yconv_reg_applies(const Group& G) {
 template <typename T>
 bool zconv_reg_applies(const Group& G) { return G.is3d && G.nz <= 8 && !yz_applies<T>(G); }
 
+// Register y pass of a 3-D FP32 group (Py = 64, 128, 192, 256 or 512, split
+// 8 x 8, 8 x 16, 8 x 24, 16 x 16, 16 x 32); false: not applicable.
+template <typename T>
+bool launch_ypass_reg(const Group& G, const YArgs<T>& y, bool inv, hipStream_t s) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return false;
+  } else {
+    if (!G.is3d || (size_t)G.Py * G.Kx >= (1u << 27)) return false;
+    const bool prune = G.plan_yf.prune != 0;
+    auto go = [&](auto kf, auto kfp, auto ki, auto kip, int NC) {
+      const dim3 grid((G.Kx + NC - 1) / NC, 3 * G.nz, G.R);
+      if (!inv) {
+        if (prune) kfp<<<grid, 64, 0, s>>>(y); else kf<<<grid, 64, 0, s>>>(y);
+      } else {
+        if (prune) kip<<<grid, 64, 0, s>>>(y); else ki<<<grid, 64, 0, s>>>(y);
+      }
+      return true;
+    };
+#define MMX_YP(N1, N2)                                                                          \
+  go(k_ypass_reg<float, N1, N2, false, false>, k_ypass_reg<float, N1, N2, false, true>,         \
+     k_ypass_reg<float, N1, N2, true, false>, k_ypass_reg<float, N1, N2, true, true>, 64 / N1)
+    switch (G.Py) {
+      case 64: return MMX_YP(8, 8);
+      case 128: return MMX_YP(8, 16);
+      case 192: return MMX_YP(8, 24);
+      case 256: return MMX_YP(16, 16);
+      case 512: return MMX_YP(16, 32);
+      default: return false;
+    }
+#undef MMX_YP
+  }
+}
+
+// Register z pass with the tensor product of a 3-D FP32 group (Pz = 32, 64
+// or 128, split 4 x 8, 8 x 8, 8 x 16); false: not applicable.
+template <typename T>
+bool launch_zline_reg(const Group& G, const YArgs<T>& z, hipStream_t s) {
+  if constexpr (!std::is_same<T, float>::value) {
+    return false;
+  } else {
+    // 32-bit offsets within a replica's spectrum
+    if (!G.is3d || (size_t)3 * G.nz * G.Sy * G.Kx * sizeof(cpx<float>) >= (1ull << 31))
+      return false;
+    const bool prune = G.plan_zf.prune != 0;
+    auto go = [&](auto k, auto kp, int NC) {
+      const dim3 grid((G.Kx + NC - 1) / NC, G.Py, G.R);
+      if (prune) kp<<<grid, 64, 0, s>>>(z); else k<<<grid, 64, 0, s>>>(z);
+      return true;
+    };
+    switch (G.Pz) {
+      case 32: return go(k_zline_reg<float, 4, 8, false>, k_zline_reg<float, 4, 8, true>, 16);
+      case 64: return go(k_zline_reg<float, 8, 8, false>, k_zline_reg<float, 8, 8, true>, 8);
+      case 128: return go(k_zline_reg<float, 8, 16, false>, k_zline_reg<float, 8, 16, true>, 8);
+      default: return false;
+    }
+  }
+}
+
+// whether the separate register y passes exist for this group
+template <typename T>
+bool ypass_reg_applies(const Group& G) {
+  return std::is_same<T, float>::value && G.is3d &&
+         (G.Py == 64 || G.Py == 128 || G.Py == 192 || G.Py == 256 || G.Py == 512) &&
+         (size_t)G.Py * G.Kx < (1u << 27);
+}
+
 // m: group-local base pointer of the state used for fields.
 template <typename T>
 mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb, const Epilogue& ep,
@@ -1003,7 +1073,7 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
         k_yconv<T><<<grid, kBlock, (2 * (size_t)3 * G.Wy * G.Py + G.Py) * cpxb<T>(), s>>>(y);
       }
       HIP_TRY(hipGetLastError());
-    } else if (yz_applies<T>(G)) {
+    } else if (yz_applies<T>(G) && !(G.yz_split && ypass_reg_applies<T>(G))) {
       y.W = G.Wz;
       y.tw = G.tw_y.as<cpx<T>>();
       y.twz = G.tw_z.as<cpx<T>>();
@@ -1028,17 +1098,18 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
       const size_t ldy = lds_ycols<T>(true, G.Wy, G.Py);
       {
         ProfScope ps(ctx->prof, "k_ypass_fwd", s);
-        k_ypass<T, false><<<gy, kBlock, ldy, s>>>(y);
+        if (!launch_ypass_reg<T>(G, y, false, s)) k_ypass<T, false><<<gy, kBlock, ldy, s>>>(y);
       }
       HIP_TRY(hipGetLastError());
       YArgs<T> zz = y;
       zz.W = G.Wz;
       zz.tw = G.tw_z.as<cpx<T>>();
+      zz.twz = G.tw_z.as<cpx<T>>();
       zz.pf = G.plan_zf;
       zz.pi = G.plan_zi;
       {
         ProfScope psz(ctx->prof, "k_zconv", s);
-        if (zconv_reg_applies<T>(G)) {
+        if (G.nz <= 8 && G.is3d) {
           dim3 gz((G.Py * G.Kx + kBlock - 1) / kBlock, G.R);
           if (G.nz <= 2)
             k_zconv_reg<T, 2><<<gz, kBlock, 0, s>>>(zz);
@@ -1046,7 +1117,7 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
             k_zconv_reg<T, 4><<<gz, kBlock, 0, s>>>(zz);
           else
             k_zconv_reg<T, 8><<<gz, kBlock, 0, s>>>(zz);
-        } else {
+        } else if (!launch_zline_reg<T>(G, zz, s)) {
           dim3 gz((G.Kx + G.Wz - 1) / G.Wz, G.Py, G.R);
           k_zconv<T><<<gz, kBlock, (2 * (size_t)3 * G.Wz * G.Pz + G.Pz) * cpxb<T>(), s>>>(zz);
         }
@@ -1054,7 +1125,7 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
       HIP_TRY(hipGetLastError());
       {
         ProfScope ps(ctx->prof, "k_ypass_inv", s);
-        k_ypass<T, true><<<gy, kBlock, ldy, s>>>(y);
+        if (!launch_ypass_reg<T>(G, y, true, s)) k_ypass<T, true><<<gy, kBlock, ldy, s>>>(y);
       }
       HIP_TRY(hipGetLastError());
     }
@@ -2061,6 +2132,11 @@ mmx_status autotune_impl(mmx_ctx* ctx) {
       MMX_TRY(time_eval<T>(ctx, G, t));
       if (t < bt) { bt = t; bestW = W; }
     }
+    // few-layer groups: the fused y-z kernel (its column tile tuned) against
+    // the separate register y passes around the z pass
+    const bool both_yz = yz_applies<T>(G) && ypass_reg_applies<T>(G);
+    if (both_yz) G.yz_split = 0;
+    float t_fused = 1e30f;
     if (G.is3d && !zconv_reg_applies<T>(G)) {
       bt = 1e30f;
       for (int W : cand) {
@@ -2070,8 +2146,15 @@ mmx_status autotune_impl(mmx_ctx* ctx) {
         MMX_TRY(time_eval<T>(ctx, G, t));
         if (t < bt) { bt = t; bestWz = W; }
       }
+      t_fused = bt;
     }
     MMX_TRY(apply_tiles<T>(G, bestL, bestW, bestWz));
+    if (both_yz) {
+      G.yz_split = 1;
+      float t_split = 1e30f;
+      MMX_TRY(time_eval<T>(ctx, G, t_split));
+      G.yz_split = t_split <= t_fused ? 1 : 0;
+    }
     // Heun path: one predictor-corrector step staged (two evaluations) against
     // one replica-resident step, on a zeroed state (scratch buffer m7)
     G.fused_faster = 0;

@@ -29,6 +29,8 @@ __device__ inline void dft_reg(cpx<T>* v) {
   if constexpr (R == 8) Dft<T, INV>::r8(v);
   if constexpr (R == 12) Dft<T, INV>::r12(v);
   if constexpr (R == 16) Dft<T, INV>::r16(v);
+  if constexpr (R == 24) Dft<T, INV>::r24(v);
+  if constexpr (R == 32) Dft<T, INV>::r32(v);
 }
 
 template <typename T, int N1, int N2, bool PRUNE>
