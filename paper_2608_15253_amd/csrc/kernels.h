@@ -601,6 +601,12 @@ struct FArgs {
   const float* hext;  // if set (demag term off): Hd = hext_scale * hext + (0, 0, hext_mz m_z)
   T hext_scale, hext_mz;
   int fwd;            // Heun epilogues: also x-transform the new state into S
+  // RK stage epilogue (FM_RKK with fwd): the next stage's state m0 + dt sum_j
+  // cn[j] k_j (k_j from kk, the stage's own slope from registers at index
+  // cstage), normalised if cnext == 2, is written to mnext and x-transformed
+  T cn[6];
+  int cnext, cstage;
+  T* mnext;
   FftPlan plan_f;     // forward x plan (pruned like the one of k_xfwd)
   T* hd_out;          // if set: the exact demag field is also stored here
   int rot;            // Heun epilogues take the rotation (Depondt-Mertens) update
@@ -1019,7 +1025,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
   // Heun epilogues with `fwd`: the new state of the block's rows is packed
   // into the free LDS buffer (real view, line c L + l) and x-transformed
   // after the cell loop, so the next field evaluation needs no k_xfwd pass
-  constexpr bool kFwdMode = (MODE == FM_HEUN1 || MODE == FM_HEUN2);
+  constexpr bool kFwdMode = (MODE == FM_HEUN1 || MODE == FM_HEUN2 || MODE == FM_RKK);
   const bool fwd = kFwdMode && demag && a.fwd;
   T* F = fwd ? reinterpret_cast<T*>(Hbuf == A ? Bf : A) : nullptr;
   if (fwd && !a.plan_f.prune) {
@@ -1112,6 +1118,30 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
     if (MODE == FM_TORQUE || MODE == FM_RKK) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) out_r[c * N + cell] = k[c];
+      if (MODE == FM_RKK && fwd) {
+        // the next stage's combined state, in the order of the combine pass
+        T mv[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          T sv = a.m0[rb + c * N + cell];
+          for (int j = 0; j < 6; ++j) {
+            if (a.cn[j] == T(0)) continue;
+            const T kj = (j == a.cstage) ? k[c] : a.kk[j][rb + c * N + cell];
+            sv += dt * a.cn[j] * kj;
+          }
+          mv[c] = sv;
+        }
+        if (a.cnext == 2) {
+          const T inv = T(1) / sqrt(mv[0] * mv[0] + mv[1] * mv[1] + mv[2] * mv[2]);
+          mv[0] *= inv; mv[1] *= inv; mv[2] *= inv;
+        }
+        const T ws = a.msr ? a.msr[cell] : T(1);  // transform input M = Ms_i m
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          a.mnext[rb + c * N + cell] = mv[c];
+          F[(c * L + l) * 2 * hx + x] = a.msr ? ws * mv[c] : mv[c];
+        }
+      }
     } else if (MODE == FM_HEUN1) {
       T k1v[3], mn[3];
       heun_predict(gpm, alpha, a.rot != 0, mc, H, k, tau, dt, k1v, mn);

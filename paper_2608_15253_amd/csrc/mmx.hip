@@ -156,7 +156,7 @@ struct Group {
   double B[3] = {0, 0, 0};
   size_t off = 0;  // element offset of this group in caller arrays
   // device buffers (regions of the context's arena)
-  Buf tw_x, wpost, tw_y, tw_z, Nt, S, ms, m7, k[7], Trep, seeds, partial, E;
+  Buf tw_x, wpost, tw_y, tw_z, Nt, S, ms, ms2, m7, k[7], Trep, seeds, partial, E;
   Buf tgen, tstart, tflag, S_init;  // retire/refill trials
   Buf Jrep;  // spin-transfer current density per replica (A/m^2)
   mmx_material_ext ext{};  // bulk DMI, cubic anisotropy, RKKY
@@ -523,6 +523,7 @@ void arena_walk(mmx_ctx* ctx, F&& take) {
     take(G.Nt, (size_t)kTensorStride * G.Tz * G.Ty * G.Kx * w);
     take(G.S, (size_t)G.R * 3 * G.nz * G.Sy * G.Kx * c);
     take(G.ms, st);
+    take(G.ms2, st);
     take(G.m7, st);
     for (int j = 0; j < 7; ++j) take(G.k[j], st);
     take(G.Trep, (size_t)G.R * sizeof(double));
@@ -672,6 +673,11 @@ struct Epilogue {
   double e[7] = {0, 0, 0, 0, 0, 0, 0};
   int use_k_err = 0;
   int fwd = 0;  // Heun modes: also write the half spectrum of the new state
+  // RK stages with fwd: the next stage's combine (coefficients per slope,
+  // this stage's slope index, 2 = normalise) written to mnext, from base m0
+  double cn[6] = {0, 0, 0, 0, 0, 0};
+  int cnext = 0, cstage = 0;
+  void* mnext = nullptr;
 };
 
 // orthonormal cubic axes from c1 and c2 (c2 orthogonalised against c1)
@@ -1146,6 +1152,10 @@ mmx_status eval_group(mmx_ctx* ctx, Group& G, const T* mbase, const Combine& cb,
   for (int j = 0; j < 7; ++j) a.e[j] = ep.e[j];
   for (int j = 0; j < 6; ++j) a.kk[j] = G.k[j].as<T>();
   a.fwd = ep.fwd;
+  for (int j = 0; j < 6; ++j) a.cn[j] = (T)ep.cn[j];
+  a.cnext = ep.cnext;
+  a.cstage = ep.cstage;
+  a.mnext = reinterpret_cast<T*>(ep.mnext);
   a.plan_f = G.plan_x;
   a.st = ctx->st.as<RkState>();
   a.partial = G.partial.as<double>();
@@ -1225,6 +1235,12 @@ mmx_status rk_stages(mmx_ctx* ctx, Group& G, T* mg, const double e[7], const Sta
   RkState* st = ctx->st.as<RkState>();
   const int* done = &st->done;
   const double* dtdev = &st->dt;
+  // Without learned stages every stage's epilogue also forms the next
+  // stage's state and its x transform (the states alternate between two
+  // buffers, since a stage still reads its own state's neighbours), so only
+  // the second stage needs the separate combine pass.
+  const bool chain = hook == nullptr && (ctx->terms & MMX_DEMAG);
+  void* state[7] = {nullptr, G.ms.p, G.ms2.p, G.ms.p, G.ms2.p, G.ms.p, G.m7.p};
   for (int sidx = 1; sidx < 7; ++sidx) {
     Combine cb;
     for (int j = 0; j < sidx; ++j) {
@@ -1236,9 +1252,17 @@ mmx_status rk_stages(mmx_ctx* ctx, Group& G, T* mg, const double e[7], const Sta
     }
     Epilogue ep;
     if (sidx < 6) {
-      cb.mout = G.ms.p;
+      cb.mout = chain ? state[sidx] : G.ms.p;
       ep.mode = FM_RKK;
       ep.out = G.k[sidx].p;
+      if (chain) {
+        ep.fwd = 1;
+        ep.m0 = mg;
+        for (int j = 0; j <= sidx; ++j) ep.cn[j] = DP_A[sidx + 1][j];
+        ep.cstage = sidx;
+        ep.cnext = (sidx + 1 == 6) ? 2 : 1;
+        ep.mnext = state[sidx + 1];
+      }
     } else {
       cb.mout = G.m7.p;
       cb.normalise = 1;
@@ -1257,6 +1281,11 @@ mmx_status rk_stages(mmx_ctx* ctx, Group& G, T* mg, const double e[7], const Sta
                                          0, 1.0, dtdev, 0.0, done, ctx->terms & ~MMX_DEMAG);
       ctx->hext = nullptr;
       MMX_TRY(r);
+    } else if (chain && sidx > 1) {
+      // state and half spectrum written by the previous stage's epilogue
+      ctx->hd_out = nullptr;
+      MMX_TRY(eval_group<T>(ctx, G, reinterpret_cast<const T*>(state[sidx]), Combine{}, ep, 0, 1.0,
+                            dtdev, 0.0, done, 0xFFFFFFFFu, true));
     } else {
       ctx->hd_out = (hook && sidx == 6) ? hook->hd : nullptr;
       const mmx_status r = eval_group<T>(ctx, G, mg, cb, ep, 0, 1.0, dtdev, 0.0, done);

@@ -168,3 +168,32 @@ def test_training_pipeline_reduces_the_loss_and_labels_match_oracle():
         net.close()
     assert np.isfinite(l1) and l1 < 0.8 * l0
     assert gate.shape == (16,)
+
+
+def test_gain_of_a_trained_network_over_plain_rk45():
+    """What a trained network gains: data from the method, a briefly trained
+    network, then held-out relaxations with plain FP32 RK45 and with learned
+    stages (gate 1e-3), both against an FP64 RK45 reference.  The gated run
+    keeps the plain run's accuracy (every kept learned step passed the exact
+    gate, failures fall back to exact steps); the speed ratio is measured and
+    reported, not assumed (at these sizes the exact pruned FFT convolution is
+    cheaper than one network forward, so no gain is expected)."""
+    from paper_2608_15253_amd import surrogate as sg
+    n = (32, 24, 1)
+    m_all, t_all = sg.generate(n, snapshots=128, replicas=16, every=20, log=lambda s: None)
+    net = sg.Net(24, 32, C=8, M1=4, M2=3, L=2, Cp=16, batch=16, use_mfma=True, seed=3)
+    try:
+        sg.train(net, m_all, t_all, 112, epochs=30, lr0=3e-3, log=lambda s: None)
+        rep = sg.speedup(net, n=n, R=8, t_end=2e-11, tol=1e-5, gates=(1e-3,),
+                         log=lambda s: None)
+    finally:
+        net.close()
+    plain, run = rep["plain"], rep["learned"][0]
+    print(f"plain {plain['seconds']:.3f} s |dm| {plain['dm']:.2e}; learned {run['seconds']:.3f} s "
+          f"(x{run['speedup']:.3f}) |dm| {run['dm']:.2e}, kept {run['surrogate_steps']}/"
+          f"{run['accepted']}, gate failures {run['gate_failures']}/{run['gate_checks']}")
+    assert np.isfinite(run["dm"]) and run["speedup"] > 0
+    assert run["dm"] <= 10 * plain["dm"] + 1e-5
+    # the network was tried: its attempts were gated or rejected by the
+    # controller (then repeated with the exact field)
+    assert run["gate_checks"] + run["surrogate_rejected"] >= 1
