@@ -640,6 +640,67 @@ def bench_histogram(args):
                               "max_abs_dm_gpu_f64_vs_oracle": float(np.abs(gpu - ref).max())}}
 
 
+def _fno_flops(H, W, C, M1, M2, L, Cp, B):
+    """FLOPs of one network forward of B films: the 1x1 maps (lift 5 -> C,
+    L maps C -> C, projection C -> Cp -> 3) as 2 MACs per weight per pixel,
+    the truncated transforms (x: M1 complex modes from W real points per row;
+    y: 2 M2 modes from H rows per kx) and the per-mode complex C x C mixing."""
+    P = H * W
+    conv = 2 * P * (5 * C + L * C * C + C * Cp + Cp * 3)
+    J = 2 * M2
+    dft = L * C * (2 * 2 * H * W * M1 + 8 * M1 * J * H) * 2   # forward and inverse
+    mix = L * M1 * J * C * C * 8
+    return B * (conv + dft + mix), B * conv
+
+
+def bench_fno(args):
+    """The learned operator's network on 128x128 films (width 32, 12 x 12
+    modes, 4 layers, projection 128, BF16 matrix-core 1x1 maps): time per
+    forward and per forward + backward of a batch, random weights, FLOP rate
+    of the whole forward and of its matrix-core part."""
+    import torch
+    import paper_2608_15253_amd as mmx
+    from workloads import random_unit
+    H = W = 128
+    C, M1, M2, L, Cp = 32, 12, 12, 4, 128
+    B = args.fno_batch
+    f = mmx.mmx_fno_create(H, W, C, M1, M2, L, Cp, B, True)
+    try:
+        mmx.mmx_fno_set_stream(f, torch.cuda.current_stream().cuda_stream)
+        n = mmx.mmx_fno_param_count(f)
+        prm = torch.empty(n, dtype=torch.float32, device="cuda:0")
+        mmx.mmx_fno_init(f, prm, 1)
+        m = torch.tensor(random_unit((W, H, 1), seed=3, replicas=B)[:, :, 0], dtype=torch.float32,
+                         device="cuda:0").contiguous()
+        h = torch.empty((B, 3, H, W), dtype=torch.float32, device="cuda:0")
+        g = torch.zeros(n, dtype=torch.float32, device="cuda:0")
+        for _ in range(3):
+            mmx.mmx_fno_forward(f, prm, m, h, B)
+        torch.cuda.synchronize()
+        reps = args.fno_reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mmx.mmx_fno_forward(f, prm, m, h, B)
+        torch.cuda.synchronize()
+        t_fwd = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            mmx.mmx_fno_forward(f, prm, m, h, B)
+            mmx.mmx_fno_backward(f, prm, h, h, g, False)
+        torch.cuda.synchronize()
+        t_fb = (time.perf_counter() - t0) / reps
+    finally:
+        mmx.mmx_fno_destroy(f)
+    flops, conv = _fno_flops(H, W, C, M1, M2, L, Cp, B)
+    return {"metric": "learned operator forward, films per second (128x128, BF16 1x1 maps)",
+            "value": B / t_fwd, "unit": "films/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "bf16", "data": "synthetic",
+            "config": {"workload": "fno_128x128_w32_m12_l4", "batch": B, "params": n},
+            "ms_forward": t_fwd * 1e3, "ms_forward_backward": t_fb * 1e3,
+            "forward_gflop": flops / 1e9, "forward_tflops": flops / t_fwd / 1e12,
+            "conv1x1_gflop": conv / 1e9}
+
+
 def setup(R, prec, seeds, n=(64, 64, 1)):
     import torch
     import paper_2608_15253_amd as mmx
@@ -733,13 +794,15 @@ def main():
     ap.add_argument("--traffic-cmd", default="", help="command line recorded in the summary")
     ap.add_argument("--workload", default="switching",
                     choices=["switching", "uneven", "closure", "skyrmion512", "depondt", "stt",
-                             "throughput", "fields_ext", "histogram"],
+                             "throughput", "fields_ext", "histogram", "fno"],
                     help="switching: the benchmark line; the others measure the other "
                          "workload configurations (one JSON line each)")
     ap.add_argument("--hist-steps", type=int, default=200000,
                     help="histogram: Heun steps (2e5 = 2 ns)")
     ap.add_argument("--f64-replicas", type=int, default=256,
                     help="histogram: replicas rerun in FP64")
+    ap.add_argument("--fno-batch", type=int, default=8, help="fno: films per batch")
+    ap.add_argument("--fno-reps", type=int, default=20, help="fno: timed repetitions")
     ap.add_argument("--hist-bz", type=float, default=-0.15,
                     help="histogram: applied field along z (T)")
     ap.add_argument("--oracle-steps", type=int, default=1000,
@@ -762,7 +825,8 @@ def main():
                           "depondt": bench_depondt, "stt": bench_stt,
                           "throughput": bench_throughput,
                           "fields_ext": bench_fields_ext,
-                          "histogram": bench_histogram}[args.workload](args)))
+                          "histogram": bench_histogram,
+                          "fno": bench_fno}[args.workload](args)))
         return
     # the CPU baseline runs first: its worker processes are forked before
     # this process initialises the GPU

@@ -6,14 +6,17 @@
 // matrix cores: v_mfma_f32_16x16x32_bf16 with BF16 operands staged in LDS and
 // FP32 accumulation (a VALU FP32 variant of the same kernel serves parity
 // checks).  The truncated Fourier transforms (M1 x-modes, 2 M2 y-modes), the
-// per-mode complex channel mixing and all reductions are FP32 on the VALU.
+// per-mode complex channel mixing and the weight gradients run as FP32
+// matrix-core products (fno_mfma.h); the VALU kernels below serve shapes
+// outside those kernels' limits, the loss and Adam.
 #pragma once
 #include "common.h"
 
 namespace mmx {
 
 constexpr int kFnoBlock = 256;
-constexpr int kFnoPixTile = 64;  // pixels per GEMM workgroup (16 per wave)
+constexpr int kFnoPixTile = 64;   // pixels per VALU 1x1-map workgroup
+constexpr int kConvPixMfma = 64;  // pixels per matrix-core 1x1-map workgroup (a multiple of 64)
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -37,55 +40,100 @@ struct ConvArgs {
 };
 
 // Y[b][m][p] = sum_k W[m][k] X[b][k][p] + bias[m], then the epilogue.
-// Workgroup: sample blockIdx.y, pixels [64 blockIdx.x, +64); wave w owns 16
-// pixels and every 16-row tile of the output channels.
+// Workgroup: sample blockIdx.y, pixels [PT blockIdx.x, +PT); on the matrix
+// cores wave w owns PT / 64 tiles of 16 pixels and every 16-row tile of the
+// output channels (64-pixel workgroups measured faster than 128).
 template <bool MFMA>
 __global__ void __launch_bounds__(kFnoBlock) k_conv1x1(ConvArgs a) {
   extern __shared__ unsigned char smem_raw[];
-  const int b = blockIdx.y, p0 = blockIdx.x * kFnoPixTile;
+  constexpr int PT = MFMA ? kConvPixMfma : kFnoPixTile;
+  const int b = blockIdx.y, p0 = blockIdx.x * PT;
   const int Mp = (a.M + 15) & ~15, Kp = (a.K + 31) & ~31;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const float* Xb = a.X + (size_t)b * a.K * a.P;
   if (MFMA) {
-    __bf16* Ws = reinterpret_cast<__bf16*>(smem_raw);   // [Mp][Kp]
-    __bf16* Xs = Ws + (size_t)Mp * Kp;                  // [Kp][64]
-    for (int i = threadIdx.x; i < Mp * Kp; i += blockDim.x) {
-      const int m = i / Kp, k = i - m * Kp;
-      float v = 0.f;
-      if (m < a.M && k < a.K) v = a.trans ? a.Wt[(size_t)k * a.M + m] : a.Wt[(size_t)m * a.K + k];
-      Ws[i] = (__bf16)v;
-    }
-    for (int i = threadIdx.x; i < Kp * kFnoPixTile; i += blockDim.x) {
-      const int k = i / kFnoPixTile, px = i - k * kFnoPixTile;
-      float v = 0.f;
-      if (k < a.K && p0 + px < a.P) v = Xb[(size_t)k * a.P + p0 + px];
-      Xs[i] = (__bf16)v;
-    }
-    __syncthreads();
-    const int col = lane & 15, grp = lane >> 4;
-    for (int mt = 0; mt < Mp / 16; ++mt) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-      for (int kt = 0; kt < Kp / 32; ++kt) {
-        bf16x8 av, bv;
+    // both operands k-contiguous in LDS, rows padded by 8 elements, so that a
+    // lane's 8 reduction values are one 16-byte read
+    const int KS = Kp + 8;
+    __bf16* Ws = reinterpret_cast<__bf16*>(smem_raw);   // [Mp][KS]
+    __bf16* Xs = Ws + (size_t)Mp * KS;                  // [PT pixels][KS]
+    // weights, then pixels: four global loads in flight per thread before the
+    // converted values go to LDS
+    const int nw = Mp * Kp;
+    for (int i0 = threadIdx.x; i0 < nw; i0 += 4 * kFnoBlock) {
+      float v[4];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          const int k = kt * 32 + 8 * grp + j;
-          av[j] = Ws[(size_t)(mt * 16 + col) * Kp + k];
-          bv[j] = Xs[(size_t)k * kFnoPixTile + wave * 16 + col];
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kFnoBlock, m = i / Kp, k = i - m * Kp;
+        v[u] = 0.f;
+        if (i < nw && m < a.M && k < a.K)
+          v[u] = a.trans ? a.Wt[(size_t)k * a.M + m] : a.Wt[(size_t)m * a.K + k];
       }
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int m = mt * 16 + 4 * grp + j;
-        const int p = p0 + wave * 16 + col;
-        if (m < a.M && p < a.P) {
-          const size_t o = ((size_t)b * a.M + m) * a.P + p;
-          float y = acc[j] + (a.bias ? a.bias[m] : 0.f);
-          if (a.epi == CE_ACCUM) y += a.Y[o];
-          if (a.epi == CE_GELU_GRAD) y *= gelu_grad_f(a.S[o]);
-          a.Y[o] = y;
-          if (a.epi == CE_GELU) a.A[o] = gelu_f(y);
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * kFnoBlock, m = i / Kp, k = i - m * Kp;
+        if (i < nw) Ws[(size_t)m * KS + k] = (__bf16)v[u];
+      }
+    }
+    if (a.P % 4 == 0) {
+      // 16-byte loads of four pixels of one channel
+      constexpr int QX = PT / 4;  // 16-byte pieces per channel row
+      const int nx = Kp * QX;
+      for (int i0 = threadIdx.x; i0 < nx; i0 += 4 * kFnoBlock) {
+        f32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u * kFnoBlock, k = i / QX, px = p0 + 4 * (i % QX);
+          v[u] = f32x4{0.f, 0.f, 0.f, 0.f};
+          if (i < nx && k < a.K && px < a.P)
+            v[u] = *reinterpret_cast<const f32x4*>(Xb + (size_t)k * a.P + px);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int i = i0 + u * kFnoBlock, k = i / QX, q = 4 * (i % QX);
+          if (i < nx) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Xs[(size_t)(q + e) * KS + k] = (__bf16)v[u][e];
+          }
+        }
+      }
+    } else {
+      for (int i = threadIdx.x; i < Kp * PT; i += blockDim.x) {
+        const int k = i / PT, px = i - k * PT;
+        float v = 0.f;
+        if (k < a.K && p0 + px < a.P) v = Xb[(size_t)k * a.P + p0 + px];
+        Xs[(size_t)px * KS + k] = (__bf16)v;
+      }
+    }
+    __syncthreads();
+    const int col = lane & 15, grp = lane >> 4, nkt = Kp / 32;
+    for (int pt = 0; pt < PT / 64; ++pt) {
+      const int px = wave * (PT / 4) + pt * 16 + col;  // this lane's pixel column
+      // B operands of every reduction step (Kp <= 128)
+      bf16x8 bv[4];
+#pragma unroll
+      for (int kt = 0; kt < 4; ++kt)
+        if (kt < nkt) bv[kt] = *reinterpret_cast<const bf16x8*>(Xs + (size_t)px * KS + kt * 32 + 8 * grp);
+      for (int mt = 0; mt < Mp / 16; ++mt) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        const __bf16* wrow = Ws + (size_t)(mt * 16 + col) * KS + 8 * grp;
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt)
+          if (kt < nkt)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                *reinterpret_cast<const bf16x8*>(wrow + kt * 32), bv[kt], acc, 0, 0, 0);
+        const int p = p0 + px;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int m = mt * 16 + 4 * grp + j;
+          if (m < a.M && p < a.P) {
+            const size_t o = ((size_t)b * a.M + m) * a.P + p;
+            float y = acc[j] + (a.bias ? a.bias[m] : 0.f);
+            if (a.epi == CE_ACCUM) y += a.Y[o];
+            if (a.epi == CE_GELU_GRAD) y *= gelu_grad_f(a.S[o]);
+            a.Y[o] = y;
+            if (a.epi == CE_GELU) a.A[o] = gelu_f(y);
+          }
         }
       }
     }
@@ -114,64 +162,6 @@ __global__ void __launch_bounds__(kFnoBlock) k_conv1x1(ConvArgs a) {
       if (a.epi == CE_GELU) a.A[o] = gelu_f(y);
     }
   }
-}
-
-// Partial weight gradients of a channel map: for pixel chunk blockIdx.x,
-// part[chunk][m][k] = sum dY[b][m][p] X[b][k][p], part[chunk][M][... ] bias
-// row: part[chunk][M*K + m] = sum dY[b][m][p].  Chunks span 1024 pixels of the
-// flattened (b, p) range.
-constexpr int kDwChunk = 1024;
-constexpr int kDwTile = 32;
-
-__global__ void __launch_bounds__(kFnoBlock) k_dw_partial(const float* dY, const float* X, int M,
-                                                          int K, int P, int B, float* part) {
-  extern __shared__ unsigned char smem_raw[];
-  float* Ys = reinterpret_cast<float*>(smem_raw);   // [M][tile]
-  float* Xs = Ys + (size_t)M * kDwTile;              // [K][tile]
-  const long total = (long)B * P;
-  const long q0 = (long)blockIdx.x * kDwChunk;
-  const int npair = M * K + M;
-  float acc[24];
-#pragma unroll
-  for (int i = 0; i < 24; ++i) acc[i] = 0.f;
-  for (long t0 = q0; t0 < q0 + kDwChunk && t0 < total; t0 += kDwTile) {
-    __syncthreads();
-    for (int i = threadIdx.x; i < (M + K) * kDwTile; i += blockDim.x) {
-      const int row = i / kDwTile, px = i - row * kDwTile;
-      const long q = t0 + px;
-      float v = 0.f;
-      if (q < total) {
-        const long b = q / P, p = q - b * P;
-        v = (row < M) ? dY[((size_t)b * M + row) * P + p] : X[((size_t)b * K + row - M) * P + p];
-      }
-      Ys[i] = v;  // rows >= M land in Xs (contiguous)
-    }
-    __syncthreads();
-    int slot = 0;
-    for (int pr = threadIdx.x; pr < npair; pr += blockDim.x, ++slot) {
-      float s = 0.f;
-      if (pr < M * K) {
-        const int m = pr / K, k = pr - m * K;
-        for (int px = 0; px < kDwTile; ++px) s += Ys[m * kDwTile + px] * Xs[k * kDwTile + px];
-      } else {
-        const int m = pr - M * K;
-        for (int px = 0; px < kDwTile; ++px) s += Ys[m * kDwTile + px];
-      }
-      acc[slot] += s;
-    }
-  }
-  int slot = 0;
-  for (int pr = threadIdx.x; pr < npair; pr += blockDim.x, ++slot)
-    part[(size_t)blockIdx.x * npair + pr] = acc[slot];
-}
-
-// out[i] (+)= sum over chunks of part[chunk][i], fixed order
-__global__ void k_sum_chunks(const float* part, int nchunk, int n, float* out, int accumulate) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float s = 0.f;
-  for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + i];
-  out[i] = accumulate ? out[i] + s : s;
 }
 
 // Truncated forward transform of every (b, channel) plane:
@@ -266,55 +256,6 @@ __global__ void __launch_bounds__(kFnoBlock) k_spec_inv(SpecArgs a) {
   }
 }
 
-// Per-mode complex channel mixing.  Forward: out[b][o][mode] =
-// sum_i R[mode][i][o] in[b][i][mode]; adjoint: out[b][i][mode] =
-// sum_o conj(R[mode][i][o]) in[b][o][mode].  Modes are (kx, j), J fastest.
-__global__ void __launch_bounds__(kFnoBlock) k_mix(const cpx<float>* in, const cpx<float>* R,
-                                                   cpx<float>* out, int B, int C, int nmode,
-                                                   int adjoint) {
-  extern __shared__ unsigned char smem_raw[];
-  cpx<float>* Rs = reinterpret_cast<cpx<float>*>(smem_raw);  // [C][C]
-  cpx<float>* Vs = Rs + C * C;                               // [B][C]
-  const int mode = blockIdx.x;
-  for (int i = threadIdx.x; i < C * C; i += blockDim.x) Rs[i] = R[(size_t)mode * C * C + i];
-  for (int i = threadIdx.x; i < B * C; i += blockDim.x) Vs[i] = in[(size_t)i * nmode + mode];
-  __syncthreads();
-  for (int i = threadIdx.x; i < B * C; i += blockDim.x) {
-    const int b = i / C, q = i - b * C;
-    float re = 0.f, im = 0.f;
-    for (int s = 0; s < C; ++s) {
-      const cpx<float> v = Vs[b * C + s];
-      if (!adjoint) {
-        const cpx<float> r = Rs[s * C + q];           // R[i = s][o = q]
-        re += r.re * v.re - r.im * v.im;
-        im += r.re * v.im + r.im * v.re;
-      } else {
-        const cpx<float> r = Rs[q * C + s];           // conj(R[i = q][o = s])
-        re += r.re * v.re + r.im * v.im;
-        im += r.re * v.im - r.im * v.re;
-      }
-    }
-    out[(size_t)i * nmode + mode] = {re, im};
-  }
-}
-
-// dR[mode][i][o] = sum_b conj(Vh[b][i][mode]) dUh[b][o][mode]
-__global__ void __launch_bounds__(kFnoBlock) k_mix_grad(const cpx<float>* Vh, const cpx<float>* dUh,
-                                                        cpx<float>* dR, int B, int C, int nmode) {
-  const int mode = blockIdx.x;
-  for (int i = threadIdx.x; i < C * C; i += blockDim.x) {
-    const int ci = i / C, co = i - ci * C;
-    float re = 0.f, im = 0.f;
-    for (int b = 0; b < B; ++b) {
-      const cpx<float> v = Vh[((size_t)b * C + ci) * nmode + mode];
-      const cpx<float> d = dUh[((size_t)b * C + co) * nmode + mode];
-      re += v.re * d.re + v.im * d.im;
-      im += v.re * d.im - v.im * d.re;
-    }
-    dR[(size_t)mode * C * C + i] = {re, im};
-  }
-}
-
 // Input features [m_x, m_y, m_z, x/W - 1/2, y/H - 1/2] per pixel.
 __global__ void k_fno_features(const float* m, float* X0, int B, int H, int W) {
   const long P = (long)H * W;
@@ -361,21 +302,33 @@ __global__ void __launch_bounds__(kFnoBlock) k_fno_loss_partial(const float* h, 
   }
 }
 
-__global__ void k_fno_loss_final(const double* part, int nblk, int B, double* per_sample,
-                                 double* loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double L = 0;
-  for (int b = 0; b < B; ++b) {
-    double n = 0, d = 0;
-    for (int k = 0; k < nblk; ++k) {
-      n += part[((size_t)b * nblk + k) * 2];
-      d += part[((size_t)b * nblk + k) * 2 + 1];
-    }
+// Per-sample sums of the partials (one wave per sample, fixed-order tree),
+// then the batch-mean loss from one wave.
+__global__ void __launch_bounds__(64) k_fno_loss_sample(const double* part, int nblk,
+                                                        double* per_sample) {
+  const int b = blockIdx.x, k = threadIdx.x;
+  double n = 0, d = 0;
+  for (int i = k; i < nblk; i += 64) {
+    n += part[((size_t)b * nblk + i) * 2];
+    d += part[((size_t)b * nblk + i) * 2 + 1];
+  }
+  for (int s = 32; s > 0; s >>= 1) {
+    n += __shfl_xor(n, s);
+    d += __shfl_xor(d, s);
+  }
+  if (k == 0) {
     per_sample[2 * b] = n;
     per_sample[2 * b + 1] = d;
-    L += n / d;
   }
-  *loss = L / B;
+}
+
+__global__ void __launch_bounds__(64) k_fno_loss_mean(const double* per_sample, int B,
+                                                      double* loss) {
+  const int k = threadIdx.x;
+  double L = 0;
+  for (int b = k; b < B; b += 64) L += per_sample[2 * b] / per_sample[2 * b + 1];
+  for (int s = 32; s > 0; s >>= 1) L += __shfl_xor(L, s);
+  if (k == 0) *loss = L / B;
 }
 
 __global__ void k_fno_dh(const float* h, const float* t, const double* per_sample, long n_per,

@@ -2,6 +2,7 @@
 // parameter layout (see include/mmx.h).  Included by mmx.hip.
 #pragma once
 #include "fno.h"
+#include "fno_mfma.h"
 
 struct mmx_fno {
   int H = 0, W = 0, C = 0, M1 = 0, M2 = 0, J = 0, L = 0, Cp = 0, Bmax = 0, mfma = 1;
@@ -24,12 +25,13 @@ using namespace mmx;
 mmx_status fno_conv(mmx_fno* f, const float* X, const float* Wt, const float* bias, float* Y,
                     float* A, const float* S, int M, int K, int trans, int epi, int B) {
   ConvArgs a{X, Wt, bias, Y, A, S, M, K, (int)f->P, trans, epi};
-  dim3 grid((unsigned)((f->P + kFnoPixTile - 1) / kFnoPixTile), B);
   if (f->mfma) {
-    const int Mp = (M + 15) & ~15, Kp = (K + 31) & ~31;
-    const size_t lds = ((size_t)Mp * Kp + (size_t)Kp * kFnoPixTile) * sizeof(__bf16);
+    const dim3 grid((unsigned)((f->P + kConvPixMfma - 1) / kConvPixMfma), B);
+    const int Mp = (M + 15) & ~15, KS = ((K + 31) & ~31) + 8;
+    const size_t lds = ((size_t)Mp * KS + (size_t)kConvPixMfma * KS) * sizeof(__bf16);
     k_conv1x1<true><<<grid, kFnoBlock, lds, f->stream>>>(a);
   } else {
+    const dim3 grid((unsigned)((f->P + kFnoPixTile - 1) / kFnoPixTile), B);
     const size_t lds = ((size_t)M * K + (size_t)K * kFnoPixTile) * sizeof(float);
     k_conv1x1<false><<<grid, kFnoBlock, lds, f->stream>>>(a);
   }
@@ -37,28 +39,71 @@ mmx_status fno_conv(mmx_fno* f, const float* X, const float* Wt, const float* bi
   return MMX_OK;
 }
 
-// grads[0 .. M K + M) (+)= weight and bias gradients of a channel map
+template <int MT, int KT>
+void launch_dw(dim3 grid, hipStream_t st, bool vec, const float* dY, const float* X, int M, int K,
+               int P, int chunk, int kgroups, float* part) {
+  if (vec)
+    k_dw_mfma<MT, KT, true><<<grid, 64, 0, st>>>(dY, X, M, K, P, chunk, kgroups, part);
+  else
+    k_dw_mfma<MT, KT, false><<<grid, 64, 0, st>>>(dY, X, M, K, P, chunk, kgroups, part);
+}
+
+// grads[0 .. M K + M) = weight and bias gradients of a channel map: partial
+// sums per pixel chunk on the matrix cores, then a fixed-order sum of the
+// chunks
 mmx_status fno_dw(mmx_fno* f, const float* dY, const float* X, int M, int K, int B, float* out) {
   const int npair = M * K + M;
-  if (npair > 24 * kFnoBlock) return fail(MMX_EUNSUP, "channel map too large for the gradient kernel");
-  const long total = (long)B * f->P;
-  const int nchunk = (int)((total + kDwChunk - 1) / kDwChunk);
-  const size_t need = (size_t)nchunk * npair * sizeof(float);
+  const long P = f->P;
+  long chunk = ((long)B * P + kDwRows - 1) / kDwRows;
+  chunk = std::max(64L, (chunk + 15) / 16 * 16);
+  const int nch = (int)((P + chunk - 1) / chunk);
+  const int rows = nch * B;
+  const size_t need = (size_t)rows * npair * sizeof(float);
   if (f->part.bytes < need) HIP_TRY(f->part.alloc(need));
-  k_dw_partial<<<nchunk, kFnoBlock, (size_t)(M + K) * kDwTile * sizeof(float), f->stream>>>(
-      dY, X, M, K, (int)f->P, B, f->part.as<float>());
+  // output tiles in groups of at most 4 x 4
+  auto group = [](int tiles) { return tiles >= 3 ? 4 : tiles; };
+  const int mt = (M + 15) / 16, kt = (K + 15) / 16, MT = group(mt), KT = group(kt);
+  const int gm = (mt + MT - 1) / MT, gk = (kt + KT - 1) / KT;
+  const dim3 grid((unsigned)nch, (unsigned)B, (unsigned)(gm * gk));
+  const bool vec = P % 4 == 0;
+  float* part = f->part.as<float>();
+  const int c = (int)chunk;
+  switch (MT * 8 + KT) {
+    case 1 * 8 + 1: launch_dw<1, 1>(grid, f->stream, vec, dY, X, M, K, (int)P, c, gk, part); break;
+    case 1 * 8 + 2: launch_dw<1, 2>(grid, f->stream, vec, dY, X, M, K, (int)P, c, gk, part); break;
+    case 1 * 8 + 4: launch_dw<1, 4>(grid, f->stream, vec, dY, X, M, K, (int)P, c, gk, part); break;
+    case 2 * 8 + 1: launch_dw<2, 1>(grid, f->stream, vec, dY, X, M, K, (int)P, c, gk, part); break;
+    case 2 * 8 + 2: launch_dw<2, 2>(grid, f->stream, vec, dY, X, M, K, (int)P, c, gk, part); break;
+    case 2 * 8 + 4: launch_dw<2, 4>(grid, f->stream, vec, dY, X, M, K, (int)P, c, gk, part); break;
+    case 4 * 8 + 1: launch_dw<4, 1>(grid, f->stream, vec, dY, X, M, K, (int)P, c, gk, part); break;
+    case 4 * 8 + 2: launch_dw<4, 2>(grid, f->stream, vec, dY, X, M, K, (int)P, c, gk, part); break;
+    default: launch_dw<4, 4>(grid, f->stream, vec, dY, X, M, K, (int)P, c, gk, part); break;
+  }
   HIP_TRY(hipGetLastError());
-  k_sum_chunks<<<(npair + 255) / 256, 256, 0, f->stream>>>(f->part.as<float>(), nchunk, npair, out, 0);
+  k_sum_rows<<<(npair + 63) / 64, 1024, 0, f->stream>>>(part, rows, npair, out);
   HIP_TRY(hipGetLastError());
   return MMX_OK;
+}
+
+// the matrix-core transforms take up to 16 x-modes and 32 y-modes
+bool spec_mfma_fits(const mmx_fno* f, size_t lds_bytes) {
+  return f->M1 <= 16 && f->J <= 32 && lds_bytes <= 65536;
 }
 
 mmx_status fno_spec_fwd(mmx_fno* f, const float* in, float* out, const float* coef, int planes) {
   SpecArgs a{in, out, f->Fx.as<cpx<float>>(), f->Fy.as<cpx<float>>(), coef, nullptr, nullptr,
              f->H, f->W, f->M1, f->J};
-  const size_t lds = ((size_t)f->M1 * f->W + (size_t)f->J * f->H + (size_t)f->H * f->M1) *
-                     sizeof(cpx<float>);
-  k_spec_fwd<<<planes, kFnoBlock, lds, f->stream>>>(a);
+  const size_t mlds = (size_t)spec_fwd_lds_floats(f->H, f->W) * sizeof(float);
+  if (spec_mfma_fits(f, mlds)) {
+    if (f->W % 4 == 0)
+      k_spec_fwd_mfma<true><<<planes, kFnoBlock, mlds, f->stream>>>(a);
+    else
+      k_spec_fwd_mfma<false><<<planes, kFnoBlock, mlds, f->stream>>>(a);
+  } else {
+    const size_t lds = ((size_t)f->M1 * f->W + (size_t)f->J * f->H + (size_t)f->H * f->M1) *
+                       sizeof(cpx<float>);
+    k_spec_fwd<<<planes, kFnoBlock, lds, f->stream>>>(a);
+  }
   HIP_TRY(hipGetLastError());
   return MMX_OK;
 }
@@ -67,20 +112,26 @@ mmx_status fno_spec_inv(mmx_fno* f, const float* in, float* out, const float* co
                         const float* add, float* act, int planes) {
   SpecArgs a{in, out, f->Fx.as<cpx<float>>(), f->Fy.as<cpx<float>>(), coef, add, act,
              f->H, f->W, f->M1, f->J};
-  const size_t lds = ((size_t)f->M1 * f->W + (size_t)f->J * f->H + (size_t)f->M1 * f->H +
-                      (size_t)f->M1 * f->J) * sizeof(cpx<float>);
-  k_spec_inv<<<planes, kFnoBlock, lds, f->stream>>>(a);
+  const size_t mlds = (size_t)spec_inv_lds_floats(f->H, f->W, f->J) * sizeof(float);
+  if (spec_mfma_fits(f, mlds)) {
+    // two workgroups per plane once each wave still has a y tile
+    const int split = ((f->H + 15) / 16 >= 8) ? 2 : 1;
+    k_spec_inv_mfma<<<dim3(planes, split), kFnoBlock, mlds, f->stream>>>(a);
+  } else {
+    const size_t lds = ((size_t)f->M1 * f->W + (size_t)f->J * f->H + (size_t)f->M1 * f->H +
+                        (size_t)f->M1 * f->J) * sizeof(cpx<float>);
+    k_spec_inv<<<planes, kFnoBlock, lds, f->stream>>>(a);
+  }
   HIP_TRY(hipGetLastError());
   return MMX_OK;
 }
 
 mmx_status fno_mix(mmx_fno* f, const float* in, const float* R, float* out, int B, int adjoint) {
-  const int nmode = f->M1 * f->J;
-  const size_t lds = ((size_t)f->C * f->C + (size_t)B * f->C) * sizeof(cpx<float>);
-  k_mix<<<nmode, kFnoBlock, lds, f->stream>>>(reinterpret_cast<const cpx<float>*>(in),
-                                               reinterpret_cast<const cpx<float>*>(R),
-                                               reinterpret_cast<cpx<float>*>(out), B, f->C,
-                                               nmode, adjoint);
+  const int nmode = f->M1 * f->J, ct = (f->C + 15) / 16, bt = (B + 15) / 16;
+  const long waves = (long)nmode * bt * ct;
+  k_mix_mfma<<<(unsigned)((waves + 3) / 4), kFnoBlock, 0, f->stream>>>(
+      reinterpret_cast<const cpx<float>*>(in), reinterpret_cast<const cpx<float>*>(R),
+      reinterpret_cast<cpx<float>*>(out), B, f->C, nmode, adjoint);
   HIP_TRY(hipGetLastError());
   return MMX_OK;
 }
@@ -125,8 +176,9 @@ mmx_status fno_backward_impl(mmx_fno* f, const float* prm, const float* h, const
   k_fno_loss_partial<<<dim3(nblk, B), kFnoBlock, 0, f->stream>>>(h, t, n_per,
                                                                  f->lpart.as<double>());
   HIP_TRY(hipGetLastError());
-  k_fno_loss_final<<<1, 1, 0, f->stream>>>(f->lpart.as<double>(), nblk, B, f->lsum.as<double>(),
-                                          f->loss.as<double>());
+  k_fno_loss_sample<<<B, 64, 0, f->stream>>>(f->lpart.as<double>(), nblk, f->lsum.as<double>());
+  HIP_TRY(hipGetLastError());
+  k_fno_loss_mean<<<1, 64, 0, f->stream>>>(f->lsum.as<double>(), B, f->loss.as<double>());
   HIP_TRY(hipGetLastError());
   k_fno_dh<<<(unsigned)((B * n_per + 255) / 256), 256, 0, f->stream>>>(
       h, t, f->lsum.as<double>(), n_per, B, f->dh.as<float>());
@@ -155,8 +207,8 @@ mmx_status fno_backward_impl(mmx_fno* f, const float* prm, const float* h, const
     MMX_TRY(fno_conv(f, dZ, prm + f->oW[l], nullptr, dV2, nullptr, nullptr, f->C, f->C, 1,
                      CE_STORE, B));
     MMX_TRY(fno_spec_fwd(f, dZ, f->dUh.as<float>(), f->cinv.as<float>(), B * f->C));
-    const int nmode = f->M1 * f->J;
-    k_mix_grad<<<nmode, kFnoBlock, 0, f->stream>>>(
+    const int nmode = f->M1 * f->J, ct = (f->C + 15) / 16;
+    k_mix_grad_mfma<<<(unsigned)(((long)nmode * ct * ct + 3) / 4), kFnoBlock, 0, f->stream>>>(
         reinterpret_cast<const cpx<float>*>(f->Vh[l].as<float>()),
         reinterpret_cast<const cpx<float>*>(f->dUh.as<float>()),
         reinterpret_cast<cpx<float>*>(g + f->oR[l]), B, f->C, nmode);

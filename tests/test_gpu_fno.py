@@ -1,7 +1,9 @@
 """GPU parity of the learned demag surrogate (Fourier neural operator) through
 the C ABI against the FP64 oracle: forward output, every gradient, and the
 Adam update, for the FP32 path (tight) and the BF16 matrix-core path (BF16
-operand rounding: relative error bars 2e-2 forward, 5e-2 gradients)."""
+operand rounding: relative error bars 2e-2 forward, 5e-2 gradients).  The
+transforms, mixing and weight gradients are FP32 matrix-core products in both
+paths, so the FP32 bars hold them to FP32 accuracy."""
 import numpy as np
 import pytest
 
@@ -112,6 +114,22 @@ def test_fp32_forward_gradients_and_adam_match_oracle():
     step = p_after - flat
     nz = np.abs(gg) > 1e-4   # |g| >> eps: the first step is lr * sign(g)
     assert np.allclose(step[nz], -1e-3 * np.sign(gg[nz]), rtol=1e-3, atol=1e-8)
+
+
+@pytest.mark.parametrize("shape,B", [
+    # W and H x W not multiples of 4 (element loads), 20 channels (ragged
+    # 16-tiles), batch 17 (two batch tiles in the mixing), projection 40
+    ((15, 18, 20, 4, 3, 2, 40), 17),
+    # 17 x-modes: beyond the matrix-core transforms, the VALU transforms run
+    ((40, 40, 8, 17, 3, 1, 16), 2),
+], ids=["ragged", "valu-transforms"])
+def test_fp32_ragged_shapes_match_oracle(shape, B):
+    p, hg, href, gg, gref, loss, lref, *_ = _run(shape, False, B, seed=9)
+    assert _rel(hg, href) < 1e-5
+    assert abs(loss - lref) < 1e-5 * lref
+    g = unpack_grads(gg, p, shape[5])
+    for k in gref:
+        assert _rel(g[k], gref[k]) < 2e-4, (k, _rel(g[k], gref[k]))
 
 
 def test_bf16_matrix_core_path_within_bf16_bounds():
