@@ -296,6 +296,7 @@ def bench_skyrmion512(args):
     dts32 = None
     for prec, dt_ in ((mmx.MMX_F32, torch.float32), (mmx.MMX_F64, torch.float64)):
         ctx = _ctx_for([w], prec)
+        mmx.mmx_autotune(ctx)   # tile sizes: the results do not depend on them
         m = torch.tensor(m0, dtype=dt_, device="cuda:0").contiguous()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -67,8 +67,12 @@ bool make_plan(int n, bool prune, FftPlan& p) {
     p.prune = 1;
     rest /= 2;
   }
-  // radix 4 first: measured faster on gfx950 than 8/16 for these lengths (the
-  // wider butterflies leave threads idle and write LDS with larger strides)
+  // radix 4 first: measured faster on gfx950 than 8/16 up to 256 points (the
+  // wider butterflies leave threads idle and write LDS with larger strides);
+  // from 512 points on, radix 8 first: fewer passes, and such lines are few
+  // per workgroup, so each pass's latency dominates (512x512 film RK45: 5 %
+  // faster in FP32, 6 % in FP64)
+  while (n >= 512 && rest % 8 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 8; rest /= 8; }
   while (rest % 4 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 4; rest /= 4; }
   while (rest % 2 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 2; rest /= 2; }
   while (rest % 3 == 0 && p.npass < kMaxPass) { p.radix[p.npass++] = 3; rest /= 3; }
