@@ -272,7 +272,11 @@ __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
   const int W = a.W, Py = a.Py, nl = 3 * W;
   cpx<T>* Bf = A + nl * Py;
   const cpx<T>* tw = stage_table(Bf + nl * Py, a.tw, Py);
-  const int r = blockIdx.z, kx0 = blockIdx.x * W;
+  // neighbouring column tiles share the cache lines of the spectrum rows:
+  // keep them on one XCD (one L2) instead of dealing them round robin
+  int bx, by, bz;
+  xcd_block(bx, by, bz);
+  const int r = bz, kx0 = bx * W;
   const size_t rbase = (size_t)r * 3;
   for (int t = threadIdx.x; t < nl * Py; t += blockDim.x) {
     const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, Py), c = udiv(rest, Py);
@@ -317,12 +321,13 @@ __global__ void __launch_bounds__(kBlock) k_ypass(YArgs<T> a) {
   const int W = a.W, Py = a.Py, ld = Py + 1;
   cpx<T>* Bf = A + W * ld;
   const cpx<T>* tw = stage_table(Bf + W * ld, a.tw, Py);
-  const int kx0 = blockIdx.x * W;
+  int bx, by, bz;
+  xcd_block(bx, by, bz);  // neighbouring column tiles on one XCD (shared lines)
+  const int kx0 = bx * W;
   // one (component, z) plane of one replica: no product couples the
   // components here, so a workgroup takes W columns of a single one (wider
   // tiles, longer contiguous runs along kx)
-  cpx<T>* __restrict__ P =
-      a.S + ((size_t)blockIdx.z * 3 * a.nz + blockIdx.y) * a.Sy * a.Kx + kx0;
+  cpx<T>* __restrict__ P = a.S + ((size_t)bz * 3 * a.nz + by) * a.Sy * a.Kx + kx0;
   const int nin = INV ? Py : a.ny;
   for (int t = threadIdx.x; t < W * Py; t += blockDim.x) {
     const int w = umod(t, W), y = udiv(t, W);
@@ -348,7 +353,9 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
   const int W = a.W, Pz = a.Pz, nl = 3 * W;
   cpx<T>* Bf = A + nl * Pz;
   const cpx<T>* tw = stage_table(Bf + nl * Pz, a.tw, Pz);
-  const int r = blockIdx.z, ky = blockIdx.y, kx0 = blockIdx.x * W;
+  int bx, by, bz;
+  xcd_block(bx, by, bz);  // neighbouring column tiles on one XCD (shared lines)
+  const int r = bz, ky = by, kx0 = bx * W;
   const size_t rbase = (size_t)r * 3;
   for (int t = threadIdx.x; t < nl * Pz; t += blockDim.x) {
     const int w = umod(t, W), rest = udiv(t, W), z = umod(rest, Pz), c = udiv(rest, Pz);
