@@ -385,6 +385,47 @@ def test_uneven_groups_in_one_context(prec):
 
 
 @pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
+def test_uneven_groups_switching_times_bitwise(prec):
+    """Several groups in one captured Heun sequence run as concurrent graph
+    branches; their switching times (folded into the register column kernel
+    for the 32x32 group, a separate reduction for the others) and states
+    equal those of each group's own context bit for bit."""
+    import paper_2608_15253_amd as mmx
+    terms = ("exchange", "anisotropy", "zeeman", "demag", "thermal")
+    shapes = [((32, 32, 1), 3), ((8, 8, 1), 2), ((16, 12, 1), 2)]
+    cases = [Case(n, (4e-9, 4e-9, 4e-9), R=R, alpha=1.0, Ku=1e5, B=(0, 0, -2.0), T=50.0,
+                  seeds=list(replica_seeds(70 + g, R)), terms=terms)
+             for g, (n, R) in enumerate(shapes)]
+    m0s = [_round(uniform(c.n, (0.05, 0.0, 1.0), replicas=c.R), prec) for c in cases]
+    flat = np.concatenate([m.ravel() for m in m0s])
+    nsteps, dt = 200, 1e-13     # captured runs of 128, 64 and 8 steps
+    R_total = sum(c.R for c in cases)
+    ctx = open_ctx(cases[0], prec, groups=cases)
+    try:
+        md = dev(flat, prec)
+        ts = dev(-np.ones(R_total), 2)
+        mmx.mmx_heun(ctx, md, dt, nsteps, 0, ts)
+        got, gts = host(md), host(ts)
+    finally:
+        mmx.mmx_destroy(ctx)
+    assert (gts > 0).sum() > 0
+    off, roff = 0, 0
+    for c, m0 in zip(cases, m0s):
+        one = open_ctx(c, prec)
+        try:
+            ms = dev(m0, prec)
+            t1 = dev(-np.ones(c.R), 2)
+            mmx.mmx_heun(one, ms, dt, nsteps, 0, t1)
+            single, st = host(ms), host(t1)
+        finally:
+            mmx.mmx_destroy(one)
+        assert np.array_equal(got[off:off + m0.size].reshape(m0.shape), single), c.n
+        assert np.array_equal(gts[roff:roff + c.R], st), (c.n, gts[roff:roff + c.R], st)
+        off += m0.size
+        roff += c.R
+
+
+@pytest.mark.parametrize("prec", [2, 1], ids=["f64", "f32"])
 def test_heun_resume_is_bitwise(prec):
     """Checkpoint / resume of the thermal Heun run: the state is m and the
     step index (the Philox counter), so N steps equal N/2 steps, a copy of m
