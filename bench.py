@@ -247,6 +247,18 @@ def bench_uneven(args):
                        "T_K": ws[0].T, "dt_s": dt}, "finite": finite}
 
 
+def _tile(ctx, args):
+    """Tile sizes of group 0: the autotuner's choice, or those given with
+    --tiles (to profile the same configuration that a timed run chose; the
+    autotuner's short timings can pick differently under a tracer)."""
+    import paper_2608_15253_amd as mmx
+    if args.tiles:
+        mmx.mmx_set_tiles(ctx, 0, args.tiles)
+    else:
+        mmx.mmx_autotune(ctx)
+    return mmx.mmx_get_tiles(ctx, 0)
+
+
 def bench_closure(args):
     """256x256x32 block of 4 nm cubes (Landau seed), FP32 RK45 at tol 1e-6
     from 0 to t_end: accepted steps per second and cell-steps/s."""
@@ -255,7 +267,7 @@ def bench_closure(args):
     from workloads import closure_block_fp32, landau_seed
     w = closure_block_fp32()
     ctx = _ctx_for([w], mmx.MMX_F32)
-    mmx.mmx_autotune(ctx)
+    tiles = _tile(ctx, args)
     t_end = args.t_end or 2e-11
     m = torch.tensor(landau_seed(w.n)[None], dtype=torch.float32, device="cuda:0").contiguous()
     warm = m.clone()
@@ -276,7 +288,7 @@ def bench_closure(args):
             "config": {"workload": "closure_block_256x256x32_rk45", "t_end_s": t_end,
                        "tol": w.extra["tol"]},
             "accepted": st.accepted, "rejected": st.rejected, "seconds": el,
-            "energy_J": E[0].tolist()}
+            "energy_J": E[0].tolist(), "tiles": list(tiles)}
 
 
 def bench_skyrmion512(args):
@@ -296,7 +308,7 @@ def bench_skyrmion512(args):
     dts32 = None
     for prec, dt_ in ((mmx.MMX_F32, torch.float32), (mmx.MMX_F64, torch.float64)):
         ctx = _ctx_for([w], prec)
-        mmx.mmx_autotune(ctx)   # tile sizes: the results do not depend on them
+        tiles = _tile(ctx, args)   # the results do not depend on the tiles
         m = torch.tensor(m0, dtype=dt_, device="cuda:0").contiguous()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -315,11 +327,11 @@ def bench_skyrmion512(args):
         Q = torch.zeros(1, dtype=torch.float64, device="cuda:0")
         mmx.mmx_energy(ctx, m, E)
         mmx.mmx_topological_charge(ctx, m, Q)
-        out[prec] = (m.double().cpu().numpy(), E[0].tolist(), float(Q[0]), st, el)
+        out[prec] = (m.double().cpu().numpy(), E[0].tolist(), float(Q[0]), st, el, list(tiles))
         mmx.mmx_destroy(ctx)
         print(f"  prec {prec}: {el:.1f} s, {st.accepted} steps", file=sys.stderr, flush=True)
-    m32, e32, q32, s32, t32 = out[mmx.MMX_F32]
-    m64, e64, q64, s64, t64 = out[mmx.MMX_F64]
+    m32, e32, q32, s32, t32, tl32 = out[mmx.MMX_F32]
+    m64, e64, q64, s64, t64, tl64 = out[mmx.MMX_F64]
     cells = w.n[0] * w.n[1]
     return {"metric": "RK45 cell-steps/s (accepted steps x cells / s), FP32 precision form",
             "value": cells * s32.accepted / t32, "unit": "cell-steps/s", "n_gpus": 1,
@@ -327,9 +339,9 @@ def bench_skyrmion512(args):
             "config": {"workload": "skyrmion_film_512x512_rk45", "t_end_s": t_end,
                        "tol": x["tol"]},
             "fp32": {"seconds": t32, "accepted": s32.accepted, "rejected": s32.rejected,
-                     "energy_J": e32, "Q": q32},
+                     "energy_J": e32, "Q": q32, "tiles": tl32},
             "fp64": {"seconds": t64, "accepted": s64.accepted, "rejected": s64.rejected,
-                     "energy_J": e64, "Q": q64},
+                     "energy_J": e64, "Q": q64, "tiles": tl64},
             "max_dm_fp32_vs_fp64": float(np.abs(m32 - m64).max()),
             "max_dm_fp32_vs_fp64_replay_of_fp32_steps": float(np.abs(m32 - out["replay64"]).max()),
             "rel_dE_total": abs(e32[5] - e64[5]) / abs(e64[5]), "dQ": abs(q32 - q64)}
@@ -810,6 +822,8 @@ def main():
                     help="histogram: steps of the oracle subset check")
     ap.add_argument("--t-end", type=float, default=None,
                     help="closure / skyrmion512: integration horizon (s)")
+    ap.add_argument("--tiles", type=int, nargs=3, default=None, metavar=("L", "WY", "WZ"),
+                    help="closure / skyrmion512: fixed tile sizes instead of the autotuner's")
     args = ap.parse_args()
     if args.traffic_summary:
         print(traffic_summary(*args.traffic_summary, args.traffic_cmd, args.replicas))

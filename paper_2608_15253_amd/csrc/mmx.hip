@@ -2123,7 +2123,9 @@ mmx_status time_eval(mmx_ctx* ctx, Group& G, float& ms) {
   ep.out = G.k[0].p;
   mmx_status st = MMX_OK;
   float best = 1e30f;
-  for (int rep = 0; rep < 3 && st == MMX_OK; ++rep) {
+  // five repetitions, the fastest of the last four (the first warms caches):
+  // single evaluations of small grids take tens of microseconds
+  for (int rep = 0; rep < 5 && st == MMX_OK; ++rep) {
     (void)hipEventRecord(a, ctx->stream);
     st = eval_group<T>(ctx, G, G.ms.as<T>(), Combine{}, ep, 0, 1.0, nullptr, 0.0, nullptr,
                        ctx->terms & ~MMX_THERMAL);
@@ -2131,7 +2133,7 @@ mmx_status time_eval(mmx_ctx* ctx, Group& G, float& ms) {
     (void)hipEventSynchronize(b);
     float t = 0;
     (void)hipEventElapsedTime(&t, a, b);
-    if (rep > 0) best = std::min(best, t);  // first repetition warms caches
+    if (rep > 0) best = std::min(best, t);
   }
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
