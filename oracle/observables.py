@@ -13,6 +13,12 @@ printing their discretisation.  Readings:
 * Topological charge: Q = (1/4 pi) sum_i m_i . (d_x m x d_y m)_i dx dy with
   central differences, periodic wrap on periodic axes, and the cell itself as the
   missing neighbour at open edges; layer z = 0.
+* Switching probability of a thermally activated macrospin under spin-transfer
+  torque in a window t: the finite-window Neel-Brown law with Sun's barrier
+  reduction as the paper states it (Results, replica-batched STT switching
+  sweep), P = 1 - exp[-t f0 exp(-Delta (1 - J/J_c0)^2)], the barrier clamped
+  at zero for J >= J_c0.  The paper fixes f0 and Delta from the macrospin
+  parameters without printing f0; the caller passes both.
 """
 from __future__ import annotations
 
@@ -69,3 +75,13 @@ def topological_charge(m, grid):
     dym = diff(1, 1) if grid.n[1] > 1 else np.zeros_like(m0)
     q = np.sum(m0 * np.cross(dxm, dym, axis=0))
     return float(q * grid.cell[0] * grid.cell[1] / (4.0 * math.pi))
+
+
+def switching_probability_neel_brown_sun(j, t, f0, delta):
+    """P_sw(J / J_c0 = j) in a window of t seconds for attempt frequency f0
+    (1/s) and thermal stability delta = K V / (kB T) (Results, replica-batched
+    STT switching sweep): the Neel-Brown escape probability with the barrier
+    delta (1 - j)^2, zero for j >= 1."""
+    j = np.asarray(j, dtype=np.float64)
+    barrier = delta * np.clip(1.0 - j, 0.0, None) ** 2
+    return -np.expm1(-t * f0 * np.exp(-barrier))   # exact also for tiny probabilities

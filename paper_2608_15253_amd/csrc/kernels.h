@@ -917,7 +917,10 @@ __device__ inline double mz_checked(const T mn[3]) {
 // dt Omega.  Corrector at m~ (mc) from the saved state mo: Heun's
 // m + dt/2 (k1 + k) written as (mo + m~)/2 + dt/2 k (m~ = mo + dt k1, so no
 // slope has to be stored), normalised; or the rotation of mo by
-// dt/2 (Omega_1 + Omega_2), not normalised.
+// dt/2 (Omega_1 + Omega_2), which keeps |m| = 1 in exact arithmetic.  In FP32
+// the rounding of cos|w| near 1 repeats step after step when the rotation
+// barely changes (a macrospin at rest near its easy axis drifted by 1e-3 in
+// |m| over 2e5 steps), so the FP32 rotation is renormalised; FP64 is not.
 // tau: spin-transfer torque at (mc), entering Omega as mc x tau
 template <typename T>
 __device__ inline void heun_predict(T gpm, T alpha, bool rot, const T mc[3], const T H[3],
@@ -949,6 +952,11 @@ __device__ inline void heun_correct(T gpm, T alpha, bool rot, const T mc[3], con
 #pragma unroll
     for (int c = 0; c < 3; ++c) w[c] = T(0.5) * dt * (k1v[c] + o[c]);
     rodrigues(mo, w, mn);
+    if constexpr (sizeof(T) == sizeof(float)) {
+      const T inv = T(1) / sqrt(mn[0] * mn[0] + mn[1] * mn[1] + mn[2] * mn[2]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) mn[c] *= inv;
+    }
   } else {
     T u[3];
 #pragma unroll

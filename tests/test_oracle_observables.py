@@ -49,3 +49,22 @@ def test_relaxing_skyrmion_keeps_charge_near_minus_one():
     res = it.rk45_run(m0, grid, mat, 0.0, 5e-11, tol=1e-5, dt0=1e-14, energy=True)
     assert abs(ob.topological_charge(res.m, grid) + 1) < 0.15
     assert res.energy[-1] < res.energy[0]
+
+
+def test_neel_brown_sun_limits_and_half_crossing():
+    """Switching law (Results, replica-batched STT switching sweep), pinned by
+    what its definition fixes independently of its code: no barrier at and
+    above J_c0 (P = 1 - exp(-t f0) for every j >= 1), the zero-current limit
+    1 - exp(-t f0 e^-Delta), strict increase below J_c0, and the half-switching
+    current solved by hand, j* = 1 - sqrt(ln(t f0 / ln 2) / Delta)."""
+    from oracle.observables import switching_probability_neel_brown_sun as psw
+    t, f0, delta = 2e-9, 4.9e10, 121.0
+    assert np.allclose(psw([1.0, 1.2, 3.0], t, f0, delta), -np.expm1(-t * f0), rtol=0, atol=1e-15)
+    assert abs(psw(0.0, t, f0, delta) - (-math.expm1(-t * f0 * math.exp(-delta)))) < 1e-60
+    j = np.linspace(0.0, 1.0, 401)
+    p = psw(j, t, f0, delta)
+    assert np.all(np.diff(p) >= 0) and p[-1] > p[0]
+    js = 1.0 - math.sqrt(math.log(t * f0 / math.log(2.0)) / delta)
+    assert abs(psw(js, t, f0, delta) - 0.5) < 1e-12
+    # a longer window or a faster attempt rate lowers the half-switching current
+    assert psw(js, 2 * t, f0, delta) > 0.5 and psw(js, t, 2 * f0, delta) > 0.5
