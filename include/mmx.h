@@ -272,9 +272,11 @@ mmx_status mmx_heun(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t 
  * alpha m x H).  Per step, with the thermal field drawn once (as mmx_heun):
  * Omega_1 at m; predictor m~ = rotation of m about Omega_1 by |Omega_1| dt;
  * Omega_2 at m~; the new state is the rotation of m about (Omega_1 +
- * Omega_2)/2 by |Omega_1 + Omega_2| dt/2.  No normalisation.  Step numbering
- * and t_switch as in mmx_heun.  Runs on the staged path (MMX_EUNSUP under
- * MMX_PATH_FUSED). */
+ * Omega_2)/2 by |Omega_1 + Omega_2| dt/2.  FP64 runs take no normalisation;
+ * FP32 runs renormalise the new state (the rounding of cos|w| near 1 would
+ * otherwise repeat step after step when the rotation barely changes).  Step
+ * numbering and t_switch as in mmx_heun.  Runs on the staged path
+ * (MMX_EUNSUP under MMX_PATH_FUSED). */
 mmx_status mmx_depondt(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t step0,
                        void* t_switch);
 
