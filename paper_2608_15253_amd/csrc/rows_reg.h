@@ -209,20 +209,37 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   //    spectrum row is read once, in coalesced order (columns q + N1 i, lane
   //    0 also hx; all loads issued up front), and staged in LDS, where each
   //    lane picks its pairs
-  cpx<T> sv[3][N2], slast[3];
+  //    Rows of up to 64 points load all three components up front; longer
+  //    rows (N2 >= 12) load one component at a time, which keeps their
+  //    register count down (16 x 16: 195 -> 170 VGPRs; measured faster there
+  //    and slower on the 8 x 8 rows)
+  constexpr bool kUpFront = N2 < 12;
+  cpx<T> sv[kUpFront ? 3 : 1][N2], slast[kUpFront ? 3 : 1];
+  if constexpr (kUpFront) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
+    for (int c = 0; c < 3; ++c) {
 #pragma unroll
-    for (int i = 0; i < N2; ++i)
-      sv[c][i] = live ? Srow[c * cstride + q + N1 * i] : cpx<T>{0, 0};
-    slast[c] = (live && q == 0) ? Srow[c * cstride + hx] : cpx<T>{0, 0};
+      for (int i = 0; i < N2; ++i)
+        sv[c][i] = live ? Srow[c * cstride + q + N1 * i] : cpx<T>{0, 0};
+      slast[c] = (live && q == 0) ? Srow[c * cstride + hx] : cpx<T>{0, 0};
+    }
   }
   cpx<T> v[3][SP::NV];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    if constexpr (kUpFront) {
 #pragma unroll
-    for (int i = 0; i < N2; ++i) E[q + N1 * i] = sv[c][i];
-    if (q == 0) E[hx] = slast[c];
+      for (int i = 0; i < N2; ++i) E[q + N1 * i] = sv[c][i];
+      if (q == 0) E[hx] = slast[c];
+    } else {
+#pragma unroll
+      for (int i = 0; i < N2; ++i)
+        sv[0][i] = live ? Srow[c * cstride + q + N1 * i] : cpx<T>{0, 0};
+      slast[0] = (live && q == 0) ? Srow[c * cstride + hx] : cpx<T>{0, 0};
+#pragma unroll
+      for (int i = 0; i < N2; ++i) E[q + N1 * i] = sv[0][i];
+      if (q == 0) E[hx] = slast[0];
+    }
     __syncthreads();
 #pragma unroll
     for (int s = 0; s < S2; ++s)
