@@ -450,8 +450,10 @@ mmx_status mmx_autotune(mmx_ctx* ctx);
  * mmx_fno_backward differentiates the last mmx_fno_forward (its activations
  * stay in library buffers) and overwrites grads.  Errors: MMX_EINVAL for bad
  * sizes / nulls, MMX_EUNSUP beyond C, Cp <= 128, batch <= 64, MMX_ESTATE for a
- * backward without forward.  Work is queued on the FNO's stream; the loss is
- * returned synchronously when `loss` is not null.
+ * backward without forward.  mmx_fno_create allocates every device buffer
+ * the forward and backward passes use (sized for batch_max); forward,
+ * backward and Adam allocate nothing.  Work is queued on the FNO's stream;
+ * the loss is returned synchronously when `loss` is not null.
  * ------------------------------------------------------------------------ */
 typedef struct mmx_fno mmx_fno;
 mmx_status mmx_fno_create(int32_t H, int32_t W, int32_t C, int32_t M1, int32_t M2, int32_t L,

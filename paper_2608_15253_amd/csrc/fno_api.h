@@ -48,18 +48,27 @@ void launch_dw(dim3 grid, hipStream_t st, bool vec, const float* dY, const float
     k_dw_mfma<MT, KT, false><<<grid, 64, 0, st>>>(dY, X, M, K, P, chunk, kgroups, part);
 }
 
+// pixel chunk of the weight-gradient partials: about kDwRows partial rows
+// (chunks x samples) per map, at least 64 pixels, a multiple of 16
+long dw_chunk(long P, int B) {
+  const long chunk = ((long)B * P + kDwRows - 1) / kDwRows;
+  return std::max(64L, (chunk + 15) / 16 * 16);
+}
+
+long dw_rows(long P, int B) { return (P + dw_chunk(P, B) - 1) / dw_chunk(P, B) * B; }
+
 // grads[0 .. M K + M) = weight and bias gradients of a channel map: partial
 // sums per pixel chunk on the matrix cores, then a fixed-order sum of the
-// chunks
+// chunks.  The partial buffer is sized at creation for every batch up to the
+// maximum, so the backward pass allocates nothing.
 mmx_status fno_dw(mmx_fno* f, const float* dY, const float* X, int M, int K, int B, float* out) {
   const int npair = M * K + M;
   const long P = f->P;
-  long chunk = ((long)B * P + kDwRows - 1) / kDwRows;
-  chunk = std::max(64L, (chunk + 15) / 16 * 16);
+  const long chunk = dw_chunk(P, B);
   const int nch = (int)((P + chunk - 1) / chunk);
   const int rows = nch * B;
-  const size_t need = (size_t)rows * npair * sizeof(float);
-  if (f->part.bytes < need) HIP_TRY(f->part.alloc(need));
+  if (f->part.bytes < (size_t)rows * npair * sizeof(float))
+    return fail(MMX_ESTATE, "weight-gradient partial buffer too small");
   // output tiles in groups of at most 4 x 4
   auto group = [](int tiles) { return tiles >= 3 ? 4 : tiles; };
   const int mt = (M + 15) / 16, kt = (K + 15) / 16, MT = group(mt), KT = group(kt);
@@ -317,6 +326,13 @@ mmx_status mmx_fno_create(int32_t H, int32_t W, int32_t C, int32_t M1, int32_t M
   HIP_TRY(f->Uh.alloc(spec));
   HIP_TRY(f->dUh.alloc(spec));
   HIP_TRY(f->dVh.alloc(spec));
+  // weight-gradient partials: largest map (lift, C x C, projections) at the
+  // largest row count over batches 1 .. batch_max
+  long rows_max = 0;
+  for (int b = 1; b <= batch_max; ++b) rows_max = std::max(rows_max, dw_rows(f->P, b));
+  const long npair_max =
+      std::max(std::max((long)C * 5 + C, (long)C * C + C), std::max((long)Cp * C + Cp, 3L * Cp + 3));
+  HIP_TRY(f->part.alloc((size_t)rows_max * npair_max * sizeof(float)));
   HIP_TRY(f->lpart.alloc((size_t)batch_max * 64 * 2 * sizeof(double)));
   HIP_TRY(f->lsum.alloc((size_t)batch_max * 2 * sizeof(double)));
   HIP_TRY(f->loss.alloc(sizeof(double)));

@@ -37,7 +37,7 @@ struct HeunFusedArgs {
   double* tsw;          // switching times or null
   double dt;
   uint64_t step0;
-  const unsigned long long* stepdev;  // if set, step0 is read here (graph replays)
+  const unsigned long long* stepdev;  // if set, the step index is *stepdev + step0
   int nsteps;
   int C;                // grid rows per x chunk
   int W;                // spectrum columns per y chunk
@@ -185,7 +185,7 @@ __global__ void __launch_bounds__(kFusedBlock) k_heun_fused(HeunFusedArgs<T> a) 
   const int l = t / nx, x = t - (t / nx) * nx;
   const bool active_col = t < C * nx;
   for (int s = 0; s < a.nsteps; ++s) {
-    const uint64_t step = (a.stepdev ? *a.stepdev : a.step0) + (uint64_t)s;
+    const uint64_t step = (a.stepdev ? *a.stepdev : 0ull) + a.step0 + (uint64_t)s;
     double mz_acc = 0.0;
     for (int stage = 0; stage < 2; ++stage) {
       // predictor: fields at m; corrector: fields at the predictor state ms

@@ -250,6 +250,7 @@ struct YArgs {
   const int* sw_nblk;  // the corrector's workgroups per replica (device)
   int sw_N;
   double sw_dt;
+  // the check's time is st sw_dt, st = (*sw_stepdev if set) + sw_step
   unsigned long long sw_step;
   const unsigned long long* sw_stepdev;
 };
@@ -278,13 +279,19 @@ __global__ void __launch_bounds__(kBlock) k_yconv(YArgs<T> a) {
   xcd_block(bx, by, bz);
   const int r = bz, kx0 = bx * W;
   const size_t rbase = (size_t)r * 3;
-  for (int t = threadIdx.x; t < nl * Py; t += blockDim.x) {
-    const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, Py), c = udiv(rest, Py);
-    cpx<T> v = {0, 0};
-    if (y < a.ny && kx0 + w < a.Kx)
-      v = a.S[(((rbase + c) * a.nz) * a.Sy + y) * a.Kx + kx0 + w];
-    A[(c * W + w) * Py + y] = v;
-  }
+  batched_move<cpx<T>>(
+      nl * Py,
+      [&](int t) {
+        const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, Py), c = udiv(rest, Py);
+        cpx<T> v = {0, 0};
+        if (y < a.ny && kx0 + w < a.Kx)
+          v = a.S[(((rbase + c) * a.nz) * a.Sy + y) * a.Kx + kx0 + w];
+        return v;
+      },
+      [&](int t, cpx<T> v) {
+        const int w = umod(t, W), rest = udiv(t, W), y = umod(rest, Py), c = udiv(rest, Py);
+        A[(c * W + w) * Py + y] = v;
+      });
   __syncthreads();
   cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, tw);
   cpx<T>* scratch = (X == A) ? Bf : A;
@@ -329,12 +336,15 @@ __global__ void __launch_bounds__(kBlock) k_ypass(YArgs<T> a) {
   // tiles, longer contiguous runs along kx)
   cpx<T>* __restrict__ P = a.S + ((size_t)bz * 3 * a.nz + by) * a.Sy * a.Kx + kx0;
   const int nin = INV ? Py : a.ny;
-  for (int t = threadIdx.x; t < W * Py; t += blockDim.x) {
-    const int w = umod(t, W), y = udiv(t, W);
-    cpx<T> v = {0, 0};
-    if (y < nin && kx0 + w < a.Kx) v = P[(size_t)y * a.Kx + w];
-    A[w * ld + y] = v;
-  }
+  batched_move<cpx<T>>(
+      W * Py,
+      [&](int t) {
+        const int w = umod(t, W), y = udiv(t, W);
+        cpx<T> v = {0, 0};
+        if (y < nin && kx0 + w < a.Kx) v = P[(size_t)y * a.Kx + w];
+        return v;
+      },
+      [&](int t, cpx<T> v) { A[umod(t, W) * ld + udiv(t, W)] = v; });
   __syncthreads();
   const cpx<T>* Y = lds_fft<T, INV>(A, Bf, W, INV ? a.pi : a.pf, tw, ld);
   const int nout = INV ? a.ny : Py;
@@ -357,13 +367,19 @@ __global__ void __launch_bounds__(kBlock) k_zconv(YArgs<T> a) {
   xcd_block(bx, by, bz);  // neighbouring column tiles on one XCD (shared lines)
   const int r = bz, ky = by, kx0 = bx * W;
   const size_t rbase = (size_t)r * 3;
-  for (int t = threadIdx.x; t < nl * Pz; t += blockDim.x) {
-    const int w = umod(t, W), rest = udiv(t, W), z = umod(rest, Pz), c = udiv(rest, Pz);
-    cpx<T> v = {0, 0};
-    if (z < a.nz && kx0 + w < a.Kx)
-      v = a.S[(((rbase + c) * a.nz + z) * a.Sy + ky) * a.Kx + kx0 + w];
-    A[(c * W + w) * Pz + z] = v;
-  }
+  batched_move<cpx<T>>(
+      nl * Pz,
+      [&](int t) {
+        const int w = umod(t, W), rest = udiv(t, W), z = umod(rest, Pz), c = udiv(rest, Pz);
+        cpx<T> v = {0, 0};
+        if (z < a.nz && kx0 + w < a.Kx)
+          v = a.S[(((rbase + c) * a.nz + z) * a.Sy + ky) * a.Kx + kx0 + w];
+        return v;
+      },
+      [&](int t, cpx<T> v) {
+        const int w = umod(t, W), rest = udiv(t, W), z = umod(rest, Pz), c = udiv(rest, Pz);
+        A[(c * W + w) * Pz + z] = v;
+      });
   __syncthreads();
   cpx<T>* X = lds_fft<T, false>(A, Bf, nl, a.pf, tw);
   cpx<T>* scratch = (X == A) ? Bf : A;
@@ -587,7 +603,9 @@ struct FArgs {
   const uint64_t* seeds;
   double sig2pref;  // 2 alpha kB / (mu0^2 Ms V gamma0); sigma^2 = sig2pref T / dt
   uint64_t step;
-  const unsigned long long* stepdev;  // if set, the step index is read here (graph replays)
+  // if set, the step index is *stepdev + step (graph replays: a device
+  // counter advanced once per captured run, step the offset within it)
+  const unsigned long long* stepdev;
   double dt_th;
   const T* m;
   cpx<T>* S;
@@ -1065,7 +1083,7 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
   T* out_r = a.out ? a.out + rb : nullptr;
   T* mout_r = a.mout ? a.mout + rb : nullptr;
   T* k1_r = a.k1 ? a.k1 + rb : nullptr;
-  const uint64_t step_now = a.stepdev ? *a.stepdev : a.step;
+  const uint64_t step_now = (a.stepdev ? *a.stepdev : 0ull) + a.step;
   const T bJ = stt_bj(a, r);
   double acc[5] = {0, 0, 0, 0, 0};
   for (int t = threadIdx.x; t < ncell_blk; t += blockDim.x) {

@@ -1668,7 +1668,8 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
     }
   }
   // one Heun step of every staged group on ctx->stream; with ctx->cur_stepdev
-  // set the step index comes from device memory and is advanced in-stream
+  // set the kernels take the step index *cur_stepdev + step (step: the offset
+  // within a captured run, after which the counter is advanced once)
   auto one_step = [&](uint64_t step) -> mmx_status {
     hipStream_t st = ctx->stream;
     for (int gi : staged) {
@@ -1727,14 +1728,11 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       if (tsw_d && !folds[gi]) {
         ProfScope ps(ctx->prof, "k_switch_reduce", st);
         k_switch_reduce<<<(G.R + 63) / 64, 64, 0, st>>>(G.partial.as<double>(), G.nblk_last, G.R,
-                                                         G.N, tsw_d + roff, (double)(step + 1) * dt,
+                                                         G.N, tsw_d + roff,
+                                                         (unsigned long long)(step + 1),
                                                          ctx->cur_stepdev, dt);
         HIP_TRY(hipGetLastError());
       }
-    }
-    if (ctx->cur_stepdev) {
-      k_inc_u64<<<1, 1, 0, st>>>(const_cast<unsigned long long*>(ctx->cur_stepdev), 1ull);
-      HIP_TRY(hipGetLastError());
     }
     return MMX_OK;
   };
@@ -1774,8 +1772,10 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
   }
   if (!ctx->prof.on && n_steps > 0) {
     // n_steps = a sum of runs of 2^i steps (i < kHeunGraphs, largest first);
-    // each run length is captured once into a graph (the step index lives in
-    // device memory and is advanced in the graph) and kept for later calls
+    // each run length is captured once into a graph (the run's first step
+    // index lives in device memory, each captured step adds its offset within
+    // the run, and the graph's last node advances it by the run length) and
+    // kept for later calls
     // with the same arrays and configuration, so every call of any length
     // replays captured steps
     MMX_TRY(ensure_graph_stream(ctx));
@@ -1812,7 +1812,9 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
       if (gs.exec[i]) continue;
       ctx->cur_stepdev = sd;
       const mmx_status st = capture_graph(ctx, [&]() -> mmx_status {
-        for (int j = 0; j < (1 << i); ++j) MMX_TRY(one_step(step0));
+        for (int j = 0; j < (1 << i); ++j) MMX_TRY(one_step((uint64_t)j));
+        k_inc_u64<<<1, 1, 0, ctx->stream>>>(sd, 1ull << i);
+        HIP_TRY(hipGetLastError());
         return MMX_OK;
       }, &gs.exec[i]);
       ctx->cur_stepdev = nullptr;
@@ -1836,7 +1838,7 @@ mmx_status heun_impl(mmx_ctx* ctx, void* m, double dt, int64_t n_steps, uint64_t
     ProfScope ps(ctx->prof, "k_switch_reduce", s);
     k_switch_reduce<<<(G.R + 63) / 64, 64, 0, s>>>(G.partial.as<double>(), G.nblk_last, G.R, G.N,
                                                    tsw_d + roffs[gi],
-                                                   (double)(step0 + (uint64_t)n_steps) * dt,
+                                                   (unsigned long long)(step0 + (uint64_t)n_steps),
                                                    nullptr, dt);
     HIP_TRY(hipGetLastError());
   }

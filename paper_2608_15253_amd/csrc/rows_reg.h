@@ -280,7 +280,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
     const double Tr = a.Trep[r];
     if (Tr > 0) sigma = (T)sqrt(a.sig2pref * Tr / a.dt_th);
   }
-  const uint64_t step_now = a.stepdev ? *a.stepdev : a.step;
+  const uint64_t step_now = (a.stepdev ? *a.stepdev : 0ull) + a.step;
   const T bJ = STT ? stt_bj(a, r) : T(0);
   const T* __restrict__ mr = a.m + rb;
   T* mout_r = a.mout + rb;

@@ -147,12 +147,15 @@ __global__ void k_rk_commit(const RkState* st, T* m, const T* m7, T* k1, const T
   }
 }
 
-// per-replica fixed-order sums of workgroup partials
+// per-replica fixed-order sums of workgroup partials; the check's time is
+// step_after dt, step_after = (*stepdev if set) + the given count
 __global__ void k_switch_reduce(const double* partial, int nblk, int R, int N, double* tsw,
-                                double t_after, const unsigned long long* stepdev, double dt) {
+                                unsigned long long step_after, const unsigned long long* stepdev,
+                                double dt) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
-  switch_check(partial, tsw, nblk, N, r, stepdev ? (double)(*stepdev + 1) * dt : t_after);
+  const unsigned long long st = (stepdev ? *stepdev : 0ull) + step_after;
+  switch_check(partial, tsw, nblk, N, r, (double)st * dt);
 }
 
 // Retire/refill bookkeeping after a step (one thread per replica): a replica
@@ -167,7 +170,7 @@ __global__ void k_refill_check(const double* partial, int nblk, int R, int N, in
   if (r >= R) return;
   double s = 0;
   for (int b = 0; b < nblk; ++b) s += partial[(size_t)r * nblk + b];
-  const unsigned long long step = stepdev ? *stepdev : step_host;
+  const unsigned long long step = (stepdev ? *stepdev : 0ull) + step_host;
   int f = 0;
   if (s / N < 0) {
     const int c = counts[r];

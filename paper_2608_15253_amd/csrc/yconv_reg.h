@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
   int tile, by, rep;
   xcd_block(tile, by, rep);
   if (a.sw_tsw && tile == 0 && lane == 0) {
-    const unsigned long long st = a.sw_stepdev ? *a.sw_stepdev : a.sw_step;
+    const unsigned long long st = (a.sw_stepdev ? *a.sw_stepdev : 0ull) + a.sw_step;
     switch_check(a.sw_part, a.sw_tsw, *a.sw_nblk, a.sw_N, rep, (double)st * a.sw_dt);
   }
   const int kx = tile * NC + wc;
