@@ -47,7 +47,7 @@ __global__ void __launch_bounds__(64) k_ypass_reg(YArgs<T> a) {
                                       (row * Kx + (unsigned)kx) * (unsigned)sizeof(cpx<T>));
   };
   for (int i = lane; i < n; i += 64) twl[i] = a.tw[i];
-  __syncthreads();
+  wave_sync();
   const cpx<T>* tw = twl;
   cpx<T>* Ew = E + wc * N1 * STR;
   cpx<T> X[N2];
@@ -66,7 +66,7 @@ __global__ void __launch_bounds__(64) k_ypass_reg(YArgs<T> a) {
 #pragma unroll
       for (int cc = 1; cc < N1; ++cc) Ew[cc * STR + av] = cmul(v[s][cc], tw[av * cc]);
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int av = 0; av < N2; ++av) X[av] = Ew[q * STR + av];
     dft_reg<T, false, N2>(X);
@@ -81,7 +81,7 @@ __global__ void __launch_bounds__(64) k_ypass_reg(YArgs<T> a) {
     Ew[q * STR] = X[0];
 #pragma unroll
     for (int av = 1; av < N2; ++av) Ew[q * STR + av] = cmulc(X[av], tw[av * q]);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int s = 0; s < S2; ++s) {
       const int av = q + N1 * s;
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(64) k_zline_reg(YArgs<T> a) {
   };
   // the z pass arguments carry the z twiddles exp(-2 pi i k / Pz) in tw
   for (int i = lane; i < n; i += 64) twl[i] = a.tw[i];
-  __syncthreads();
+  wave_sync();
   const cpx<T>* tw = twl;
   cpx<T>* Ew = E + wc * N1 * STR;
   cpx<T> X[3][N2];
@@ -146,10 +146,10 @@ __global__ void __launch_bounds__(64) k_zline_reg(YArgs<T> a) {
       for (int cc = 1; cc < N1; ++cc) Ew[cc * STR + av] = cmul(v[s][cc], tw[av * cc]);
     }
     if (c < 2) load(c + 1);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int av = 0; av < N2; ++av) X[c][av] = Ew[q * STR + av];
-    __syncthreads();
+    wave_sync();
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) dft_reg<T, false, N2>(X[c]);
@@ -174,7 +174,7 @@ __global__ void __launch_bounds__(64) k_zline_reg(YArgs<T> a) {
     Ew[q * STR] = X[c][0];
 #pragma unroll
     for (int av = 1; av < N2; ++av) Ew[q * STR + av] = cmulc(X[c][av], tw[av * q]);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int s = 0; s < S2; ++s) {
       const int av = q + N1 * s;
@@ -187,7 +187,7 @@ __global__ void __launch_bounds__(64) k_zline_reg(YArgs<T> a) {
         for (int b = 0; b < NB; ++b) at(c, (unsigned)(av + N2 * b)) = u[b];
       }
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 

@@ -67,10 +67,10 @@ __device__ inline void line_transform(cpx<T> (&v)[NV], cpx<T>* E, int q,
       E[cc * STR + av] = INV ? cmulc(v[s * N1 + cc], w) : cmul(v[s * N1 + cc], w);
     }
   }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int av = 0; av < N2; ++av) v[av] = E[q * STR + av];
-  __syncthreads();
+  wave_sync();
   dft_reg<T, INV, N2>(v);
 }
 
@@ -97,10 +97,10 @@ __device__ inline void rows_store_spectrum(const cpx<T> (&v)[3][NV], cpx<T>* E, 
   // cover 2 N1 consecutive columns), lane 0 also the last column kx = hx
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    if (c > 0) __syncthreads();  // the previous component's reads are done
+    if (c > 0) wave_sync();  // the previous component's reads are done
 #pragma unroll
     for (int d = 0; d < N2; ++d) E[q + N1 * d] = v[c][d];
-    __syncthreads();
+    wave_sync();
     if (live) {
 #pragma unroll
       for (int d = 0; d < N2 / 2; ++d) {
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(64) k_rows_fwd(FArgs<T> a) {
     if (i < hx) twl[i] = a.tw[i];
     wpl[i] = a.wpost[i];
   }
-  __syncthreads();
+  wave_sync();
   const T* __restrict__ mr = a.m + rb;
   const unsigned row0 = (unsigned)a.nx * (unsigned)(y + a.ny * z);
   cpx<T> v[3][SP::NV];
@@ -182,14 +182,17 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   constexpr int hx = N1 * N2, RPW = 64 / N1, S2 = SP::S2;
   const int nx = a.nx, RS = rows_lds_stride(nx);  // LDS per row (dynamic)
   extern __shared__ unsigned char smem_raw[];
-  cpx<T>* Es = reinterpret_cast<cpx<T>*>(smem_raw);
+  // dynamic LDS starts 16-byte aligned and rows are whole complex slots: with
+  // the alignment stated, complex LDS accesses are single 8-byte operations
+  // (not pairs of 4-byte ones)
+  cpx<T>* Es = static_cast<cpx<T>*>(__builtin_assume_aligned(smem_raw, 16));
   __shared__ double red[64];
   const int lane = threadIdx.x, row = lane / N1, q = lane - row * N1;
   int bx, by, bz;
   xcd_block(bx, by, bz);
   const int r = bz, z = by, y = bx * RPW + row;
   const bool live = y < a.ny;
-  cpx<T>* E = Es + row * RS;
+  cpx<T>* E = static_cast<cpx<T>*>(__builtin_assume_aligned(Es + row * RS, 8));
   T* Hs = reinterpret_cast<T*>(E);  // real view [c][x], x < nx
   const size_t rb = (size_t)r * 3 * a.N;
   const unsigned N = (unsigned)a.N;
@@ -197,22 +200,18 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   // spectrum row of component c: S[(((r 3 + c) nz + z) Sy + y) Kx + kx]
   cpx<T>* Srow = a.S + (((size_t)r * 3 * a.nz + z) * a.Sy + (live ? y : 0)) * Kx;
   const size_t cstride = (size_t)a.nz * a.Sy * Kx;
-  __shared__ cpx<T> twl[hx], wpl[hx + 1];  // transform and split tables
-  for (int i = lane; i <= hx; i += 64) {
-    if (i < hx) twl[i] = a.tw[i];
-    wpl[i] = a.wpost[i];
+  // transform and split tables staged in LDS: their loads go out first and
+  // the spectrum loads of the up-front case (step 1) right after them, so the
+  // two global latencies overlap
+  __shared__ cpx<T> twl[hx], wpl[hx + 1];
+  constexpr int TWL = (hx + 1 + 63) / 64;
+  cpx<T> twv[TWL], wpv[TWL];
+#pragma unroll
+  for (int j = 0; j < TWL; ++j) {
+    const int i = lane + 64 * j;
+    if (i < hx) twv[j] = a.tw[i];
+    if (i <= hx) wpv[j] = a.wpost[i];
   }
-  __syncthreads();
-  const cpx<T>* tw = twl;  // exp(-2 pi i k / hx), k < hx
-  // 1. inverse x transform of the demag spectrum: inputs Z[k] at k = q + N1 s
-  //    + N2 b (complex-to-real combination of S[k] and S[hx - k]).  Each
-  //    spectrum row is read once, in coalesced order (columns q + N1 i, lane
-  //    0 also hx; all loads issued up front), and staged in LDS, where each
-  //    lane picks its pairs
-  //    Rows of up to 64 points load all three components up front; longer
-  //    rows (N2 >= 12) load one component at a time, which keeps their
-  //    register count down (16 x 16: 195 -> 170 VGPRs; measured faster there
-  //    and slower on the 8 x 8 rows)
   constexpr bool kUpFront = N2 < 12;
   cpx<T> sv[kUpFront ? 3 : 1][N2], slast[kUpFront ? 3 : 1];
   if constexpr (kUpFront) {
@@ -224,6 +223,23 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
       slast[c] = (live && q == 0) ? Srow[c * cstride + hx] : cpx<T>{0, 0};
     }
   }
+#pragma unroll
+  for (int j = 0; j < TWL; ++j) {
+    const int i = lane + 64 * j;
+    if (i < hx) twl[i] = twv[j];
+    if (i <= hx) wpl[i] = wpv[j];
+  }
+  wave_sync();
+  const cpx<T>* tw = twl;  // exp(-2 pi i k / hx), k < hx
+  // 1. inverse x transform of the demag spectrum: inputs Z[k] at k = q + N1 s
+  //    + N2 b (complex-to-real combination of S[k] and S[hx - k]).  Each
+  //    spectrum row is read once, in coalesced order (columns q + N1 i, lane
+  //    0 also hx; all loads issued up front), and staged in LDS, where each
+  //    lane picks its pairs
+  //    Rows of up to 64 points load all three components up front; longer
+  //    rows (N2 >= 12) load one component at a time, which keeps their
+  //    register count down (16 x 16: 195 -> 170 VGPRs; measured faster there
+  //    and slower on the 8 x 8 rows); the up-front loads are issued above
   cpx<T> v[3][SP::NV];
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
@@ -240,7 +256,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
       for (int i = 0; i < N2; ++i) E[q + N1 * i] = sv[0][i];
       if (q == 0) E[hx] = slast[0];
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int s = 0; s < S2; ++s)
 #pragma unroll
@@ -258,7 +274,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
         const cpx<T> O = cmulc(D, wpl[k]);  // D * conj(W^k)
         v[c][s * N1 + b] = live ? cpx<T>{Ev.re - O.im, Ev.im + O.re} : cpx<T>{0, 0};
       }
-    __syncthreads();
+    wave_sync();
     line_transform<T, N1, N2, true>(v[c], E, q, tw);
   }
   // lane q holds z[q + N1 d] = H_demag at cells x = 2 (q + N1 d) + {0, 1};
@@ -273,7 +289,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
         Hs[c * nx + x + 1] = v[c][d].im;
       }
     }
-  __syncthreads();
+  wave_sync();
   const T dt = (T)a.dth;
   T sigma = 0;
   if ((a.terms & T_THERMAL) && a.Trep) {
@@ -332,7 +348,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) Hs[c * nx + x] = mn_out[c];
   }
-  __syncthreads();
+  wave_sync();
   // the row's new state goes out from LDS in 16-byte pieces (the N1 lanes of
   // a row write 16 N1 consecutive bytes per instruction), or cell by cell
   // when the state of this replica group is not 16-byte aligned
@@ -365,7 +381,7 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
                                ? cpx<T>{Hs[c * nx + 2 * k], Hs[c * nx + 2 * k + 1]}
                                : cpx<T>{0, 0};
       }
-  __syncthreads();
+  wave_sync();
 #pragma unroll
   for (int c = 0; c < 3; ++c) line_transform<T, N1, N2, false>(v[c], E, q, tw);
   // 3. the half spectrum of the new state
@@ -373,10 +389,10 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   if (MODE == FM_HEUN2) {
     // per-workgroup sum of m_z (fixed order) for the switching detector
     red[lane] = acc;
-    __syncthreads();
+    wave_sync();
     for (int s = 32; s > 0; s >>= 1) {
       if (lane < s) red[lane] += red[lane + s];
-      __syncthreads();
+      wave_sync();
     }
     if (lane == 0) {
       const size_t blk = (size_t)by * gridDim.x + bx;

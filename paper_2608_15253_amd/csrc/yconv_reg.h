@@ -63,11 +63,6 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
     return *reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(S) + i * (unsigned)sizeof(cpx<T>));
   };
   cpx<T>* Ew = E + wc * N1 * STR;
-  // twiddle table exp(-2 pi i k / n) staged in LDS (broadcast reads)
-  __shared__ cpx<T> twl[n];
-  for (int i = lane; i < n; i += 64) twl[i] = a.tw[i];
-  __syncthreads();
-  const cpx<T>* tw = twl;
   cpx<T> X[3][N2];
   // forward, step 1 per component (the next component's loads are issued
   // before the transpose of the current one): N1-point transforms over b for
@@ -82,7 +77,21 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
                       ? at(off0 + (unsigned)c * plane + (unsigned)(N1 * s + N2 * b) * (unsigned)Kx)
                       : cpx<T>{0, 0};
   };
+  // twiddle table exp(-2 pi i k / n) staged in LDS (broadcast reads); its
+  // loads go out first and the first component's right after them, so the
+  // two global latencies overlap
+  __shared__ cpx<T> twl[n];
+  constexpr int TWL = (n + 63) / 64;
+  cpx<T> twv[TWL];
+#pragma unroll
+  for (int j = 0; j < TWL; ++j)
+    if (lane + 64 * j < n) twv[j] = a.tw[lane + 64 * j];
   load(0);
+#pragma unroll
+  for (int j = 0; j < TWL; ++j)
+    if (lane + 64 * j < n) twl[lane + 64 * j] = twv[j];
+  wave_sync();
+  const cpx<T>* tw = twl;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
 #pragma unroll
@@ -94,14 +103,40 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
       for (int cc = 1; cc < N1; ++cc) Ew[cc * STR + av] = cmul(v[s][cc], tw[(av * cc) & (n - 1)]);
     }
     if (c < 2) load(c + 1);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int av = 0; av < N2; ++av) X[c][av] = Ew[q * STR + av];
-    __syncthreads();
+    wave_sync();
+  }
+  // The transpose buffer is free now: the tile's tensor entries (xx, yy, zz,
+  // xy of rows ty <= n/2 for its NC columns, [ty][column]) are copied into it
+  // straight from global memory (LDS DMA, no registers) while the step-2
+  // transforms run.  Fetched one row per lane as the product needs them, the
+  // N2 dependent loads took a sixth of the kernel's time.
+  constexpr int TROWS = n / 2 + 1, TENT = NC * TROWS;
+  static_assert(TENT * sizeof(float4) <= sizeof(E), "tensor tile fits the transpose buffer");
+  float4* Tl = reinterpret_cast<float4*>(E);
+  {
+    const int kx0 = tile * NC;
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the transpose reads of E are done
+#pragma unroll
+    for (int j = 0; j < (TENT + 63) / 64; ++j) {
+      const int e = 64 * j + lane;
+      if (e < TENT) {
+        const int ty = e / NC, col = e - ty * NC;
+        const int kc = min(kx0 + col, Kx - 1);  // columns past Kx: any valid entry, unused
+        const T* src = a.Nt + ((size_t)ty * Kx + kc) * kTensorStride;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(Tl + 64 * j),
+                                         16, 0, 0);
+      }
+    }
   }
   // forward, step 2: N2-point transforms over a -> rows ky = q + N1 d
 #pragma unroll
   for (int c = 0; c < 3; ++c) dft_reg<T, false, N2>(X[c]);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the tensor entries are in LDS
+  wave_sync();
   if (live) {
 #pragma unroll
     for (int d = 0; d < N2; ++d) {
@@ -109,10 +144,12 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
       const bool lo = 2 * ky <= n;
       const int ty = lo ? ky : n - ky;
       const T sy = lo ? T(1) : T(-1);
-      tensor_apply(a.Nt, (size_t)ty * Kx + kx, sy, T(1), sy, false, X[0][d], X[1][d],
-                   X[2][d]);
+      const float4 e4 = Tl[ty * NC + wc];
+      const T ev[4] = {e4.x, e4.y, e4.z, e4.w};
+      tensor_apply(ev, 0, sy, T(1), sy, false, X[0][d], X[1][d], X[2][d]);
     }
   }
+  wave_sync();  // the inverse transposes overwrite E
   // inverse per component: N2-point transforms over d, conjugate twiddles,
   // transpose back, N1-point transforms over c for a = q + N1 s, store
 #pragma unroll
@@ -121,7 +158,7 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
     Ew[q * STR] = X[c][0];
 #pragma unroll
     for (int av = 1; av < N2; ++av) Ew[q * STR + av] = cmulc(X[c][av], tw[(av * q) & (n - 1)]);
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int s = 0; s < S2; ++s) {
       const int av = q + N1 * s;
@@ -135,7 +172,7 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
           at(off0 + (unsigned)c * plane + (unsigned)(N1 * s + N2 * b) * (unsigned)Kx) = u[b];
       }
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
