@@ -647,14 +647,23 @@ struct FArgs {
   T sttp[3], stt_P, stt_L2, stt_e2;
 };
 
-template <typename T>
-// Offsets within one replica are 32-bit (3 N < 2^32): with the replica's base
-// pointer uniform across the workgroup the loads take the scalar-base plus
-// 32-bit vector-offset form instead of 64-bit address arithmetic per lane.
+// The three components of a cell of one replica (component stride N).  With
+// O32 the byte offsets are formed in 32 bits (the caller guarantees
+// 3 N sizeof(T) < 2^32): with the replica's base pointer uniform across the
+// workgroup the loads then take the scalar-base plus 32-bit vector-offset
+// form instead of 64-bit address arithmetic per lane.
+template <typename T, bool O32 = false>
 __device__ inline void ld3(const T* __restrict__ mr, unsigned N, unsigned cell, T v[3]) {
-  v[0] = mr[cell];
-  v[1] = mr[N + cell];
-  v[2] = mr[2 * N + cell];
+  if constexpr (O32) {
+    const char* b = reinterpret_cast<const char*>(mr);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      v[c] = *reinterpret_cast<const T*>(b + ((unsigned)c * N + cell) * (unsigned)sizeof(T));
+  } else {
+    v[0] = mr[cell];
+    v[1] = mr[N + cell];
+    v[2] = mr[2 * N + cell];
+  }
 }
 
 // Exchange (six-point Laplacian), interfacial DMI (central differences), both
@@ -684,7 +693,7 @@ __device__ inline void cubic_terms(const FArgs<T>& a, const T mc[3], T Hc[3], T&
 // magnetisation mc; neighbours read from m.  EXT adds bulk DMI (into Hdm),
 // cubic anisotropy (into Han) and RKKY (into Hex); kernels that never see
 // those terms instantiate it without.
-template <typename T, bool EXT = true>
+template <typename T, bool EXT = true, bool O32 = false>
 __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, unsigned cell,
                                    int x, int y, int z, const T mc[3], T kbc, T Hex[3],
                                    T Hdm[3], T Han[3], T Hz[3]) {
@@ -732,11 +741,11 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, 
     }
     // neighbour cells (jm, jp); a ghost keeps the cell's own index
     unsigned jm = cell, jp = cell;
-    if (coord[ax] > 0) { jm = cell - stride[ax]; ld3(mr, N, jm, mm); }
-    else if (a.pbc[ax]) { jm = cell + (unsigned)(n - 1) * stride[ax]; ld3(mr, N, jm, mm); }
+    if (coord[ax] > 0) { jm = cell - stride[ax]; ld3<T, O32>(mr, N, jm, mm); }
+    else if (a.pbc[ax]) { jm = cell + (unsigned)(n - 1) * stride[ax]; ld3<T, O32>(mr, N, jm, mm); }
     else { for (int c = 0; c < 3; ++c) mm[c] = mc[c] - gv[c]; }
-    if (coord[ax] < n - 1) { jp = cell + stride[ax]; ld3(mr, N, jp, mp); }
-    else if (a.pbc[ax]) { jp = cell - (unsigned)(n - 1) * stride[ax]; ld3(mr, N, jp, mp); }
+    if (coord[ax] < n - 1) { jp = cell + stride[ax]; ld3<T, O32>(mr, N, jp, mp); }
+    else if (a.pbc[ax]) { jp = cell - (unsigned)(n - 1) * stride[ax]; ld3<T, O32>(mr, N, jp, mp); }
     else { for (int c = 0; c < 3; ++c) mp[c] = mc[c] + gv[c]; }
     if (a.terms & T_EXCH) {
       if (EXT && Ac) {
@@ -795,7 +804,7 @@ __device__ inline void local_terms(const FArgs<T>& a, const T* __restrict__ mr, 
   if (EXT && (a.terms & T_RKKY) && (z == a.rkz0 || z == a.rkz1)) {
     const int zp = (z == a.rkz0) ? a.rkz1 : a.rkz0;
     T mo[3];
-    ld3(mr, N, (unsigned)((int)cell + (zp - z) * (int)stride[2]), mo);
+    ld3<T, O32>(mr, N, (unsigned)((int)cell + (zp - z) * (int)stride[2]), mo);
 #pragma unroll
     for (int c = 0; c < 3; ++c) Hex[c] += a.crkky * mo[c];
   }

@@ -815,6 +815,8 @@ bool launch_rows_reg(mmx_ctx* ctx, Group& G, FArgs<T>& a, int mode) {
     // the register row kernels take neither the further field terms nor the
     // bulk-DMI edge ghosts
     if ((a.terms & (T_DMI_BULK | T_CUBIC | T_RKKY)) || a.kbb != 0 || a.Acell) return false;
+    // cell offsets within a replica are formed in 32 bits
+    if ((unsigned long long)3 * G.N * sizeof(float) >= (1ull << 32)) return false;
     hipStream_t s = ctx->stream;
     // variants: [stage][rotation][spin-transfer]
     using RowKernel = void (*)(FArgs<float>);

@@ -200,6 +200,12 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
   // spectrum row of component c: S[(((r 3 + c) nz + z) Sy + y) Kx + kx]
   cpx<T>* Srow = a.S + (((size_t)r * 3 * a.nz + z) * a.Sy + (live ? y : 0)) * Kx;
   const size_t cstride = (size_t)a.nz * a.Sy * Kx;
+  // spectrum row loads are unconditional, so that no branch splits the batch
+  // and the waits for it count exactly: a row past the last reads row 0, and
+  // what it computes from it is never stored (every store of the kernel is
+  // guarded by `live`, and lanes exchange data only within their row)
+  auto sload = [&](int c, int i) { return Srow[c * cstride + q + N1 * i]; };
+  auto slast_load = [&](int c) { return Srow[c * cstride + hx]; };
   // transform and split tables staged in LDS: their loads go out first and
   // the spectrum loads of the up-front case (step 1) right after them, so the
   // two global latencies overlap
@@ -219,8 +225,8 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
     for (int c = 0; c < 3; ++c) {
 #pragma unroll
       for (int i = 0; i < N2; ++i)
-        sv[c][i] = live ? Srow[c * cstride + q + N1 * i] : cpx<T>{0, 0};
-      slast[c] = (live && q == 0) ? Srow[c * cstride + hx] : cpx<T>{0, 0};
+        sv[c][i] = sload(c, i);
+      slast[c] = slast_load(c);
     }
   }
 #pragma unroll
@@ -250,8 +256,8 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
     } else {
 #pragma unroll
       for (int i = 0; i < N2; ++i)
-        sv[0][i] = live ? Srow[c * cstride + q + N1 * i] : cpx<T>{0, 0};
-      slast[0] = (live && q == 0) ? Srow[c * cstride + hx] : cpx<T>{0, 0};
+        sv[0][i] = sload(c, i);
+      slast[0] = slast_load(c);
 #pragma unroll
       for (int i = 0; i < N2; ++i) E[q + N1 * i] = sv[0][i];
       if (q == 0) E[hx] = slast[0];
@@ -310,9 +316,9 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
     if (live) {
       const unsigned cell = (unsigned)x + (unsigned)nx * (unsigned)(y + a.ny * z);
       T mc[3];
-      ld3(mr, N, cell, mc);
+      ld3<T, true>(mr, N, cell, mc);
       T Hex[3], Hdm[3], Han[3], Hz[3];
-      local_terms<T, false>(a, mr, cell, x, y, z, mc, a.kbc, Hex, Hdm, Han, Hz);
+      local_terms<T, false, true>(a, mr, cell, x, y, z, mc, a.kbc, Hex, Hdm, Han, Hz);
       T H[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) H[c] = Hex[c] + Hdm[c] + Han[c] + Hz[c] + Hs[c * nx + x];
@@ -336,8 +342,8 @@ __global__ void __launch_bounds__(64) k_rows_reg(FArgs<T> a) {
         }
       } else {
         T mo[3], k1v[3];
-        ld3(a.m0 + rb, N, cell, mo);
-        if (ROT) ld3(k1_r, N, cell, k1v);
+        ld3<T, true>(a.m0 + rb, N, cell, mo);
+        if (ROT) ld3<T, true>(k1_r, N, cell, k1v);
         else k1v[0] = k1v[1] = k1v[2] = T(0);
         heun_correct(a, ROT, mc, H, kv, tau, mo, k1v, dt, mn_out);
         acc += mz_checked(mn_out);

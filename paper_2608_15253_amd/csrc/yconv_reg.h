@@ -64,18 +64,29 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
   };
   cpx<T>* Ew = E + wc * N1 * STR;
   cpx<T> X[3][N2];
-  // forward, step 1 per component (the next component's loads are issued
-  // before the transpose of the current one): N1-point transforms over b for
-  // a = q + N1 s, twiddles, transpose so that lane q gathers Y[a][q], all a
-  cpx<T> v[S2][N1];
-  auto load = [&](int c) {
+  // forward, step 1 per component: N1-point transforms over b for a = q +
+  // N1 s, twiddles, transpose so that lane q gathers Y[a][q], all a.  The
+  // columns of component c + 1 are loaded into the second register set
+  // before component c is transformed, and a scheduling barrier after each
+  // transpose keeps the compiler from pulling the next transform (and with
+  // it the wait for those loads) ahead of it.
+  cpx<T> va[S2][N1], vb[S2][N1];
+  // loads are unconditional (a lane past the last column reads the last
+  // column and drops the value), so that no branch splits a batch of loads
+  // and the waits for them can count exactly
+  const unsigned offl = live ? off0 : (unsigned)q * (unsigned)Kx + (unsigned)(Kx - 1);
+  auto load = [&](cpx<T> (&v)[S2][N1], int c) {
 #pragma unroll
     for (int s = 0; s < S2; ++s)
 #pragma unroll
-      for (int b = 0; b < N1; ++b)
-        v[s][b] = (b < NB && live)
-                      ? at(off0 + (unsigned)c * plane + (unsigned)(N1 * s + N2 * b) * (unsigned)Kx)
-                      : cpx<T>{0, 0};
+      for (int b = 0; b < N1; ++b) {
+        if (b < NB) {
+          const cpx<T> x = at(offl + (unsigned)c * plane + (unsigned)(N1 * s + N2 * b) * (unsigned)Kx);
+          v[s][b] = live ? x : cpx<T>{0, 0};
+        } else {
+          v[s][b] = cpx<T>{0, 0};
+        }
+      }
   };
   // twiddle table exp(-2 pi i k / n) staged in LDS (broadcast reads); its
   // loads go out first and the first component's right after them, so the
@@ -86,7 +97,7 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
 #pragma unroll
   for (int j = 0; j < TWL; ++j)
     if (lane + 64 * j < n) twv[j] = a.tw[lane + 64 * j];
-  load(0);
+  load(va, 0);
 #pragma unroll
   for (int j = 0; j < TWL; ++j)
     if (lane + 64 * j < n) twl[lane + 64 * j] = twv[j];
@@ -94,6 +105,8 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
   const cpx<T>* tw = twl;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    cpx<T>(&v)[S2][N1] = (c & 1) ? vb : va;
+    if (c < 2) load((c & 1) ? va : vb, c + 1);
 #pragma unroll
     for (int s = 0; s < S2; ++s) {
       const int av = q + N1 * s;
@@ -102,11 +115,11 @@ __global__ void __launch_bounds__(64) k_yconv_reg(YArgs<T> a) {
 #pragma unroll
       for (int cc = 1; cc < N1; ++cc) Ew[cc * STR + av] = cmul(v[s][cc], tw[(av * cc) & (n - 1)]);
     }
-    if (c < 2) load(c + 1);
     wave_sync();
 #pragma unroll
     for (int av = 0; av < N2; ++av) X[c][av] = Ew[q * STR + av];
     wave_sync();
+    __builtin_amdgcn_sched_barrier(0);
   }
   // The transpose buffer is free now: the tile's tensor entries (xx, yy, zz,
   // xy of rows ty <= n/2 for its NC columns, [ty][column]) are copied into it
