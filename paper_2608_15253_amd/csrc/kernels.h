@@ -163,6 +163,22 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
     const int l = udiv(t, kw), k = t - l * kw, y = y0 + l;
     cpx<T> v[3] = {{0, 0}, {0, 0}, {0, 0}};
     if (y < a.ny && k < npair) {
+      // both cells' state and slope values are loaded before the sums (a
+      // cell past the row end loads its partner and is dropped)
+      T pm[2][3], pkv[2][6][3];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int x = (2 * k + h < a.nx) ? 2 * k + h : 2 * k;
+        const size_t cell = (size_t)x + (size_t)a.nx * (y + (size_t)a.ny * z);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pm[h][c] = a.m[rb + (size_t)c * a.N + cell];
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+          if (j < a.ncoef) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) pkv[h][j][c] = a.kk[j][rb + (size_t)c * a.N + cell];
+          }
+      }
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int x = 2 * k + h;
@@ -171,9 +187,10 @@ __global__ void __launch_bounds__(kBlock) k_xfwd(XArgs<T> a) {
         T mv[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          T s = a.m[rb + (size_t)c * a.N + cell];
-          for (int j = 0; j < a.ncoef; ++j)
-            s += dt * a.coef[j] * a.kk[j][rb + (size_t)c * a.N + cell];
+          T s = pm[h][c];
+#pragma unroll
+          for (int j = 0; j < 6; ++j)
+            if (j < a.ncoef) s += dt * a.coef[j] * pkv[h][j][c];
           mv[c] = s;
         }
         if (a.normalise) {
@@ -1099,6 +1116,26 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
     const int l = udiv(t, a.nx), x = t - l * a.nx, y = y0 + l;
     if (y >= a.ny) continue;
     const unsigned cell = (unsigned)x + (unsigned)a.nx * (unsigned)(y + a.ny * z);
+    // the epilogue's own inputs (the step's base state and the earlier
+    // slopes) are loaded before the field is computed, so their latencies
+    // overlap it instead of following it one load at a time
+    constexpr bool kPre = (MODE == FM_RKK || MODE == FM_RK7 || MODE == FM_HEUN2);
+    T pm0[kPre ? 3 : 1], pk[kPre ? 6 : 1][3];
+    if constexpr (MODE == FM_RKK) {
+      if (fwd) {
+        ld3(a.m0 + rb, N, cell, pm0);
+#pragma unroll
+        for (int j = 0; j < 6; ++j)
+          if (a.cn[j] != T(0) && j != a.cstage) ld3(a.kk[j] + rb, N, cell, pk[j]);
+      }
+    } else if constexpr (MODE == FM_RK7) {
+#pragma unroll
+      for (int j = 0; j < 6; ++j)
+        if (a.e[j] != 0.0) ld3(a.kk[j] + rb, N, cell, pk[j]);
+    } else if constexpr (MODE == FM_HEUN2) {
+      ld3(a.m0 + rb, N, cell, pm0);
+      if (a.rot) ld3(k1_r, N, cell, pk[0]);
+    }
     T mc[3];
     ld3(mr, N, cell, mc);
     T Hex[3], Hdm[3], Han[3], Hz[3];
@@ -1165,10 +1202,11 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
         T mv[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          T sv = a.m0[rb + c * N + cell];
+          T sv = pm0[c];
+#pragma unroll
           for (int j = 0; j < 6; ++j) {
             if (a.cn[j] == T(0)) continue;
-            const T kj = (j == a.cstage) ? k[c] : a.kk[j][rb + c * N + cell];
+            const T kj = (j == a.cstage) ? k[c] : pk[j][c];
             sv += dt * a.cn[j] * kj;
           }
           mv[c] = sv;
@@ -1195,12 +1233,11 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
         if (fwd) F[(c * L + l) * 2 * hx + x] = a.msr ? ws * mn[c] : mn[c];
       }
     } else if (MODE == FM_HEUN2) {
-      T mo[3], k1v[3];
-      ld3(a.m0 + rb, N, cell, mo);
-      if (a.rot) ld3(k1_r, N, cell, k1v);
-      else k1v[0] = k1v[1] = k1v[2] = T(0);
+      T k1v[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) k1v[c] = a.rot ? pk[0][c] : T(0);
       T mn[3];
-      heun_correct(gpm, alpha, a.rot != 0, mc, H, k, tau, mo, k1v, dt, mn);
+      heun_correct(gpm, alpha, a.rot != 0, mc, H, k, tau, pm0, k1v, dt, mn);
       const T ws = a.msr ? a.msr[cell] : T(1);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
@@ -1215,8 +1252,9 @@ __global__ void __launch_bounds__(kBlock) k_fields(FArgs<T> a) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         double s = a.e[6] * (double)k[c];
+#pragma unroll
         for (int j = 0; j < 6; ++j)
-          if (a.e[j] != 0.0) s += a.e[j] * (double)a.kk[j][rb + c * N + cell];
+          if (a.e[j] != 0.0) s += a.e[j] * (double)pk[j][c];
         s *= dt_state;
         d2 += s * s;
       }
