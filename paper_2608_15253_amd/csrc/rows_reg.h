@@ -47,8 +47,8 @@ struct RowSplit {
 
 // One N1 x N2 transform of a line held by N1 lanes: in, v[s N1 + b] =
 // x[q + N1 s + N2 b] (s < S2 with q + N1 s < N2, b < N1); out, v[d] =
-// X[q + N1 d] (d < N2).  E: N1 (N2 + 1) LDS slots of this line (workgroup
-// barriers).
+// X[q + N1 d] (d < N2).  E: N1 (N2 + 1) LDS slots of this line (one-wave
+// workgroup, wavefront-scope synchronisation).
 template <typename T, int N1, int N2, bool INV, int NV>
 __device__ inline void line_transform(cpx<T> (&v)[NV], cpx<T>* E, int q,
                                       const cpx<T>* __restrict__ tw) {
@@ -77,8 +77,8 @@ __device__ inline void line_transform(cpx<T> (&v)[NV], cpx<T>* E, int q,
 // Real-to-complex split S[kx] = E + conj(W^kx) O of a row whose half-length
 // transform X sits in the lanes as v[c][d] = X[q + N1 d]: lane q stores
 // kx = q + N1 d and (lane 0) kx = hx; the partner X[hx - kx] comes through
-// LDS, one component at a time (hx slots of E).  Followed by no barrier: E
-// is reused only after the next one.
+// LDS, one component at a time (hx slots of E).  Followed by no
+// synchronisation: E is reused only after the next one.
 template <typename T, int N1, int N2, int NV>
 __device__ inline void rows_store_spectrum(const cpx<T> (&v)[3][NV], cpx<T>* E, int q, bool live,
                                            cpx<T>* __restrict__ Srow, size_t cstride,
