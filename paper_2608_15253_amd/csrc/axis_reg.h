@@ -46,18 +46,39 @@ __global__ void __launch_bounds__(64) k_ypass_reg(YArgs<T> a) {
     return *reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(P) +
                                       (row * Kx + (unsigned)kx) * (unsigned)sizeof(cpx<T>));
   };
-  for (int i = lane; i < n; i += 64) twl[i] = a.tw[i];
-  wave_sync();
-  const cpx<T>* tw = twl;
+  // loads are unconditional (a lane past the last column reads the last
+  // column; what it computes is never stored), so that no branch splits a
+  // batch of loads; the twiddle table's loads go out first, the line's right
+  // after them, and the table is written to LDS once both are in flight
+  const unsigned kxl = live ? (unsigned)kx : Kx - 1;
+  auto atl = [&](unsigned row) -> cpx<T> {
+    return *reinterpret_cast<const cpx<T>*>(reinterpret_cast<const char*>(P) +
+                                            (row * Kx + kxl) * (unsigned)sizeof(cpx<T>));
+  };
+  constexpr int TWL = (n + 63) / 64;
+  cpx<T> twv[TWL];
+#pragma unroll
+  for (int j = 0; j < TWL; ++j)
+    if (lane + 64 * j < n) twv[j] = a.tw[lane + 64 * j];
   cpx<T>* Ew = E + wc * N1 * STR;
   cpx<T> X[N2];
+  cpx<T> v[INV ? 1 : S2][N1];
   if constexpr (!INV) {
-    cpx<T> v[S2][N1];
 #pragma unroll
     for (int s = 0; s < S2; ++s)
 #pragma unroll
       for (int b = 0; b < N1; ++b)
-        v[s][b] = (b < NB && live) ? at((unsigned)(q + N1 * s + N2 * b)) : cpx<T>{0, 0};
+        v[s][b] = (b < NB) ? atl((unsigned)(q + N1 * s + N2 * b)) : cpx<T>{0, 0};
+  } else {
+#pragma unroll
+    for (int d = 0; d < N2; ++d) X[d] = atl((unsigned)(q + N1 * d));
+  }
+#pragma unroll
+  for (int j = 0; j < TWL; ++j)
+    if (lane + 64 * j < n) twl[lane + 64 * j] = twv[j];
+  wave_sync();
+  const cpx<T>* tw = twl;
+  if constexpr (!INV) {
 #pragma unroll
     for (int s = 0; s < S2; ++s) {
       const int av = q + N1 * s;
@@ -75,8 +96,6 @@ __global__ void __launch_bounds__(64) k_ypass_reg(YArgs<T> a) {
       for (int d = 0; d < N2; ++d) at((unsigned)(q + N1 * d)) = X[d];
     }
   } else {
-#pragma unroll
-    for (int d = 0; d < N2; ++d) X[d] = live ? at((unsigned)(q + N1 * d)) : cpx<T>{0, 0};
     dft_reg<T, true, N2>(X);
     Ew[q * STR] = X[0];
 #pragma unroll
@@ -120,23 +139,44 @@ __global__ void __launch_bounds__(64) k_zline_reg(YArgs<T> a) {
     const unsigned i = ((unsigned)c * nz + z) * plane + (unsigned)ky * Kx + (unsigned)kx;
     return *reinterpret_cast<cpx<T>*>(reinterpret_cast<char*>(P) + i * (unsigned)sizeof(cpx<T>));
   };
-  // the z pass arguments carry the z twiddles exp(-2 pi i k / Pz) in tw
-  for (int i = lane; i < n; i += 64) twl[i] = a.tw[i];
-  wave_sync();
-  const cpx<T>* tw = twl;
+  // loads are unconditional (a lane past the last column reads the last
+  // column; what it computes is never stored), so that no branch splits a
+  // batch; component c + 1 is loaded into the second register set before
+  // component c is transformed, and a scheduling barrier after each
+  // transpose keeps the next transform (and its wait) behind it.  The z
+  // pass arguments carry the z twiddles exp(-2 pi i k / Pz) in tw; their
+  // loads go out first.
+  const unsigned kxl = live ? (unsigned)kx : Kx - 1;
+  auto atl = [&](int c, unsigned z) -> cpx<T> {
+    const unsigned i = ((unsigned)c * nz + z) * plane + (unsigned)ky * Kx + kxl;
+    return *reinterpret_cast<const cpx<T>*>(reinterpret_cast<const char*>(P) +
+                                            i * (unsigned)sizeof(cpx<T>));
+  };
+  constexpr int TWL = (n + 63) / 64;
+  cpx<T> twv[TWL];
+#pragma unroll
+  for (int j = 0; j < TWL; ++j)
+    if (lane + 64 * j < n) twv[j] = a.tw[lane + 64 * j];
   cpx<T>* Ew = E + wc * N1 * STR;
   cpx<T> X[3][N2];
-  cpx<T> v[S2][N1];
-  auto load = [&](int c) {
+  cpx<T> va[S2][N1], vb[S2][N1];
+  auto load = [&](cpx<T> (&v)[S2][N1], int c) {
 #pragma unroll
     for (int s = 0; s < S2; ++s)
 #pragma unroll
       for (int b = 0; b < N1; ++b)
-        v[s][b] = (b < NB && live) ? at(c, (unsigned)(q + N1 * s + N2 * b)) : cpx<T>{0, 0};
+        v[s][b] = (b < NB) ? atl(c, (unsigned)(q + N1 * s + N2 * b)) : cpx<T>{0, 0};
   };
-  load(0);
+  load(va, 0);
+#pragma unroll
+  for (int j = 0; j < TWL; ++j)
+    if (lane + 64 * j < n) twl[lane + 64 * j] = twv[j];
+  wave_sync();
+  const cpx<T>* tw = twl;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
+    cpx<T>(&v)[S2][N1] = (c & 1) ? vb : va;
+    if (c < 2) load((c & 1) ? va : vb, c + 1);
 #pragma unroll
     for (int s = 0; s < S2; ++s) {
       const int av = q + N1 * s;
@@ -145,11 +185,11 @@ __global__ void __launch_bounds__(64) k_zline_reg(YArgs<T> a) {
 #pragma unroll
       for (int cc = 1; cc < N1; ++cc) Ew[cc * STR + av] = cmul(v[s][cc], tw[av * cc]);
     }
-    if (c < 2) load(c + 1);
     wave_sync();
 #pragma unroll
     for (int av = 0; av < N2; ++av) X[c][av] = Ew[q * STR + av];
     wave_sync();
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) dft_reg<T, false, N2>(X[c]);
