@@ -124,7 +124,12 @@ __global__ void __launch_bounds__(64) k_zline_reg(YArgs<T> a) {
   static_assert(N2 % N1 == 0 && 64 % N1 == 0, "line split");
   constexpr int n = N1 * N2, NC = 64 / N1, S2 = N2 / N1, STR = N2 + 1;
   constexpr int NB = PRUNE ? N1 / 2 : N1;
-  __shared__ cpx<T> E[NC * N1 * STR];
+  // the transpose buffer also takes the tile's tensor entries between the
+  // forward and the inverse transposes: NC columns x (n/2 + 1) kz rows x the
+  // 8 reals of a frequency, [tz][column] as two 16-byte halves
+  constexpr int TROWS = n / 2 + 1, TENT = NC * TROWS;
+  constexpr int ESZ = NC * N1 * STR > 4 * TENT ? NC * N1 * STR : 4 * TENT;
+  __shared__ cpx<T> E[ESZ];
   __shared__ cpx<T> twl[n];
   if (a.done && *a.done) return;
   const int lane = threadIdx.x, wc = lane / N1, q = lane - wc * N1;
@@ -191,12 +196,36 @@ __global__ void __launch_bounds__(64) k_zline_reg(YArgs<T> a) {
     wave_sync();
     __builtin_amdgcn_sched_barrier(0);
   }
+  // the tile's tensor entries go straight from global memory into the free
+  // transpose buffer (direct-to-LDS loads, no registers) while the step-2
+  // transforms run, instead of N2 dependent loads per lane
+  const bool ylo = 2 * ky <= a.Py;
+  const int ty = ylo ? ky : a.Py - ky;
+  static_assert(sizeof(T) == 4, "FP32 register passes");
+  float4* Tl = reinterpret_cast<float4*>(E);
+  {
+    const int kx0 = tile * NC;
+    __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0): the transpose reads of E are done
+#pragma unroll
+    for (int j = 0; j < (2 * TENT + 63) / 64; ++j) {
+      const int e2 = 64 * j + lane;  // half h of entry e
+      if (e2 < 2 * TENT) {
+        const int e = e2 >> 1, h = e2 & 1;
+        const int tz = e / NC, col = e - tz * NC;
+        const int kc = min(kx0 + col, (int)Kx - 1);  // columns past Kx: any valid entry, unused
+        const T* src = a.Nt + (((size_t)tz * a.Ty + ty) * Kx + kc) * kTensorStride + 4 * h;
+        __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                         (__attribute__((address_space(3))) void*)(Tl + 64 * j),
+                                         16, 0, 0);
+      }
+    }
+  }
 #pragma unroll
   for (int c = 0; c < 3; ++c) dft_reg<T, false, N2>(X[c]);
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): the tensor entries are in LDS
+  wave_sync();
   if (live) {
     // lane q holds kz = q + N1 d of all three components: the product is local
-    const bool ylo = 2 * ky <= a.Py;
-    const int ty = ylo ? ky : a.Py - ky;
     const T sy = ylo ? T(1) : T(-1);
 #pragma unroll
     for (int d = 0; d < N2; ++d) {
@@ -204,10 +233,12 @@ __global__ void __launch_bounds__(64) k_zline_reg(YArgs<T> a) {
       const bool zlo = 2 * kz <= n;
       const int tz = zlo ? kz : n - kz;
       const T sz = zlo ? T(1) : T(-1);
-      tensor_apply(a.Nt, ((size_t)tz * a.Ty + ty) * Kx + kx, sy, sz, sy * sz, true, X[0][d],
-                   X[1][d], X[2][d]);
+      const float4 e0 = Tl[2 * (tz * NC + wc)], e1 = Tl[2 * (tz * NC + wc) + 1];
+      const T ev[6] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y};
+      tensor_apply(ev, 0, sy, sz, sy * sz, true, X[0][d], X[1][d], X[2][d]);
     }
   }
+  wave_sync();  // the inverse transposes overwrite E
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     dft_reg<T, true, N2>(X[c]);
